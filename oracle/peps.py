@@ -1,0 +1,335 @@
+"""O3: PEPS evolution and exact overlap contraction on the CPU, in FP64.
+
+Evolution (main text, "Quantum Circuit Simulator Based on PEPS"):
+  * the state is a product of rank-5 site tensors A_n[sigma, l, r, u, d]
+    (eq. 1), initialised to |0> with all bonds of size 1;
+  * a one-qubit gate contracts the physical index (eq. 3);
+  * a two-qubit gate O on a nearest-neighbour pair is factorised by SVD as
+    sum_s U_s (x) V_s with the singular values absorbed (eq. 4; here split
+    as sqrt(S) on both sides, which leaves the product unchanged), and the
+    new index s is bundled with the shared bond on both sites (eqs. 5-6).
+    The paper writes r' = (r, s) and l' = (s, l); any consistent pair is
+    correct, and we use (old, new) on both sides: new = old * chi_o + s.
+Overlap: E_n = A_n[tau_n] (eq. 7), and <tau|psi> is the contraction of the
+network of E_n.
+
+Contractions work on labelled tensors: every leg carries the identity of its
+bond, ('h', r, c) for the bond between (r, c) and (r, c+1) and ('v', r, c)
+for the bond between (r, c) and (r+1, c).  Contracting two labelled tensors
+sums over the labels they share (a plain numpy tensordot), so a contraction
+order is just an order of sites:
+  * row scheme (supplement S-II, eqs. S2-S6): absorb sites row by row, left
+    to right; after row i the running tensor is F_i with the down legs of
+    row i open; the last step leaves the scalar amplitude;
+  * square partition for even L x L lattices (eqs. S9-S10): contract each
+    quadrant, then the upper pair, the lower pair, and the two results;
+  * loop slicing (the "cut" technique named in the conclusions): fixing a
+    bond to one value and summing the sliced results over that value.
+"""
+from __future__ import annotations
+
+from typing import Dict, Iterable, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import gates as G
+
+Label = Tuple[str, int, int]
+
+
+# --------------------------------------------------------------------------
+# evolution, eqs. (3)-(6)
+# --------------------------------------------------------------------------
+
+class PEPS:
+    def __init__(self, lv: int, lh: int):
+        self.lv, self.lh = lv, lh
+        self.A: List[np.ndarray] = []
+        for _ in range(lv * lh):
+            a = np.zeros((2, 1, 1, 1, 1), dtype=np.complex128)
+            a[0, 0, 0, 0, 0] = 1.0
+            self.A.append(a)
+
+    def pos(self, q: int) -> Tuple[int, int]:
+        return divmod(q, self.lh)
+
+    def chi(self) -> int:
+        """Bond dimension, eq. (2): the largest auxiliary dimension."""
+        return max(max(a.shape[1:]) for a in self.A)
+
+
+def svd_split(o: np.ndarray, tol: float = 1e-12):
+    """Eq. (4): O[(tn tm), (sn sm)] = sum_s U[tn, sn, s] V[s, tm, sm]."""
+    o4 = o.reshape(2, 2, 2, 2)                     # [tn, tm, sn, sm]
+    m = o4.transpose(0, 2, 1, 3).reshape(4, 4)     # rows (tn sn), cols (tm sm)
+    u, s, vh = np.linalg.svd(m)
+    k = int(np.sum(s > tol * s[0]))
+    root = np.sqrt(s[:k])
+    un = (u[:, :k] * root[None, :]).reshape(2, 2, k)
+    vm = (root[:, None] * vh[:k, :]).reshape(k, 2, 2)
+    return un, vm
+
+
+def apply_1q(peps: PEPS, u: np.ndarray, q: int) -> None:
+    peps.A[q] = np.einsum("ts,slrud->tlrud", u, peps.A[q])
+
+
+def apply_2q(peps: PEPS, o: np.ndarray, q0: int, q1: int) -> None:
+    (r0, c0), (r1, c1) = peps.pos(q0), peps.pos(q1)
+    if (r0, c0 + 1) == (r1, c1) or (r0 + 1, c0) == (r1, c1):
+        n, m, op = q0, q1, o
+    elif (r1, c1 + 1) == (r0, c0) or (r1 + 1, c1) == (r0, c0):
+        # put the left/upper qubit first: swap both the output and input pairs
+        n, m = q1, q0
+        op = o.reshape(2, 2, 2, 2).transpose(1, 0, 3, 2).reshape(4, 4)
+    else:
+        raise ValueError(f"two-qubit gate on non-neighbouring qubits {q0}, {q1}")
+    un, vm = svd_split(op)
+    k = un.shape[2]
+    a, b = peps.A[n], peps.A[m]
+    _, l, r, u, d = a.shape
+    _, l2, r2, u2, d2 = b.shape
+    if peps.pos(m)[0] == peps.pos(n)[0]:  # horizontal: n.r <-> m.l
+        na = np.einsum("tsk,slrud->tlrkud", un, a).reshape(2, l, r * k, u, d)
+        nb = np.einsum("kts,slrud->tlkrud", vm, b).reshape(2, l2 * k, r2, u2, d2)
+    else:                                   # vertical: n.d <-> m.u
+        na = np.einsum("tsk,slrud->tlrudk", un, a).reshape(2, l, r, u, d * k)
+        nb = np.einsum("kts,slrud->tlrukd", vm, b).reshape(2, l2, r2, u2 * k, d2)
+    peps.A[n], peps.A[m] = na, nb
+
+
+def build(circuit) -> PEPS:
+    """Absorb every gate of the circuit, in order, into the site tensors."""
+    peps = PEPS(circuit.lv, circuit.lh)
+    for g in circuit.gates:
+        mat = G.matrix_of(g)
+        if G.is_two_qubit(g):
+            apply_2q(peps, mat, g.q0, g.q1)
+        else:
+            apply_1q(peps, mat, g.q0)
+    return peps
+
+
+def bond_dims(peps: PEPS) -> Dict[Label, int]:
+    out = {}
+    for q, a in enumerate(peps.A):
+        r, c = peps.pos(q)
+        if c + 1 < peps.lh:
+            out[("h", r, c)] = a.shape[2]
+        if r + 1 < peps.lv:
+            out[("v", r, c)] = a.shape[4]
+    return out
+
+
+# --------------------------------------------------------------------------
+# labelled tensors
+# --------------------------------------------------------------------------
+
+class LT:
+    """A tensor with one bond label per axis."""
+
+    __slots__ = ("a", "labels")
+
+    def __init__(self, a: np.ndarray, labels: Sequence[Label]):
+        assert a.ndim == len(labels)
+        self.a, self.labels = a, list(labels)
+
+    def dim(self, label: Label) -> int:
+        return self.a.shape[self.labels.index(label)]
+
+    def ordered(self, labels: Sequence[Label]) -> np.ndarray:
+        return np.transpose(self.a, [self.labels.index(x) for x in labels])
+
+
+def contract(x: LT, y: LT) -> LT:
+    """Sum over every label the two tensors share."""
+    shared = [l for l in x.labels if l in y.labels]
+    ax = [x.labels.index(l) for l in shared]
+    ay = [y.labels.index(l) for l in shared]
+    out = np.tensordot(x.a, y.a, axes=(ax, ay))
+    labels = [l for l in x.labels if l not in shared] + [l for l in y.labels if l not in shared]
+    return LT(out, labels)
+
+
+def fix(t: LT, label: Label, value: int) -> LT:
+    """Slice one bond at a fixed value (one term of a cut loop)."""
+    if label not in t.labels:
+        return t
+    i = t.labels.index(label)
+    return LT(np.take(t.a, value, axis=i), t.labels[:i] + t.labels[i + 1:])
+
+
+def projected_sites(peps: PEPS, bits: Sequence[int]) -> Dict[Tuple[int, int], LT]:
+    """E_n = A_n[tau_n] as labelled rank-<=4 tensors (eq. 7)."""
+    out = {}
+    for q, a in enumerate(peps.A):
+        r, c = peps.pos(q)
+        e = a[int(bits[q])]
+        legs = [("h", r, c - 1), ("h", r, c), ("v", r - 1, c), ("v", r, c)]
+        inside = [c > 0, c + 1 < peps.lh, r > 0, r + 1 < peps.lv]
+        keep_axes, labels = [], []
+        for ax, (lab, ok) in enumerate(zip(legs, inside)):
+            if ok:
+                keep_axes.append(ax)
+                labels.append(lab)
+            elif e.shape[ax] != 1:
+                raise ValueError("boundary leg with dimension > 1")
+        e = e.reshape([e.shape[ax] for ax in keep_axes])
+        out[(r, c)] = LT(e, labels)
+    return out
+
+
+def contract_sites(sites: Dict[Tuple[int, int], LT], order: Iterable[Tuple[int, int]],
+                   start: Optional[LT] = None, fixed: Optional[Dict[Label, int]] = None) -> LT:
+    """Absorb sites one at a time in the given order; `fixed` slices bonds."""
+    fixed = fixed or {}
+    acc = start
+    if acc is not None:
+        for lab, v in fixed.items():
+            acc = fix(acc, lab, v)
+    for p in order:
+        t = sites[p]
+        for lab, v in fixed.items():
+            t = fix(t, lab, v)
+        acc = t if acc is None else contract(acc, t)
+    return acc
+
+
+# --------------------------------------------------------------------------
+# contraction orders
+# --------------------------------------------------------------------------
+
+def site_order(lv: int, lh: int, scheme: str) -> List[Tuple[int, int]]:
+    """Site orders of the generic scheme (Fig. S2(a)) and its mirror images."""
+    if scheme == "rows":        # top-down, left to right (eqs. S2-S6)
+        return [(r, c) for r in range(lv) for c in range(lh)]
+    if scheme == "rows_rl":     # top-down, right to left
+        return [(r, c) for r in range(lv) for c in reversed(range(lh))]
+    if scheme == "rows_bu":     # bottom-up, left to right
+        return [(r, c) for r in reversed(range(lv)) for c in range(lh)]
+    if scheme == "cols":        # left to right by columns (used when Lh > Lv)
+        return [(r, c) for c in range(lh) for r in range(lv)]
+    raise ValueError(scheme)
+
+
+def amplitude(peps: PEPS, bits: Sequence[int], scheme: str = "rows") -> complex:
+    """<tau|psi> by absorbing sites in the order of `scheme`."""
+    sites = projected_sites(peps, bits)
+    if scheme == "quadrants":
+        return amplitude_quadrants(peps, bits)
+    res = contract_sites(sites, site_order(peps.lv, peps.lh, scheme))
+    assert res.a.ndim == 0
+    return complex(res.a)
+
+
+def amplitudes(peps: PEPS, bits: np.ndarray, scheme: str = "rows") -> np.ndarray:
+    return np.array([amplitude(peps, b, scheme) for b in np.asarray(bits)], dtype=np.complex128)
+
+
+def boundary_after_rows(peps: PEPS, bits: Sequence[int], n_rows: int) -> LT:
+    """F_{n_rows}: the first n_rows rows contracted, down legs of the last open (S2-S5)."""
+    sites = projected_sites(peps, bits)
+    return contract_sites(sites, [(r, c) for r in range(n_rows) for c in range(peps.lh)])
+
+
+def row_transfer(F: LT, sites: Dict[Tuple[int, int], LT], row: int, lh: int,
+                 fixed: Optional[Dict[Label, int]] = None) -> LT:
+    """One row of the generic scheme: G_1 (S3), G_j (S4), F_row = G_Lh (S5)."""
+    return contract_sites(sites, [(row, c) for c in range(lh)], start=F, fixed=fixed)
+
+
+# --------------------------------------------------------------------------
+# square partition, eqs. (S9)-(S10)
+# --------------------------------------------------------------------------
+
+def quadrant_sites(L: int, which: str) -> List[Tuple[int, int]]:
+    m = L // 2
+    rows = range(0, m) if which[0] == "u" else range(m, L)
+    cols = range(0, m) if which[1] == "l" else range(m, L)
+    return [(r, c) for r in rows for c in cols]
+
+
+def amplitude_quadrants(peps: PEPS, bits: Sequence[int]) -> complex:
+    """Even square lattice: four m x m quadrants, then (ul.ur).(bl.br)."""
+    L = peps.lv
+    if peps.lh != L or L % 2:
+        raise ValueError("the quadrant partition needs an even square lattice")
+    sites = projected_sites(peps, bits)
+    q = {w: contract_sites(sites, quadrant_sites(L, w)) for w in ("ul", "ur", "bl", "br")}
+    top = contract(q["ul"], q["ur"])
+    bottom = contract(q["bl"], q["br"])
+    res = contract(top, bottom)
+    assert res.a.ndim == 0
+    return complex(res.a)
+
+
+def quadrant_amplitudes_sliced(peps: PEPS, base_bits: Sequence[int], left_patterns: np.ndarray,
+                               right_patterns: np.ndarray, log=None) -> np.ndarray:
+    """Square-partition amplitudes of many bitstrings with bounded memory.
+
+    The bitstrings differ only in the bottom-left quadrant (rows of
+    `left_patterns`, full bitstrings) and the bottom-right quadrant
+    (`right_patterns`); result[i, j] is the amplitude of the bitstring that
+    takes its bottom-left bits from left_patterns[i], its bottom-right bits
+    from right_patterns[j] and all other bits from base_bits.
+
+    With e, a, b, c the bond groups ul|ur, ul|bl, ur|br, bl|br:
+        amp = sum ul[e,a] ur[e,b] bl[a,c] br[b,c]
+            = sum_{b,c} X[b,c] br[b,c],  X = T^T bl,  T^T[b,a] = sum_e ur[e,b] ul[e,a].
+    Each quadrant is produced one slice at a time over one of its open bonds
+    (a cut loop), so only T^T, one X and one quadrant are ever held whole.
+    """
+    L = peps.lv
+    m = L // 2
+    if peps.lh != L or L % 2:
+        raise ValueError("needs an even square lattice")
+    e_lab = [("h", r, m - 1) for r in range(m)]
+    a_lab = [("v", m - 1, c) for c in range(m)]
+    b_lab = [("v", m - 1, c) for c in range(m, L)]
+    c_lab = [("h", r, m - 1) for r in range(m, L)]
+    dims = bond_dims(peps)
+    de = int(np.prod([dims[x] for x in e_lab]))
+    da = int(np.prod([dims[x] for x in a_lab]))
+    db = int(np.prod([dims[x] for x in b_lab]))
+    dc = int(np.prod([dims[x] for x in c_lab]))
+    say = log or (lambda *_: None)
+
+    base_sites = projected_sites(peps, base_bits)
+
+    # T^T[b, a] = sum over slices x of e_0: ur_x[e', b]^T ul_x[e', a]
+    tt = np.zeros((db, da), dtype=np.complex128)
+    e0 = e_lab[0]
+    for x in range(dims[e0]):
+        ul = contract_sites(base_sites, quadrant_sites(L, "ul"), fixed={e0: x})
+        ur = contract_sites(base_sites, quadrant_sites(L, "ur"), fixed={e0: x})
+        ulm = ul.ordered(e_lab[1:] + a_lab).reshape(de // dims[e0], da)
+        urm = ur.ordered(e_lab[1:] + b_lab).reshape(de // dims[e0], db)
+        _accumulate_matmul(tt, urm.T, ulm)
+        say(f"T slice {x + 1}/{dims[e0]}")
+
+    out = np.zeros((len(left_patterns), len(right_patterns)), dtype=np.complex128)
+    a0, b0 = a_lab[0], b_lab[0]
+    for i, lp in enumerate(left_patterns):
+        lsites = projected_sites(peps, lp)
+        bl = np.empty((da, dc), dtype=np.complex128)
+        step = da // dims[a0]
+        for y in range(dims[a0]):
+            t = contract_sites(lsites, quadrant_sites(L, "bl"), fixed={a0: y})
+            bl[y * step:(y + 1) * step] = t.ordered(a_lab[1:] + c_lab).reshape(step, dc)
+        rsites = [projected_sites(peps, rp) for rp in right_patterns]
+        stepb = db // dims[b0]
+        for z in range(dims[b0]):
+            xz = tt[z * stepb:(z + 1) * stepb] @ bl          # X[b0 = z, b', c]
+            for j, rs in enumerate(rsites):
+                br = contract_sites(rs, quadrant_sites(L, "br"), fixed={b0: z})
+                brm = br.ordered(b_lab[1:] + c_lab).reshape(stepb, dc)
+                out[i, j] += np.sum(xz * brm)
+            say(f"pattern {i + 1}/{len(left_patterns)} slice {z + 1}/{dims[b0]}")
+        del bl
+    return out
+
+
+def _accumulate_matmul(c: np.ndarray, a: np.ndarray, b: np.ndarray, rows: int = 4096) -> None:
+    """c += a @ b, a block of rows at a time to bound the temporary."""
+    for s in range(0, c.shape[0], rows):
+        c[s:s + rows] += a[s:s + rows] @ b

@@ -1,0 +1,91 @@
+"""Write the golden amplitudes the GPU parity tests compare against.
+
+Every value here comes from the CPU oracle (package `oracle`) on inputs from
+the seeded generator `rqcgen`; nothing is read from the GPU library.
+
+  python tests/golden/make_golden.py            # 3x3, 4x5, 5x5 (minutes)
+  python tests/golden/make_golden.py --big      # also 6x6 d40 (about an hour, ~34 GiB RAM)
+
+Files: rqc_<lv>x<lh>_d<d>_s<seed>.json with the circuit hash, the bitstrings
+and the FP64 amplitudes.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import rqcgen  # noqa: E402
+from oracle import peps, statevector as sv, stats  # noqa: E402
+
+
+def _write(name, circuit, bits, amps, method, extra=None):
+    d = {
+        "lv": circuit.lv, "lh": circuit.lh, "depth": circuit.depth, "seed": circuit.seed,
+        "sha256": circuit.sha256(), "method": method,
+        "bits": np.asarray(bits, dtype=int).tolist(),
+        "amps_re": [float(a.real) for a in amps], "amps_im": [float(a.imag) for a in amps],
+    }
+    if extra:
+        d.update(extra)
+    with open(os.path.join(HERE, name), "w") as f:
+        json.dump(d, f)
+    print("wrote", name, flush=True)
+
+
+def small():
+    c = rqcgen.generate(3, 3, 8, 0)
+    bits = rqcgen.all_bitstrings(9)
+    _write("rqc_3x3_d8_s0.json", c, bits, sv.amplitudes(sv.run(c), bits), "statevector")
+
+    for seed in range(8):
+        c = rqcgen.generate(4, 5, 24, seed)
+        bits = rqcgen.bitstrings(4, 5, seed, 64)
+        _write(f"rqc_4x5_d24_s{seed}.json", c, bits, sv.amplitudes(sv.run(c), bits), "statevector")
+
+    c = rqcgen.generate(5, 5, 32, 0)
+    t = time.time()
+    psi = sv.run(c)
+    bits = rqcgen.bitstrings(5, 5, 0, 256)
+    amps = sv.amplitudes(psi, bits)
+    pt = stats.porter_thomas_summary(stats.scaled_probabilities(psi.reshape(-1), 25))
+    print("5x5 state vector", time.time() - t, pt, flush=True)
+    del psi
+    # cross-check a few with the PEPS row scheme (an independent computation)
+    P = peps.build(c)
+    chk = peps.amplitudes(P, bits[:4])
+    assert np.max(np.abs(chk - amps[:4])) < 1e-12 * np.max(np.abs(amps))
+    _write("rqc_5x5_d32_s0.json", c, bits, amps, "statevector", {"porter_thomas_full": pt})
+
+
+def big():
+    c = rqcgen.generate(6, 6, 40, 0)
+    base = rqcgen.bitstrings(6, 6, 0, 1)[0]
+    cols = [2, 3, 4, 5]
+    var = rqcgen.last_row_variants(base, 6, 6, cols)     # variant i: cols bits = bits of i
+    left = var[[0, 8]]                                    # column 2 = 0 / 1 (bottom-left quadrant)
+    right = var[list(range(8))]                           # columns 3..5 = 000..111 (bottom-right)
+    t = time.time()
+    P = peps.build(c)
+    res = peps.quadrant_amplitudes_sliced(P, base, left, right,
+                                          log=lambda s: print(f"[{time.time() - t:7.0f}s] {s}", flush=True))
+    amps = res.reshape(-1)                                # i * 8 + j == variant index
+    _write("rqc_6x6_d40_s0.json", c, var, amps, "peps-square-partition-sliced",
+           {"base_index": int(next(i for i in range(16) if np.array_equal(var[i], base))),
+            "variant_cols": cols, "seconds": time.time() - t})
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--big", action="store_true")
+    ap.add_argument("--only-big", action="store_true")
+    a = ap.parse_args()
+    if not a.only_big:
+        small()
+    if a.big or a.only_big:
+        big()
