@@ -1,0 +1,164 @@
+/*
+ * psim — exact single amplitudes of 2D quantum circuits by PEPS contraction,
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * Method (Guo et al., "General-purpose quantum circuit simulator with
+ * Projected Entangled-Pair States and the quantum supremacy frontier"):
+ *   - the state of an Lv x Lh qubit lattice is a PEPS of rank-5 site tensors
+ *     A_n[sigma][l][r][u][d] (eq. 1);
+ *   - one-qubit gates contract the physical index (eq. 3); a nearest-neighbour
+ *     two-qubit gate is split into a sum of chi_o products (eq. 4) and each
+ *     factor is absorbed into one site, the new index being bundled with the
+ *     shared bond (eqs. 5-6);
+ *   - the amplitude <tau|psi> is the contraction of the projected tensors
+ *     E_n = A_n[tau_n] (eq. 7), done exactly row by row (supplement S-II,
+ *     eqs. S2-S6, Fig. S2(a)), along the short side of the lattice.
+ *
+ * Conventions shared by every entry point
+ *   - qubit n sits at row r = n / lh, column c = n % lh (row 0 on top);
+ *   - a bitstring is lv*lh bytes, byte n = tau_n in {0, 1};
+ *   - two-qubit matrices act on (q0, q1) with row index 2*tau_q0 + tau_q1;
+ *   - matrices are row-major complex as interleaved (re, im) doubles;
+ *   - every function returns a psim_status; on failure nothing is written to
+ *     the outputs and psim_last_error() describes the cause.  Handles are
+ *     opaque, owned by the caller and freed with the matching *_free call
+ *     (which accepts NULL).  Input arrays are borrowed for the duration of
+ *     the call only.
+ *   - functions that take a device (HIP) stream enqueue on it and return
+ *     after synchronising that stream.
+ */
+#ifndef PSIM_PUBLIC_H_
+#define PSIM_PUBLIC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PSIM_OK = 0,
+  PSIM_EINVAL = -1,        /* bad argument: qubit out of range, non-neighbouring 2q gate, bit not 0/1, NULL */
+  PSIM_ENOMEM = -2,        /* plan exceeds the memory budget (message states the bytes needed) or allocation failed */
+  PSIM_EDEVICE = -3,       /* HIP runtime error (message carries the HIP error string) */
+  PSIM_EUNSUPPORTED = -4,  /* valid request this build does not implement */
+  PSIM_EINTERNAL = -5
+} psim_status;
+
+/* Gate kinds.  The random circuits use H, T, SQRT_X, SQRT_Y and CZ
+ * (supplement S-I); U1 / U2 are arbitrary 2x2 / 4x4 matrices given in m. */
+typedef enum {
+  PSIM_H = 0, PSIM_T = 1, PSIM_SQRT_X = 2, PSIM_SQRT_Y = 3, PSIM_CZ = 4, PSIM_U1 = 5, PSIM_U2 = 6
+} psim_gate_kind;
+
+typedef struct {
+  int32_t kind;     /* psim_gate_kind */
+  int32_t cycle;    /* non-decreasing along the gate list; informational otherwise */
+  int32_t q0, q1;   /* q1 = -1 for one-qubit gates */
+  const double *m;  /* U1: 8 doubles, U2: 32 doubles (row-major complex); NULL for named gates */
+} psim_gate;
+
+typedef enum {
+  PSIM_FP64 = 0,     /* complex128 storage, FP64 MFMA */
+  PSIM_FP32_4M = 1,  /* complex64 storage, complex product as one real FP32 MFMA GEMM (4 real mults) */
+  PSIM_FP32_3M = 2,  /* complex64 storage, three real FP32 MFMA GEMMs (Gauss) */
+  PSIM_BF16X3 = 3    /* complex64 storage, BF16 hi/lo split, 3 BF16 MFMA products, FP32 accumulation */
+} psim_precision;
+
+typedef enum {
+  PSIM_PLAN_HOST_ONLY = 1  /* plan the contraction on the host only (no device, cannot run) */
+} psim_plan_flags;
+
+typedef struct {
+  int32_t prec;               /* psim_precision */
+  int32_t flags;              /* psim_plan_flags */
+  uint64_t mem_budget_bytes;  /* device bytes the workspace may use; 0 = 200 GiB */
+  int32_t max_batch;          /* most bitstrings per psim_amplitudes call; 0 = 1 */
+  int32_t sweep;              /* 0 = along the short side (Fig. S2(a)), 1 = rows, 2 = columns */
+  int32_t device;             /* HIP device ordinal */
+  int32_t reserved;
+} psim_plan_opts;
+
+typedef struct {
+  uint64_t workspace_bytes;   /* device workspace psim_amplitudes needs for max_batch bitstrings */
+  uint64_t weights_bytes;     /* device memory the plan itself holds (packed site matrices) */
+  uint64_t peak_tensor_elems; /* largest tensor held at once for one bitstring (all v-slices) */
+  double cmac_per_amplitude;  /* exact complex multiply-adds of the row scheme, one bitstring */
+  int64_t n_gemm_steps;       /* site contractions per bitstring */
+  int32_t L;                  /* boundary width (legs of the row boundary F) */
+  int32_t R;                  /* number of rows swept */
+  int32_t chi;                /* bond dimension, eq. (2) */
+  int32_t v_chunk;            /* v-slices processed together in interior rows */
+  int32_t sweep;              /* 1 = rows, 2 = columns */
+  int32_t prec;
+} psim_plan_stats;
+
+typedef struct psim_peps_s psim_peps_t;
+typedef struct psim_plan_s psim_plan_t;
+
+/* PEPS evolution (eqs. 3-6) on the host in FP64.  Gates are applied in array
+ * order to |0...0>.  CZ uses its exact rank-2 split sum_s |s><s| (x) Z^s;
+ * U2 is split by SVD with the singular values shared between the factors.
+ * Errors: EINVAL for bad sizes, qubits, kinds, or a 2q gate whose qubits are
+ * not lattice neighbours. */
+psim_status psim_build(int32_t lv, int32_t lh, const psim_gate *gates, size_t n_gates, psim_peps_t **out);
+
+/* Lattice and bond sizes of a built PEPS.  bond_dims (nullable) receives
+ * lv*(lh-1) horizontal bonds (row-major, bond (r,c)-(r,c+1)) followed by
+ * (lv-1)*lh vertical bonds (bond (r,c)-(r+1,c)), i.e. n_bonds entries. */
+psim_status psim_peps_info(const psim_peps_t *peps, int32_t *lv, int32_t *lh, int32_t *chi,
+                           int64_t *bond_dims, size_t n_bonds);
+
+void psim_peps_free(psim_peps_t *peps);
+
+/* Plan the exact contraction (supplement S-II, Fig. S2(a)): sweep axis, leg
+ * orders, v-slicing of the boundary for the memory budget, exact work count.
+ * Unless PSIM_PLAN_HOST_ONLY is set, projects both values of every site
+ * (E = A[tau], eq. 7), packs them for the chosen precision and uploads them to
+ * the device; the peps may be freed afterwards.
+ * Errors: ENOMEM with the bytes needed; EUNSUPPORTED for a precision this
+ * build lacks; EDEVICE on HIP failures. */
+psim_status psim_plan(const psim_peps_t *peps, const psim_plan_opts *opts, psim_plan_t **out);
+
+psim_status psim_plan_info(const psim_plan_t *plan, psim_plan_stats *out);
+
+void psim_plan_free(psim_plan_t *plan);
+
+/* Amplitudes <tau|psi> (eq. 7) of n_bitstrings bitstrings (bits: host,
+ * n_bitstrings * lv*lh bytes).  d_workspace is device memory of at least
+ * psim_plan_stats.workspace_bytes bytes, owned by the caller; hip_stream is a
+ * hipStream_t (NULL = default stream).  Bitstrings that share leading rows
+ * share those rows' work.  Results go to out_amp (host, 2*n doubles: re, im)
+ * in FP64 as mantissa * 2^exponent assembled on the host.  If more than
+ * max_batch bitstrings are passed they are processed max_batch at a time.
+ * Errors: EINVAL for bits outside {0,1} or a short workspace, EDEVICE. */
+psim_status psim_amplitudes(psim_plan_t *plan, const uint8_t *bits, size_t n_bitstrings,
+                            void *d_workspace, size_t workspace_bytes, void *hip_stream,
+                            double *out_amp);
+
+/* One site contraction of the row scheme, eq. (S4), on device buffers:
+ *   C[z][m][n] = sum_{k1,k2} A[z][k1][m][k2] * W[k1*K2 + k2][n]     (complex)
+ * A: device, complex (complex128 for PSIM_FP64, complex64 otherwise), batch
+ *    stride a_batch_stride elements, element (k1, m, k2) at k1*M*K2 + m*K2 + k2.
+ * W: host, K1*K2 x N complex128, row-major (packed and uploaded per call).
+ * C: device, same element type as A, batch stride M*N; transpose_out = 1
+ *    stores C[z][n][m] instead.  batch = number of z.
+ * Runs the same kernels the amplitude path uses; allocates its own scratch.
+ * Errors: EINVAL for non-positive sizes or NULL, EUNSUPPORTED, EDEVICE. */
+psim_status psim_contract_site(int32_t prec, int64_t batch, int64_t M, int64_t K1, int64_t K2, int64_t N,
+                               const void *d_A, int64_t a_batch_stride, const double *W,
+                               void *d_C, int32_t transpose_out, void *hip_stream);
+
+/* Message for the last failing call on this thread; valid until the next
+ * psim_* call on the same thread.  Never NULL. */
+const char *psim_last_error(void);
+
+/* Library version string. */
+const char *psim_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSIM_PUBLIC_H_ */

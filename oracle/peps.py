@@ -243,9 +243,16 @@ def row_transfer(F: LT, sites: Dict[Tuple[int, int], LT], row: int, lh: int,
 # --------------------------------------------------------------------------
 
 def quadrant_sites(L: int, which: str) -> List[Tuple[int, int]]:
+    """Sites of one m x m quadrant (m = L/2), in the order they are absorbed.
+
+    Each quadrant is swept from its outer corner toward the centre of the
+    lattice (upper quadrants top-down, lower ones bottom-up; left quadrants
+    left to right, right ones right to left), so that the bonds it leaves open
+    toward its neighbours are created late and intermediates stay small.
+    """
     m = L // 2
-    rows = range(0, m) if which[0] == "u" else range(m, L)
-    cols = range(0, m) if which[1] == "l" else range(m, L)
+    rows = list(range(0, m)) if which[0] == "u" else list(reversed(range(m, L)))
+    cols = list(range(0, m)) if which[1] == "l" else list(reversed(range(m, L)))
     return [(r, c) for r in rows for c in cols]
 
 
@@ -275,9 +282,10 @@ def quadrant_amplitudes_sliced(peps: PEPS, base_bits: Sequence[int], left_patter
 
     With e, a, b, c the bond groups ul|ur, ul|bl, ur|br, bl|br:
         amp = sum ul[e,a] ur[e,b] bl[a,c] br[b,c]
-            = sum_{b,c} X[b,c] br[b,c],  X = T^T bl,  T^T[b,a] = sum_e ur[e,b] ul[e,a].
-    Each quadrant is produced one slice at a time over one of its open bonds
-    (a cut loop), so only T^T, one X and one quadrant are ever held whole.
+            = sum_z sum_{b,c'} X_z[b,c'] br_z[b,c'],   X_z = T^T bl_z,
+        T^T[b,a] = sum_x ur_x[e',b]^T ul_x[e',a],
+    where x runs over the top bond of group e and z over the bottom bond of
+    group c (cut loops).  Only T^T and slices of the other tensors are held.
     """
     L = peps.lv
     m = L // 2
@@ -305,27 +313,27 @@ def quadrant_amplitudes_sliced(peps: PEPS, base_bits: Sequence[int], left_patter
         ulm = ul.ordered(e_lab[1:] + a_lab).reshape(de // dims[e0], da)
         urm = ur.ordered(e_lab[1:] + b_lab).reshape(de // dims[e0], db)
         _accumulate_matmul(tt, urm.T, ulm)
+        del ul, ur, ulm, urm
         say(f"T slice {x + 1}/{dims[e0]}")
 
     out = np.zeros((len(left_patterns), len(right_patterns)), dtype=np.complex128)
-    a0, b0 = a_lab[0], b_lab[0]
-    for i, lp in enumerate(left_patterns):
-        lsites = projected_sites(peps, lp)
-        bl = np.empty((da, dc), dtype=np.complex128)
-        step = da // dims[a0]
-        for y in range(dims[a0]):
-            t = contract_sites(lsites, quadrant_sites(L, "bl"), fixed={a0: y})
-            bl[y * step:(y + 1) * step] = t.ordered(a_lab[1:] + c_lab).reshape(step, dc)
-        rsites = [projected_sites(peps, rp) for rp in right_patterns]
-        stepb = db // dims[b0]
-        for z in range(dims[b0]):
-            xz = tt[z * stepb:(z + 1) * stepb] @ bl          # X[b0 = z, b', c]
-            for j, rs in enumerate(rsites):
-                br = contract_sites(rs, quadrant_sites(L, "br"), fixed={b0: z})
-                brm = br.ordered(b_lab[1:] + c_lab).reshape(stepb, dc)
+    zl = c_lab[-1]
+    lsites = [projected_sites(peps, lp) for lp in left_patterns]
+    rsites = [projected_sites(peps, rp) for rp in right_patterns]
+    for z in range(dims[zl]):
+        brs = []
+        for rs in rsites:
+            br = contract_sites(rs, quadrant_sites(L, "br"), fixed={zl: z})
+            brs.append(br.ordered(b_lab + c_lab[:-1]).reshape(db, dc // dims[zl]))
+        for i, ls in enumerate(lsites):
+            bl = contract_sites(ls, quadrant_sites(L, "bl"), fixed={zl: z})
+            blm = bl.ordered(a_lab + c_lab[:-1]).reshape(da, dc // dims[zl])
+            xz = tt @ blm                                   # X[b, c'] at c_last = z
+            for j, brm in enumerate(brs):
                 out[i, j] += np.sum(xz * brm)
-            say(f"pattern {i + 1}/{len(left_patterns)} slice {z + 1}/{dims[b0]}")
-        del bl
+            del bl, blm, xz
+        del brs
+        say(f"bottom slice {z + 1}/{dims[zl]}")
     return out
 
 

@@ -1,0 +1,221 @@
+"""psim: exact PEPS amplitudes of 2D random circuits on one MI355X.
+
+Thin ctypes binding over libpsim.so (include/psim.h).  Every step of the
+contraction runs in the library's HIP kernels; this module only marshals
+arguments.  PyTorch supplies device memory (the workspace) and the current
+HIP stream.  There is no CPU fallback: if the library is missing the import
+of any entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "_lib", "libpsim.so")
+
+PSIM_OK, PSIM_EINVAL, PSIM_ENOMEM, PSIM_EDEVICE, PSIM_EUNSUPPORTED, PSIM_EINTERNAL = 0, -1, -2, -3, -4, -5
+KIND = {"H": 0, "T": 1, "SX": 2, "SY": 3, "CZ": 4, "U1": 5, "U2": 6}
+PREC = {"fp64": 0, "fp32": 1, "fp32_4m": 1, "fp32_3m": 2, "bf16x3": 3}
+PLAN_HOST_ONLY = 1
+EXPORTED = ("psim_build", "psim_peps_info", "psim_peps_free", "psim_plan", "psim_plan_info", "psim_plan_free",
+            "psim_amplitudes", "psim_contract_site", "psim_last_error", "psim_version")
+
+
+class PsimError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"psim status {status}: {msg}")
+        self.status = status
+
+
+class _Gate(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("cycle", ctypes.c_int32), ("q0", ctypes.c_int32),
+                ("q1", ctypes.c_int32), ("m", ctypes.POINTER(ctypes.c_double))]
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("flags", ctypes.c_int32), ("mem_budget_bytes", ctypes.c_uint64),
+                ("max_batch", ctypes.c_int32), ("sweep", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class PlanStats(ctypes.Structure):
+    _fields_ = [("workspace_bytes", ctypes.c_uint64), ("weights_bytes", ctypes.c_uint64),
+                ("peak_tensor_elems", ctypes.c_uint64), ("cmac_per_amplitude", ctypes.c_double),
+                ("n_gemm_steps", ctypes.c_int64), ("L", ctypes.c_int32), ("R", ctypes.c_int32),
+                ("chi", ctypes.c_int32), ("v_chunk", ctypes.c_int32), ("sweep", ctypes.c_int32),
+                ("prec", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib(need_torch: bool = True) -> ctypes.CDLL:
+    """Load libpsim.so.  torch is imported first so that the process uses one
+    HIP runtime (torch's) for both torch allocations and the library."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if need_torch:
+        import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_1905_08394_amd.build` first")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
+    L.psim_build.argtypes = [i32, i32, ctypes.POINTER(_Gate), sz, ctypes.POINTER(vp)]
+    L.psim_peps_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                 ctypes.POINTER(i64), sz]
+    L.psim_peps_free.argtypes = [vp]
+    L.psim_peps_free.restype = None
+    L.psim_plan.argtypes = [vp, ctypes.POINTER(PlanOpts), ctypes.POINTER(vp)]
+    L.psim_plan_info.argtypes = [vp, ctypes.POINTER(PlanStats)]
+    L.psim_plan_free.argtypes = [vp]
+    L.psim_plan_free.restype = None
+    L.psim_amplitudes.argtypes = [vp, ctypes.POINTER(ctypes.c_uint8), sz, vp, sz, vp, ctypes.POINTER(ctypes.c_double)]
+    L.psim_contract_site.argtypes = [i32, i64, i64, i64, i64, i64, vp, i64, ctypes.POINTER(ctypes.c_double), vp,
+                                     i32, vp]
+    L.psim_last_error.restype = ctypes.c_char_p
+    L.psim_version.restype = ctypes.c_char_p
+    for f in ("psim_build", "psim_peps_info", "psim_plan", "psim_plan_info", "psim_amplitudes",
+              "psim_contract_site"):
+        getattr(L, f).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != PSIM_OK:
+        raise PsimError(status, lib().psim_last_error().decode())
+
+
+def _c_gates(circuit):
+    n = len(circuit.gates)
+    arr = (_Gate * max(n, 1))()
+    keep = []
+    for i, g in enumerate(circuit.gates):
+        arr[i].kind = KIND[g.kind]
+        arr[i].cycle = g.cycle
+        arr[i].q0 = g.q0
+        arr[i].q1 = g.q1
+        if g.m is not None:
+            buf = (ctypes.c_double * len(g.m))(*g.m)
+            keep.append(buf)
+            arr[i].m = ctypes.cast(buf, ctypes.POINTER(ctypes.c_double))
+    return arr, n, keep
+
+
+class Peps:
+    """PEPS of a circuit after gate absorption (psim_build)."""
+
+    def __init__(self, circuit):
+        L = lib()
+        arr, n, keep = _c_gates(circuit)
+        h = ctypes.c_void_p()
+        _check(L.psim_build(circuit.lv, circuit.lh, arr, n, ctypes.byref(h)))
+        self._h = h
+        self.lv, self.lh = circuit.lv, circuit.lh
+
+    def info(self):
+        L = lib()
+        nb = self.lv * (self.lh - 1) + (self.lv - 1) * self.lh
+        dims = (ctypes.c_int64 * max(nb, 1))()
+        lv, lh, chi = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(L.psim_peps_info(self._h, ctypes.byref(lv), ctypes.byref(lh), ctypes.byref(chi), dims, nb))
+        return {"lv": lv.value, "lh": lh.value, "chi": chi.value, "bond_dims": list(dims)[:nb]}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().psim_peps_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """Contraction plan with packed site matrices on the device (psim_plan)."""
+
+    def __init__(self, peps: Peps, prec: str = "fp32", mem_budget: int = 0, max_batch: int = 1, sweep: int = 0,
+                 device: int = 0, host_only: bool = False):
+        L = lib()
+        o = PlanOpts(PREC[prec], PLAN_HOST_ONLY if host_only else 0, mem_budget, max_batch, sweep, device, 0)
+        h = ctypes.c_void_p()
+        _check(L.psim_plan(peps._h, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.device = device
+        self.nq = peps.lv * peps.lh
+        self._ws = None
+
+    def stats(self) -> dict:
+        s = PlanStats()
+        _check(lib().psim_plan_info(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def workspace(self):
+        import torch
+        need = self.stats()["workspace_bytes"]
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = None
+            self._ws = torch.empty(need, dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+    def amplitudes(self, bits, stream=None) -> np.ndarray:
+        """<tau|psi> for each row of bits (uint8, shape (n, lv*lh))."""
+        import torch
+        b = np.ascontiguousarray(np.asarray(bits, dtype=np.uint8))
+        if b.ndim == 1:
+            b = b[None, :]
+        if b.shape[1] != self.nq:
+            raise ValueError(f"bitstrings must have {self.nq} entries")
+        out = np.zeros(2 * b.shape[0], dtype=np.float64)
+        ws = self.workspace()
+        st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        _check(lib().psim_amplitudes(self._h, b.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), b.shape[0],
+                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(st),
+                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out[0::2] + 1j * out[1::2]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().psim_plan_free(self._h)
+            self._h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def contract_site(prec: str, A, W: np.ndarray, M: int, K1: int, K2: int, N: int, batch: int = 1,
+                  a_batch_stride: Optional[int] = None, transpose_out: bool = False, stream=None):
+    """One site contraction (eq. S4) through the library kernels.
+
+    A: torch complex tensor on the GPU with batch * K1 * M * K2 elements laid out
+    A[z][k1][m][k2]; W: complex (K1*K2, N).  Returns a torch tensor C[z][m][n]
+    (or C[z][n][m] with transpose_out)."""
+    import torch
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    assert A.dtype == dt and A.is_cuda and A.is_contiguous()
+    Wd = np.ascontiguousarray(np.asarray(W, dtype=np.complex128)).view(np.float64)
+    C = torch.empty(batch * M * N, dtype=dt, device=A.device)
+    st = stream if stream is not None else torch.cuda.current_stream(A.device).cuda_stream
+    _check(lib().psim_contract_site(PREC[prec], batch, M, K1, K2, N, ctypes.c_void_p(A.data_ptr()),
+                                    a_batch_stride if a_batch_stride is not None else K1 * M * K2,
+                                    Wd.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    ctypes.c_void_p(C.data_ptr()), 1 if transpose_out else 0, ctypes.c_void_p(st)))
+    return C
+
+
+def version() -> str:
+    return lib().psim_version().decode()

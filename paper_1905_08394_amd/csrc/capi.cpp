@@ -1,0 +1,171 @@
+// C ABI of libpsim: status codes, thread-local error messages, handles.
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime_api.h>
+
+#include "psim_internal.hpp"
+
+psim_peps_t* build_peps(int32_t lv, int32_t lh, const psim_gate* gates, size_t n_gates);
+psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o);
+void free_plan(psim_plan_t* pl);
+void run_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, size_t ws_bytes, void* stream,
+                    double* out);
+
+namespace psim {
+
+static thread_local std::string g_last_error = "no error";
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+[[noreturn]] void fail(psim_status st, const std::string& msg) { throw Error{st, msg}; }
+
+}  // namespace psim
+
+using namespace psim;
+
+template <typename F>
+static psim_status guarded(F&& f) {
+  try {
+    f();
+    return PSIM_OK;
+  } catch (const Error& e) {
+    set_last_error(e.msg);
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return PSIM_ENOMEM;
+  } catch (const std::exception& e) {
+    set_last_error(std::string("internal error: ") + e.what());
+    return PSIM_EINTERNAL;
+  } catch (...) {
+    set_last_error("internal error");
+    return PSIM_EINTERNAL;
+  }
+}
+
+extern "C" {
+
+psim_status psim_build(int32_t lv, int32_t lh, const psim_gate* gates, size_t n_gates, psim_peps_t** out) {
+  return guarded([&] {
+    if (!out) fail(PSIM_EINVAL, "out is NULL");
+    *out = build_peps(lv, lh, gates, n_gates);
+  });
+}
+
+psim_status psim_peps_info(const psim_peps_t* P, int32_t* lv, int32_t* lh, int32_t* chi, int64_t* bond_dims,
+                           size_t n_bonds) {
+  return guarded([&] {
+    if (!P) fail(PSIM_EINVAL, "peps is NULL");
+    const size_t nb = (size_t)P->lv * (P->lh - 1) + (size_t)(P->lv - 1) * P->lh;
+    if (bond_dims && n_bonds < nb) fail(PSIM_EINVAL, "bond_dims needs " + std::to_string(nb) + " entries");
+    int c = 1;
+    for (const Site& s : P->sites) c = std::max({c, s.dl, s.dr, s.du, s.dd});
+    if (lv) *lv = P->lv;
+    if (lh) *lh = P->lh;
+    if (chi) *chi = c;
+    if (bond_dims) {
+      size_t x = 0;
+      for (int r = 0; r < P->lv; ++r)
+        for (int col = 0; col + 1 < P->lh; ++col) bond_dims[x++] = P->sites[r * P->lh + col].dr;
+      for (int r = 0; r + 1 < P->lv; ++r)
+        for (int col = 0; col < P->lh; ++col) bond_dims[x++] = P->sites[r * P->lh + col].dd;
+    }
+  });
+}
+
+void psim_peps_free(psim_peps_t* P) { delete P; }
+
+psim_status psim_plan(const psim_peps_t* P, const psim_plan_opts* opts, psim_plan_t** out) {
+  return guarded([&] {
+    if (!out) fail(PSIM_EINVAL, "out is NULL");
+    *out = make_plan(P, opts);
+  });
+}
+
+psim_status psim_plan_info(const psim_plan_t* pl, psim_plan_stats* s) {
+  return guarded([&] {
+    if (!pl || !s) fail(PSIM_EINVAL, "NULL argument");
+    psim_plan_stats o{};
+    o.workspace_bytes = pl->ws_total;
+    o.weights_bytes = pl->weights_bytes;
+    o.peak_tensor_elems = (uint64_t)pl->peak_elems;
+    o.cmac_per_amplitude = pl->cmac;
+    o.n_gemm_steps = (int64_t)pl->steps.size();
+    o.L = pl->L;
+    o.R = pl->R;
+    o.chi = pl->chi;
+    int vc = 0;
+    for (const auto& lev : pl->levels) vc = std::max(vc, lev.vchunk);
+    o.v_chunk = vc;
+    for (const auto& lev : pl->levels)
+      if (lev.Dv > 1) o.v_chunk = std::min(o.v_chunk, lev.vchunk);
+    o.sweep = pl->sweep;
+    o.prec = pl->opts.prec;
+    *s = o;
+  });
+}
+
+void psim_plan_free(psim_plan_t* pl) { free_plan(pl); }
+
+psim_status psim_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, size_t ws_bytes,
+                            void* stream, double* out) {
+  return guarded([&] {
+    if (!pl) fail(PSIM_EINVAL, "plan is NULL");
+    run_amplitudes(pl, bits, n, ws, ws_bytes, stream, out);
+  });
+}
+
+psim_status psim_contract_site(int32_t prec, int64_t batch, int64_t M, int64_t K1, int64_t K2, int64_t N,
+                               const void* dA, int64_t a_batch_stride, const double* W, void* dC,
+                               int32_t transpose_out, void* stream) {
+  return guarded([&] {
+    if (prec != PSIM_FP64 && prec != PSIM_FP32_4M) fail(PSIM_EUNSUPPORTED, "precision not available");
+    if (batch < 1 || M < 1 || K1 < 1 || K2 < 1 || N < 1) fail(PSIM_EINVAL, "non-positive size");
+    if (!dA || !W || !dC) fail(PSIM_EINVAL, "NULL buffer");
+    const int eb = prec == PSIM_FP64 ? 16 : 8;
+    if (((uintptr_t)dA | (uintptr_t)dC) % eb) fail(PSIM_EINVAL, "device buffers must be aligned to one complex");
+    if (batch > 1 && a_batch_stride < K1 * M * K2) fail(PSIM_EINVAL, "a_batch_stride must be at least K1*M*K2");
+    const int64_t K = K1 * K2;
+    std::vector<cd> Wc((size_t)(K * N));
+    for (int64_t x = 0; x < K * N; ++x) Wc[x] = cd(W[2 * x], W[2 * x + 1]);
+    std::vector<char> packed;
+    int64_t ld = 0;
+    pack_site_matrix(prec, Wc.data(), K, N, packed, ld);
+    void* dW = nullptr;
+    hip_check(hipMalloc(&dW, packed.size()), "hipMalloc(W)");
+    try {
+      hipStream_t st = (hipStream_t)stream;
+      hip_check(hipMemcpyAsync(dW, packed.data(), packed.size(), hipMemcpyHostToDevice, st), "upload W");
+      GemmLaunch g;
+      g.prec = prec;
+      g.A = dA;
+      g.C = dC;
+      g.W0 = dW;
+      g.ldw = ld;
+      g.M = M;
+      g.K1 = K1;
+      g.K2 = K2;
+      g.N = N;
+      g.nodes = batch;
+      g.Bz = 1;
+      g.sA_node = a_batch_stride;
+      g.sC_node = M * N;
+      g.trans_out = transpose_out ? 1 : 0;
+      launch_site_gemm(g, st);
+      hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    } catch (...) {
+      (void)hipFree(dW);
+      throw;
+    }
+    hip_check(hipFree(dW), "hipFree(W)");
+  });
+}
+
+const char* psim_last_error(void) { return g_last_error.c_str(); }
+
+const char* psim_version(void) { return "psim 0.1 (gfx950)"; }
+
+}  // extern "C"

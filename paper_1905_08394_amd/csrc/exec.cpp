@@ -1,0 +1,276 @@
+// Amplitude scheduler: runs the planned row sweep for a batch of bitstrings.
+//
+// Bitstrings that agree on their first i+1 swept rows share the boundary F_i
+// (the reuse idea of the "fast sampling" remark in S-II), so the batch is
+// organised as a trie: level i holds one node per distinct prefix of rows
+// 0..i, and each node's row is computed once from its parent's boundary.
+// Nodes of a level are processed in groups and the v leg in chunks (both
+// sized by the planner for the memory budget); every site contraction is
+// one batched GEMM launch over (node, v).  After each row the boundary of
+// every node is rescaled by an exact power of two chosen from its largest
+// component, and the exponents are carried along the trie; the amplitude is
+// mantissa * 2^(row exponents + site-matrix exponents), assembled in FP64.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <unordered_map>
+
+#include <hip/hip_runtime_api.h>
+
+#include "psim_internal.hpp"
+
+using namespace psim;
+
+namespace {
+
+struct Trie {
+  // per level: parent index of each node and the bits of its row
+  std::vector<std::vector<int32_t>> parent;
+  std::vector<std::vector<uint8_t>> tau;  // nodes x L
+  std::vector<int32_t> leaf;              // per bitstring: node at the last level
+};
+
+Trie build_trie(const psim_plan_t& pl, const uint8_t* bits, size_t n) {
+  const int R = pl.R, L = pl.L, nq = pl.lv * pl.lh;
+  Trie t;
+  t.parent.resize(R);
+  t.tau.resize(R);
+  std::vector<int32_t> cur(n, 0);  // node of each bitstring at the previous level (root = 0)
+  for (int i = 0; i < R; ++i) {
+    std::map<std::pair<int32_t, uint64_t>, int32_t> index;
+    std::vector<int32_t> next(n);
+    for (size_t b = 0; b < n; ++b) {
+      uint64_t key = 0;
+      for (int j = 0; j < L; ++j) key |= (uint64_t)bits[b * nq + pl.cs[(size_t)i * L + j].qubit] << j;
+      auto k = std::make_pair(cur[b], key);
+      auto it = index.find(k);
+      if (it == index.end()) {
+        const int32_t id = (int32_t)t.parent[i].size();
+        index.emplace(k, id);
+        t.parent[i].push_back(cur[b]);
+        for (int j = 0; j < L; ++j) t.tau[i].push_back((uint8_t)((key >> j) & 1));
+        next[b] = id;
+      } else {
+        next[b] = it->second;
+      }
+    }
+    cur.swap(next);
+  }
+  t.leaf = cur;
+  return t;
+}
+
+}  // namespace
+
+void run_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, size_t ws_bytes, void* stream,
+                    double* out) {
+  if (pl->host_only) fail(PSIM_EINVAL, "plan was made with PSIM_PLAN_HOST_ONLY");
+  if (!bits || !out) fail(PSIM_EINVAL, "bits or out is NULL");
+  if (n == 0) return;
+  if (!ws) fail(PSIM_EINVAL, "workspace is NULL");
+  if (ws_bytes < pl->ws_total)
+    fail(PSIM_EINVAL, "workspace has " + std::to_string(ws_bytes) + " bytes, plan needs " +
+                          std::to_string(pl->ws_total));
+  const int nq = pl->lv * pl->lh;
+  for (size_t x = 0; x < n * (size_t)nq; ++x)
+    if (bits[x] > 1) fail(PSIM_EINVAL, "bit " + std::to_string(x) + " is not 0 or 1");
+  // Split into sub-batches whose prefix trie fits the planned capacities:
+  // sort the bitstrings by their swept rows (row 0 first) so that neighbours
+  // share the longest prefixes, then cut greedily.
+  if (!pl->in_subbatch) {
+    std::vector<size_t> order(n);
+    for (size_t b = 0; b < n; ++b) order[b] = b;
+    auto rowkey = [&](size_t b, int i) {
+      uint64_t key = 0;
+      for (int j = 0; j < pl->L; ++j) key |= (uint64_t)bits[b * nq + pl->cs[(size_t)i * pl->L + j].qubit] << j;
+      return key;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+      for (int i = 0; i < pl->R; ++i) {
+        const uint64_t a = rowkey(x, i), b = rowkey(y, i);
+        if (a != b) return a < b;
+      }
+      return false;
+    });
+    std::vector<uint8_t> sb;
+    std::vector<double> so;
+    std::vector<int64_t> count(pl->R, 0);
+    size_t start = 0;
+    auto flush = [&](size_t end) {
+      const size_t m = end - start;
+      sb.resize(m * nq);
+      so.resize(2 * m);
+      for (size_t x = 0; x < m; ++x) std::memcpy(&sb[x * nq], bits + order[start + x] * nq, nq);
+      pl->in_subbatch = true;
+      try {
+        run_amplitudes(pl, sb.data(), m, ws, ws_bytes, stream, so.data());
+      } catch (...) {
+        pl->in_subbatch = false;
+        throw;
+      }
+      pl->in_subbatch = false;
+      for (size_t x = 0; x < m; ++x) {
+        out[2 * order[start + x]] = so[2 * x];
+        out[2 * order[start + x] + 1] = so[2 * x + 1];
+      }
+      start = end;
+    };
+    for (size_t x = 0; x < n; ++x) {
+      // first swept row where this bitstring leaves the previous one's path
+      int first = 0;
+      if (x > start) {
+        while (first < pl->R && rowkey(order[x], first) == rowkey(order[x - 1], first)) ++first;
+      }
+      bool fits = (int64_t)(x - start + 1) <= (int64_t)pl->opts.max_batch;
+      for (int i = (x > start ? first : 0); i < pl->R && fits; ++i) fits = count[i] + 1 <= pl->levels[i].cap;
+      if (!fits) {
+        flush(x);
+        std::fill(count.begin(), count.end(), 0);
+        first = 0;
+      }
+      for (int i = (x > start ? first : 0); i < pl->R; ++i) ++count[i];
+    }
+    flush(n);
+    return;
+  }
+  hip_check(hipSetDevice(pl->opts.device), "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  const int R = pl->R, L = pl->L, prec = pl->opts.prec;
+  const uint64_t eb = pl->elem_bytes;
+  Trie t = build_trie(*pl, bits, n);
+
+  // ------------------------------------------------------------ workspace
+  auto al = [](uint64_t x) { return (x + 255) / 256 * 256; };
+  char* base = (char*)(((uintptr_t)ws + 255) / 256 * 256);
+  char* p = base;
+  std::vector<int32_t*> d_parent(R);
+  std::vector<uint8_t*> d_tau(R);
+  int64_t nmax_all = 1;
+  for (int i = 0; i < R; ++i) {
+    const Level& lev = pl->levels[i];
+    d_parent[i] = (int32_t*)p;
+    p += al((uint64_t)lev.nmax * 4);
+    d_tau[i] = (uint8_t*)p;
+    p += al((uint64_t)lev.nmax * L);
+    nmax_all = std::max(nmax_all, lev.nmax);
+  }
+  int32_t* d_exp[2];
+  d_exp[0] = (int32_t*)p; p += al((uint64_t)nmax_all * 4);
+  d_exp[1] = (int32_t*)p; p += al((uint64_t)nmax_all * 4);
+  uint32_t* d_max = (uint32_t*)p; p += al((uint64_t)nmax_all * 4);
+  // boundaries of even / odd levels
+  char* dF[2] = {p + pl->levels[0].F_off, p + (R > 1 ? pl->levels[1].F_off : 0)};
+  p += pl->ws_F;
+  char* dG[2] = {p, p + pl->ws_G / 2};
+
+  for (int i = 0; i < R; ++i) {
+    if ((int64_t)t.parent[i].size() > pl->levels[i].cap) fail(PSIM_EINTERNAL, "trie larger than planned");
+    hip_check(hipMemcpyAsync(d_parent[i], t.parent[i].data(), t.parent[i].size() * 4, hipMemcpyHostToDevice, st),
+              "upload parents");
+    hip_check(hipMemcpyAsync(d_tau[i], t.tau[i].data(), t.tau[i].size(), hipMemcpyHostToDevice, st),
+              "upload bits");
+  }
+  // root exponent 0
+  const int32_t zero = 0;
+  hip_check(hipMemcpyAsync(d_exp[1], &zero, 4, hipMemcpyHostToDevice, st), "upload exponent");
+
+  // ------------------------------------------------------------ rows
+  for (int i = 0; i < R; ++i) {
+    const Level& lev = pl->levels[i];
+    const int64_t nodes = (int64_t)t.parent[i].size();
+    const void* Fprev = i == 0 ? pl->d_ones : (const void*)dF[(i - 1) % 2];
+    const int64_t Fprev_elems = i == 0 ? 1 : pl->levels[i - 1].F_elems;
+    char* Fcur = dF[i % 2];
+    const int c = lev.vchunk;
+    for (int64_t g0 = 0; g0 < nodes; g0 += lev.group) {
+      const int64_t gn = std::min<int64_t>(lev.group, nodes - g0);
+      for (int v0 = 0; v0 < lev.Dv; v0 += c) {
+        for (int j = 0; j < L; ++j) {
+          const Step& s = pl->steps[(size_t)i * L + j];
+          const DevMatrix& w0 = pl->w[((size_t)i * L + j) * 2];
+          const DevMatrix& w1 = pl->w[((size_t)i * L + j) * 2 + 1];
+          GemmLaunch g;
+          g.prec = prec;
+          g.W0 = w0.ptr;
+          g.W1 = w1.ptr;
+          g.ldw = w0.ld;
+          g.tau = d_tau[i] + g0 * L + j;
+          g.tau_stride = L;
+          g.nodes = gn;
+          g.N = s.N;
+          g.K2 = s.K2;
+          g.M = s.M;
+          if (s.kind == 2) {
+            g.trans_out = 1;
+            g.Bz = 1;
+            g.C = Fcur + (uint64_t)g0 * lev.F_elems * eb;
+            g.sC_node = lev.F_elems;
+            if (L == 1) {  // the only site: contracts the parent's boundary directly
+              g.A = Fprev;
+              g.a_index = d_parent[i] + g0;
+              g.sA_node = Fprev_elems;
+              g.K1 = lev.Dv;
+              g.beta = 0;
+            } else {
+              g.A = dG[(L - 2) % 2];
+              g.sA_node = (int64_t)c * s.M * s.K2;
+              g.K1 = c;
+              g.w_koff = (int64_t)v0 * s.K2;
+              g.beta = v0 > 0;
+            }
+          } else {
+            g.Bz = c;
+            g.K1 = s.K1;
+            g.C = dG[j % 2];
+            g.sC_v = s.g_out;
+            g.sC_node = (int64_t)c * s.g_out;
+            if (s.kind == 0) {
+              g.A = (const char*)Fprev + (uint64_t)v0 * s.K1 * s.M * eb;
+              g.a_index = d_parent[i] + g0;
+              g.sA_node = Fprev_elems;
+              g.sA_v = s.K1 * s.M;
+            } else {
+              g.A = dG[(j - 1) % 2];
+              g.sA_v = s.K1 * s.M * s.K2;
+              g.sA_node = (int64_t)c * g.sA_v;
+            }
+          }
+          launch_site_gemm(g, st);
+        }
+        if (L == 1) break;  // the single site consumed every v at once
+      }
+    }
+    // exact power-of-two rescale of every node's boundary; exponents along the trie
+    launch_rowscale(prec, Fcur, lev.F_elems, nodes, d_parent[i], d_exp[(i + 1) % 2], d_exp[i % 2], d_max, st);
+  }
+
+  // ------------------------------------------------------------ results
+  const int64_t leaves = (int64_t)t.parent[R - 1].size();
+  std::vector<char> vals((size_t)leaves * eb);
+  std::vector<int32_t> ex((size_t)leaves);
+  hip_check(hipMemcpyAsync(vals.data(), dF[(R - 1) % 2], vals.size(), hipMemcpyDeviceToHost, st), "download");
+  hip_check(hipMemcpyAsync(ex.data(), d_exp[(R - 1) % 2], ex.size() * 4, hipMemcpyDeviceToHost, st), "download");
+  hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+  for (size_t b = 0; b < n; ++b) {
+    const int32_t leaf = t.leaf[b];
+    double re, im;
+    if (eb == 16) {
+      const double* v = (const double*)vals.data();
+      re = v[2 * leaf];
+      im = v[2 * leaf + 1];
+    } else {
+      const float* v = (const float*)vals.data();
+      re = v[2 * leaf];
+      im = v[2 * leaf + 1];
+    }
+    int64_t e = ex[leaf];
+    for (int i = 0; i < R; ++i)
+      for (int j = 0; j < L; ++j) {
+        const int tau = bits[b * nq + pl->cs[(size_t)i * L + j].qubit];
+        e += pl->w[((size_t)i * L + j) * 2 + tau].exp2;
+      }
+    out[2 * b] = std::ldexp(re, (int)e);
+    out[2 * b + 1] = std::ldexp(im, (int)e);
+  }
+}

@@ -1,0 +1,479 @@
+// Site-contraction kernels for gfx950 (CDNA4).
+//
+// One launch computes, for every batch entry z = (node, v):
+//   C[m][n] = sum_{k1, k2} A[k1][m][k2] * W[k1*K2 + k2][n]        (complex, eq. S4)
+// A and C are interleaved complex (re, im).  The complex product is done as a
+// single real GEMM (the 4M scheme): the interleaved row of A (length 2K) times
+// the real 2K x 2N expansion B' of W (packed on the host, stored transposed
+// as P[n'][k']) yields the interleaved row of C.  B' has 4 real entries per
+// complex entry of W, so the real GEMM does exactly the 8 real flops of a
+// complex multiply-add.
+//
+// Tiling: 256 threads = 4 waves in a 2 x 2 grid; each wave owns a
+// (BM/2) x (BN/2) block of real outputs held in MFMA accumulators.  Tiles of
+// A (BM x BK) and P (BN x BK) are staged through LDS with double buffering:
+// global loads for stage k+1 are issued before the MFMAs of stage k and
+// written to the other LDS buffer afterwards, one barrier per stage.  Inside
+// a stage each lane reads 16-byte fragments (4 consecutive k for FP32, 2 for
+// FP64) so that one LDS read feeds several MFMAs; the k order inside a group
+// of 8 is permuted identically for A and B, which leaves the sum unchanged.
+//
+// Workgroups are assigned XCD-aware: hardware dispatches workgroup b to XCD
+// b mod 8, so tile t = (b mod 8) * ceil(T/8) + b / 8 gives each XCD a
+// contiguous range of tiles, and the N-tiles of one M-block (which share the
+// same rows of A) run on the same XCD and its L2.
+//
+// A-tile loaders: ROWMAJOR reads 16 bytes along k (needs an even K2 for
+// FP32), KMAJOR reads along m when K2 == 1 (A stored as A[k][m]: the first
+// site of a row) and transposes into LDS, GENERIC reads one complex at a time.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "psim_internal.hpp"
+
+namespace psim {
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+enum AMode { ROWMAJOR = 0, KMAJOR = 1, GENERIC = 2 };
+
+struct KArgs {
+  const void* A;
+  void* C;
+  const void* W0;
+  const void* W1;
+  const int32_t* a_index;
+  const uint8_t* tau;
+  long long tau_stride;
+  long long M, K1, K2, N;
+  long long K;        // complex K = K1 * K2
+  long long Kr, Nr;   // real 2K, 2N
+  long long ldw, w_koff_r;
+  long long sA_node, sA_v, sC_node, sC_v;
+  long long MT, NT, T;
+  int Bz, trans_out, beta;
+};
+
+// ---------------------------------------------------------------- traits
+template <typename T>
+struct Mfma;
+
+template <>
+struct Mfma<float> {
+  static constexpr int MB = 32;       // block edge
+  static constexpr int KPI = 2;       // k per instruction
+  static constexpr int NACC = 16;     // accumulators per lane per block
+  static constexpr int KV = 4;        // k per lane per group of 8
+  typedef f32x16 acc_t;
+  typedef f32x4 frag_t;
+  __device__ static inline void mma(const frag_t& a, const frag_t& b, acc_t& c, int s) {
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s], b[s], c, 0, 0, 0);
+  }
+  // row of output element r held by lane
+  __device__ static inline int out_row(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+  __device__ static inline int out_col(int lane) { return lane & 31; }
+};
+
+template <>
+struct Mfma<double> {
+  static constexpr int MB = 16;
+  static constexpr int KPI = 4;
+  static constexpr int NACC = 4;
+  static constexpr int KV = 2;
+  typedef f64x4 acc_t;
+  typedef f64x2 frag_t;
+  __device__ static inline void mma(const frag_t& a, const frag_t& b, acc_t& c, int s) {
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], c, 0, 0, 0);
+  }
+  // measured on gfx950: accumulator r of lane l holds row 4r + l/16, column l%16
+  __device__ static inline int out_row(int lane, int r) { return 4 * r + (lane >> 4); }
+  __device__ static inline int out_col(int lane) { return lane & 15; }
+};
+
+// 16-byte vector of T
+template <typename T>
+struct V16;
+template <>
+struct V16<float> { typedef f32x4 t; static constexpr int n = 4; };
+template <>
+struct V16<double> { typedef f64x2 t; static constexpr int n = 2; };
+
+// ---------------------------------------------------------------- kernel
+template <typename T, int BM, int BN, int BK, int AMODE>
+__global__ __launch_bounds__(256) void site_gemm(KArgs p) {
+  typedef Mfma<T> MF;
+  typedef typename V16<T>::t vec_t;
+  constexpr int VN = V16<T>::n;          // reals per 16-byte vector
+  constexpr int LDS_LD = BK + VN;        // padded row length (reals)
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int MBLK = WM / MF::MB, NBLK = WN / MF::MB;
+  constexpr int GROUPS = BK / 8;
+  // A tile: BM x BK reals = BM * BK / VN vectors
+  constexpr int A_VECS = BM * BK / VN / 256;
+  constexpr int B_VECS = BN * BK / VN / 256;
+  static_assert(A_VECS * VN * 256 == BM * BK, "A tile");
+  static_assert(B_VECS * VN * 256 == BN * BK, "B tile");
+  // GENERIC loader works on single complex numbers (2 reals)
+  constexpr int A_CPLX = BM * BK / 2 / 256;
+
+  __shared__ __attribute__((aligned(16))) T sA[2][BM * LDS_LD];
+  __shared__ __attribute__((aligned(16))) T sB[2][BN * LDS_LD];
+
+  const long long per_xcd = (p.T + 7) / 8;
+  const long long bid = blockIdx.x;
+  const long long t = (bid % 8) * per_xcd + bid / 8;
+  if (t >= p.T) return;
+  const long long nt = t % p.NT;
+  const long long rest = t / p.NT;
+  const long long mt = rest % p.MT;
+  const long long z = rest / p.MT;
+  const long long node = z / p.Bz, vb = z % p.Bz;
+  const long long ablk = p.a_index ? (long long)p.a_index[node] : node;
+  const T* __restrict__ A = (const T*)p.A + 2 * (ablk * p.sA_node + vb * p.sA_v);
+  const int tauv = p.tau ? (int)p.tau[node * p.tau_stride] : 0;
+  const T* __restrict__ W = (const T*)(tauv ? p.W1 : p.W0) + p.w_koff_r;
+  T* __restrict__ C = (T*)p.C + 2 * (node * p.sC_node + vb * p.sC_v);
+  const long long m0 = mt * BM, n0 = nt * BN;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  const long long sK1 = p.M * p.K2;    // complex stride of k1 in A
+  const unsigned K2u = (unsigned)p.K2;
+
+  vec_t ra[AMODE == GENERIC ? 1 : A_VECS];
+  T rc[AMODE == GENERIC ? A_CPLX * 2 : 1];
+  vec_t rb[B_VECS];
+
+  auto load_a = [&](long long kr0) {
+    if constexpr (AMODE == ROWMAJOR) {
+#pragma unroll
+      for (int it = 0; it < A_VECS; ++it) {
+        const int lin = it * 256 + tid;
+        const int row = lin / (BK / VN), kq = lin % (BK / VN);
+        const long long m = m0 + row, kr = kr0 + kq * VN;
+        vec_t v = {};
+        if (m < p.M && kr < p.Kr) {
+          const unsigned k = (unsigned)(kr >> 1);
+          const unsigned k1 = k / K2u, k2 = k - k1 * K2u;
+          v = *(const vec_t*)(A + 2 * ((long long)k1 * sK1 + m * p.K2 + k2));
+        }
+        ra[it] = v;
+      }
+    } else if constexpr (AMODE == KMAJOR) {
+      // VN/2 complex along m per vector, BK/2 complex k per tile
+      constexpr int CPV = VN / 2;
+#pragma unroll
+      for (int it = 0; it < A_VECS; ++it) {
+        const int lin = it * 256 + tid;
+        const int kk = lin / (BM / CPV), mp = lin % (BM / CPV);
+        const long long m = m0 + mp * CPV, k = (kr0 >> 1) + kk;
+        vec_t v = {};
+        if (m < p.M && k < p.K) v = *(const vec_t*)(A + 2 * (k * p.M + m));
+        ra[it] = v;
+      }
+    } else {
+#pragma unroll
+      for (int it = 0; it < A_CPLX; ++it) {
+        const int lin = it * 256 + tid;
+        const int row = lin / (BK / 2), kc = lin % (BK / 2);
+        const long long m = m0 + row, k = (kr0 >> 1) + kc;
+        T re = 0, im = 0;
+        if (m < p.M && k < p.K) {
+          const unsigned k1 = (unsigned)k / K2u, k2 = (unsigned)k - k1 * K2u;
+          const T* q = A + 2 * ((long long)k1 * sK1 + m * p.K2 + k2);
+          re = q[0];
+          im = q[1];
+        }
+        rc[2 * it] = re;
+        rc[2 * it + 1] = im;
+      }
+    }
+  };
+  auto store_a = [&](int buf) {
+    T* s = sA[buf];
+    if constexpr (AMODE == ROWMAJOR) {
+#pragma unroll
+      for (int it = 0; it < A_VECS; ++it) {
+        const int lin = it * 256 + tid;
+        const int row = lin / (BK / VN), kq = lin % (BK / VN);
+        *(vec_t*)(s + row * LDS_LD + kq * VN) = ra[it];
+      }
+    } else if constexpr (AMODE == KMAJOR) {
+      constexpr int CPV = VN / 2;
+#pragma unroll
+      for (int it = 0; it < A_VECS; ++it) {
+        const int lin = it * 256 + tid;
+        const int kk = lin / (BM / CPV), mp = lin % (BM / CPV);
+#pragma unroll
+        for (int c = 0; c < CPV; ++c) {
+          s[(mp * CPV + c) * LDS_LD + 2 * kk] = ra[it][2 * c];
+          s[(mp * CPV + c) * LDS_LD + 2 * kk + 1] = ra[it][2 * c + 1];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int it = 0; it < A_CPLX; ++it) {
+        const int lin = it * 256 + tid;
+        const int row = lin / (BK / 2), kc = lin % (BK / 2);
+        s[row * LDS_LD + 2 * kc] = rc[2 * it];
+        s[row * LDS_LD + 2 * kc + 1] = rc[2 * it + 1];
+      }
+    }
+  };
+  auto load_b = [&](long long kr0) {
+#pragma unroll
+    for (int it = 0; it < B_VECS; ++it) {
+      const int lin = it * 256 + tid;
+      const int row = lin / (BK / VN), kq = lin % (BK / VN);
+      rb[it] = *(const vec_t*)(W + (n0 + row) * p.ldw + kr0 + kq * VN);
+    }
+  };
+  auto store_b = [&](int buf) {
+    T* s = sB[buf];
+#pragma unroll
+    for (int it = 0; it < B_VECS; ++it) {
+      const int lin = it * 256 + tid;
+      const int row = lin / (BK / VN), kq = lin % (BK / VN);
+      *(vec_t*)(s + row * LDS_LD + kq * VN) = rb[it];
+    }
+  };
+
+  typename MF::acc_t acc[MBLK][NBLK];
+#pragma unroll
+  for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < NBLK; ++bj)
+#pragma unroll
+      for (int r = 0; r < MF::NACC; ++r) acc[bi][bj][r] = 0;
+
+  const long long nk = (p.Kr + BK - 1) / BK;
+  load_a(0);
+  load_b(0);
+  store_a(0);
+  store_b(0);
+  __syncthreads();
+
+  // lane's fragment position inside a group of 8 k
+  const int frow = lane % MF::MB;
+  const int fk = (lane / MF::MB) * MF::KV;
+
+  for (long long kt = 0; kt < nk; ++kt) {
+    const int cur = (int)(kt & 1);
+    const bool more = kt + 1 < nk;
+    if (more) {
+      load_a((kt + 1) * BK);
+      load_b((kt + 1) * BK);
+    }
+    const T* a_s = sA[cur];
+    const T* b_s = sB[cur];
+#pragma unroll
+    for (int g = 0; g < GROUPS; ++g) {
+      typename MF::frag_t af[MBLK], bf[NBLK];
+#pragma unroll
+      for (int bi = 0; bi < MBLK; ++bi)
+        af[bi] = *(const typename MF::frag_t*)(a_s + (wr * WM + bi * MF::MB + frow) * LDS_LD + g * 8 + fk);
+#pragma unroll
+      for (int bj = 0; bj < NBLK; ++bj)
+        bf[bj] = *(const typename MF::frag_t*)(b_s + (wc * WN + bj * MF::MB + frow) * LDS_LD + g * 8 + fk);
+#pragma unroll
+      for (int s = 0; s < MF::KV; ++s)
+#pragma unroll
+        for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < NBLK; ++bj) MF::mma(af[bi], bf[bj], acc[bi][bj], s);
+    }
+    if (more) {
+      store_a(cur ^ 1);
+      store_b(cur ^ 1);
+    }
+    __syncthreads();
+  }
+
+  // ------------------------------------------------------------ epilogue
+#pragma unroll
+  for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < NBLK; ++bj)
+#pragma unroll
+      for (int r = 0; r < MF::NACC; ++r) {
+        const long long row = m0 + wr * WM + bi * MF::MB + MF::out_row(lane, r);
+        const long long col = n0 + wc * WN + bj * MF::MB + MF::out_col(lane);
+        if (row < p.M && col < p.Nr) {
+          const T v = acc[bi][bj][r];
+          if (!p.trans_out) {
+            C[row * p.Nr + col] = v;
+          } else {
+            T* dst = C + 2 * ((col >> 1) * p.M + row) + (col & 1);
+            *dst = p.beta ? *dst + v : v;
+          }
+        }
+      }
+}
+
+// ---------------------------------------------------------------- rescale
+// Per node: largest binary exponent of any component (as exponent + 4096,
+// so that unsigned atomicMax orders it), 0 when the node is all zeros.
+template <typename T>
+__global__ void row_absmax(const T* __restrict__ F, long long per_node, uint32_t* mx) {
+  const long long node = blockIdx.y;
+  const T* f = F + 2 * node * per_node;
+  T m = 0;
+  for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < 2 * per_node;
+       x += (long long)gridDim.x * blockDim.x)
+    m = fmax(m, fabs(f[x]));
+  // wave reduction
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  __shared__ T red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
+    if (m > 0) {
+      int e;
+      frexp(m, &e);  // m = f 2^e, f in [0.5, 1)
+      atomicMax(mx + node, (uint32_t)(e + 4096));
+    }
+  }
+}
+
+__global__ void row_exponent(long long nodes, const int32_t* parent, const int32_t* exp_prev, int32_t* exp_cur,
+                             uint32_t* mx) {
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nodes) return;
+  const int e = mx[n] ? (int)mx[n] - 4096 : 0;
+  exp_cur[n] = exp_prev[parent[n]] + e;
+  mx[n] = (uint32_t)(e + 4096);  // keep the shift for row_apply
+}
+
+template <typename T>
+__global__ void row_apply(T* __restrict__ F, long long per_node, const uint32_t* mx) {
+  const long long node = blockIdx.y;
+  const int e = (int)mx[node] - 4096;
+  if (e == 0) return;
+  T* f = F + 2 * node * per_node;
+  for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < 2 * per_node;
+       x += (long long)gridDim.x * blockDim.x)
+    f[x] = ldexp(f[x], -e);
+}
+
+__global__ void zero_u32(uint32_t* p, long long n) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x < n) p[x] = 0;
+}
+
+template <typename T>
+__global__ void fill_one(T* p) {
+  p[0] = 1;
+  p[1] = 0;
+}
+
+// ---------------------------------------------------------------- host side
+void hip_check(int err, const char* what) {
+  if (err != hipSuccess)
+    fail(PSIM_EDEVICE, std::string(what) + ": " + hipGetErrorString((hipError_t)err));
+}
+
+void launch_site_gemm(const GemmLaunch& g, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (g.M < 1 || g.K1 < 1 || g.K2 < 1 || g.N < 1 || g.nodes < 1 || g.Bz < 1)
+    fail(PSIM_EINVAL, "site gemm: non-positive size");
+  if (g.M >= (1LL << 31) || g.K1 * g.K2 >= (1LL << 30))
+    fail(PSIM_EUNSUPPORTED, "site gemm: M or K too large for one batch entry");
+  KArgs a{};
+  a.A = g.A;
+  a.C = g.C;
+  a.W0 = g.W0;
+  a.W1 = g.W1 ? g.W1 : g.W0;
+  a.a_index = g.a_index;
+  a.tau = g.tau;
+  a.tau_stride = g.tau_stride;
+  a.M = g.M;
+  a.K1 = g.K1;
+  a.K2 = g.K2;
+  a.N = g.N;
+  a.K = g.K1 * g.K2;
+  a.Kr = 2 * a.K;
+  a.Nr = 2 * g.N;
+  a.ldw = g.ldw;
+  a.w_koff_r = 2 * g.w_koff;
+  a.sA_node = g.sA_node;
+  a.sA_v = g.sA_v;
+  a.sC_node = g.sC_node;
+  a.sC_v = g.sC_v;
+  a.Bz = g.Bz;
+  a.trans_out = g.trans_out;
+  a.beta = g.beta;
+  // batch entries = nodes * Bz; the kernel splits z = node * Bz + v
+  const long long Z = g.nodes * g.Bz;
+  if (g.prec == PSIM_FP64) {
+    if (g.K2 == 1 && g.K1 > 1) {
+      KArgs b = a;
+      b.MT = (b.M + 64 - 1) / 64;
+      b.NT = (b.Nr + 64 - 1) / 64;
+      b.T = b.MT * b.NT * Z;
+      const long long blocks = (b.T + 7) / 8 * 8;
+      hipLaunchKernelGGL((site_gemm<double, 64, 64, 16, KMAJOR>), dim3((unsigned)blocks), dim3(256), 0, st, b);
+    } else {
+      KArgs b = a;
+      b.MT = (b.M + 64 - 1) / 64;
+      b.NT = (b.Nr + 64 - 1) / 64;
+      b.T = b.MT * b.NT * Z;
+      const long long blocks = (b.T + 7) / 8 * 8;
+      hipLaunchKernelGGL((site_gemm<double, 64, 64, 16, GENERIC>), dim3((unsigned)blocks), dim3(256), 0, st, b);
+    }
+  } else {
+    KArgs b = a;
+    b.MT = (b.M + 128 - 1) / 128;
+    b.NT = (b.Nr + 128 - 1) / 128;
+    b.T = b.MT * b.NT * Z;
+    const long long blocks = (b.T + 7) / 8 * 8;
+    if (blocks > 0x7fffffffLL) fail(PSIM_EUNSUPPORTED, "grid too large");
+    // 16-byte vector loads need every batch entry's A to start 16-byte aligned
+    const bool even_base = ((uintptr_t)g.A % 16 == 0) && (g.sA_node % 2 == 0) && (g.sA_v % 2 == 0);
+    if (g.K2 % 2 == 0 && even_base)
+      hipLaunchKernelGGL((site_gemm<float, 128, 128, 32, ROWMAJOR>), dim3((unsigned)blocks), dim3(256), 0, st, b);
+    else if (g.K2 == 1 && g.M % 2 == 0 && g.K1 > 1 && even_base)
+      hipLaunchKernelGGL((site_gemm<float, 128, 128, 32, KMAJOR>), dim3((unsigned)blocks), dim3(256), 0, st, b);
+    else
+      hipLaunchKernelGGL((site_gemm<float, 128, 128, 32, GENERIC>), dim3((unsigned)blocks), dim3(256), 0, st, b);
+  }
+  hip_check(hipGetLastError(), "site_gemm launch");
+}
+
+void launch_rowscale(int prec, void* F, int64_t per_node, int64_t nodes, const int32_t* parent,
+                     const int32_t* exp_prev, int32_t* exp_cur, uint32_t* mx, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const unsigned nb = (unsigned)((nodes + 255) / 256);
+  hipLaunchKernelGGL(zero_u32, dim3(nb), dim3(256), 0, st, mx, nodes);
+  long long per_block = 256 * 16;
+  unsigned gx = (unsigned)std::min<long long>((2 * per_node + per_block - 1) / per_block, 4096);
+  if (gx == 0) gx = 1;
+  if (nodes > 65535) fail(PSIM_EUNSUPPORTED, "too many nodes for one rescale launch");
+  if (prec == PSIM_FP64)
+    hipLaunchKernelGGL(row_absmax<double>, dim3(gx, (unsigned)nodes), dim3(256), 0, st, (const double*)F, per_node, mx);
+  else
+    hipLaunchKernelGGL(row_absmax<float>, dim3(gx, (unsigned)nodes), dim3(256), 0, st, (const float*)F, per_node, mx);
+  hipLaunchKernelGGL(row_exponent, dim3(nb), dim3(256), 0, st, nodes, parent, exp_prev, exp_cur, mx);
+  if (prec == PSIM_FP64)
+    hipLaunchKernelGGL(row_apply<double>, dim3(gx, (unsigned)nodes), dim3(256), 0, st, (double*)F, per_node, mx);
+  else
+    hipLaunchKernelGGL(row_apply<float>, dim3(gx, (unsigned)nodes), dim3(256), 0, st, (float*)F, per_node, mx);
+  hip_check(hipGetLastError(), "rowscale launch");
+}
+
+void launch_fill_ones(int prec, void* p, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == PSIM_FP64)
+    hipLaunchKernelGGL(fill_one<double>, dim3(1), dim3(1), 0, st, (double*)p);
+  else
+    hipLaunchKernelGGL(fill_one<float>, dim3(1), dim3(1), 0, st, (float*)p);
+  hip_check(hipGetLastError(), "fill ones launch");
+}
+
+}  // namespace psim

@@ -1,0 +1,140 @@
+// Internal types of libpsim: PEPS, contraction plan, kernel launch interface.
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "psim.h"
+
+namespace psim {
+
+using cd = std::complex<double>;
+
+// ---------------------------------------------------------------- errors
+struct Error {
+  psim_status status;
+  std::string msg;
+};
+[[noreturn]] void fail(psim_status st, const std::string& msg);
+void set_last_error(const std::string& msg);
+
+// ---------------------------------------------------------------- PEPS
+// Rank-5 site tensor A[sigma][l][r][u][d] (eq. 1), row-major in that order.
+struct Site {
+  int dl = 1, dr = 1, du = 1, dd = 1;
+  std::vector<cd> t;  // 2 * dl * dr * du * dd
+  size_t size() const { return t.size(); }
+  size_t at(int s, int l, int r, int u, int d) const {
+    return ((((size_t)s * dl + l) * dr + r) * du + u) * dd + d;
+  }
+};
+
+}  // namespace psim
+
+struct psim_peps_s {
+  int lv = 0, lh = 0;
+  std::vector<psim::Site> sites;  // qubit n = r * lh + c
+};
+
+namespace psim {
+
+// gates.cpp
+void gate_matrix_1q(int kind, const double* m, cd out[4]);
+void gate_matrix_2q(int kind, const double* m, cd out[16]);
+bool is_two_qubit(int kind);
+
+// build.cpp
+void jacobi_svd4(const cd M[16], cd U[16], double S[4], cd V[16]);
+
+// ---------------------------------------------------------------- plan
+// Site of the swept lattice: contraction row i (0..R-1), column j (0..L-1).
+// Legs are named in the sweep frame (l, r, u, d); u/d run along the sweep.
+struct CSite {
+  int qubit = 0;
+  int dl = 1, dr = 1, du = 1, dd = 1;
+};
+
+// One site contraction (eqs. S3-S5) for one node (prefix) and one v value.
+struct Step {
+  int i = 0, j = 0;
+  int kind = 0;          // 0 first site, 1 interior, 2 last site (K1 = v chunk)
+  int64_t M = 1, K1 = 1, K2 = 1, N = 1;
+  int64_t g_out = 0;     // elements of the output per (node, v) (kind 0/1)
+};
+
+struct Level {
+  int64_t F_elems = 1;   // elements of F_i (boundary after row i)
+  int64_t Gmax = 0;      // largest per-(node, v) intermediate of this row
+  int Dv = 1;            // size of the leg v = u of the last site in this row
+  int vchunk = 1;        // v values per pass
+  int group = 1;         // nodes per pass
+  int64_t nmax = 1;      // most nodes (distinct prefixes) this level can have
+  int64_t cap = 1;       // nodes whose boundary fits the workspace at once
+  uint64_t F_off = 0;    // byte offset of this level's boundary buffer in the F region
+};
+
+struct DevMatrix {
+  void* ptr = nullptr;   // packed, on device
+  int64_t ld = 0;        // leading dimension (real elements) of the packed layout
+  int exp2 = 0;          // site matrix was scaled by 2^-exp2
+};
+
+}  // namespace psim
+
+struct psim_plan_s {
+  psim_plan_opts opts{};
+  int lv = 0, lh = 0;
+  int R = 0, L = 0;
+  int sweep = 1;                         // 1 rows, 2 columns
+  int chi = 1;
+  std::vector<psim::CSite> cs;           // R * L, index i * L + j
+  std::vector<psim::Level> levels;       // R
+  std::vector<psim::Step> steps;         // per row i: L steps (index i * L + j)
+  std::vector<psim::DevMatrix> w;        // per site and tau: (i * L + j) * 2 + tau
+  double cmac = 0;
+  int64_t peak_elems = 0;
+  uint64_t weights_bytes = 0;
+  uint64_t ws_F = 0, ws_G = 0, ws_tab = 0, ws_total = 0;
+  bool host_only = false;
+  int elem_bytes = 8;
+  void* d_ones = nullptr;                // device scalar 1 (the empty boundary before row 0)
+  bool in_subbatch = false;              // scheduler re-entry guard
+};
+
+namespace psim {
+
+// pack.cpp / kernels: sizes of the packed site matrix for a precision
+int64_t packed_ld(int prec, int64_t K);
+int64_t packed_rows(int prec, int64_t N);
+void pack_site_matrix(int prec, const cd* W, int64_t K, int64_t N, std::vector<char>& out, int64_t& ld);
+
+// kernels.hip: launch interface (host side)
+struct GemmLaunch {
+  int prec = PSIM_FP32_4M;
+  const void* A = nullptr;
+  void* C = nullptr;
+  const void* W0 = nullptr;
+  const void* W1 = nullptr;
+  const int32_t* a_index = nullptr;   // per node: block of A to read (nullable: node itself)
+  const uint8_t* tau = nullptr;       // per node: 0/1 selects W0/W1 (nullable: W0)
+  int64_t tau_stride = 0;
+  int64_t M = 1, K1 = 1, K2 = 1, N = 1;
+  int64_t ldw = 0;                    // packed W leading dimension
+  int64_t w_koff = 0;                 // complex k offset into W (v chunk of the last site)
+  int64_t sA_node = 0, sA_v = 0;      // strides in complex elements
+  int64_t sC_node = 0, sC_v = 0;
+  int64_t nodes = 1;
+  int32_t Bz = 1;                     // batch entries per node
+  int32_t trans_out = 0;
+  int32_t beta = 0;
+};
+void launch_site_gemm(const GemmLaunch& g, void* stream);
+void launch_rowscale(int prec, void* F, int64_t elems_per_node, int64_t nodes, const int32_t* parent,
+                     const int32_t* exp_prev, int32_t* exp_cur, uint32_t* scratch_max, void* stream);
+void launch_fill_ones(int prec, void* p, void* stream);
+
+void hip_check(int err, const char* what);
+
+}  // namespace psim

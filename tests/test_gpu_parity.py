@@ -1,0 +1,214 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Error measures for an amplitude a against the FP64 oracle value r:
+  eps_rel = |a - r| / |r|                       (per amplitude)
+  eps_rms = |a - r| * 2^(N/2)                   (relative to the RMS amplitude,
+                                                 since sum |r|^2 = 1)
+Bars: FP64 path eps_rms <= 1e-10; FP32 path eps_rms <= 1e-5 on every
+amplitude.  A site contraction (eq. S4) is compared element by element with
+the oracle's labelled tensordot: max |C - C_ref| <= tol * max |C_ref| with
+tol = 1e-12 (FP64) and 2e-6 * log2(2K) (FP32 accumulation over 2K real terms).
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import rqcgen
+from oracle import peps as opeps
+from oracle import statevector as sv
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ps():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1905_08394_amd as ps
+    ps.lib()
+    return ps
+
+
+def _golden(name):
+    with open(os.path.join(HERE, "golden", name)) as f:
+        g = json.load(f)
+    return g, np.array(g["bits"], dtype=np.uint8), np.array(g["amps_re"]) + 1j * np.array(g["amps_im"])
+
+
+def _errors(a, r, n):
+    a, r = np.asarray(a), np.asarray(r)
+    d = np.abs(a - r)
+    return d / np.abs(r), d * 2.0 ** (n / 2)
+
+
+# ---------------------------------------------------------------- site step
+
+def _oracle_step(A, W, M, K1, K2, N):
+    """The oracle's S4 contraction on labelled tensors: C[m][n]."""
+    out = []
+    for z in range(A.shape[0]):
+        a = opeps.LT(A[z].reshape(K1, M, K2), [("k1",), ("m",), ("k2",)])
+        w = opeps.LT(W.reshape(K1, K2, N), [("k1",), ("k2",), ("n",)])
+        out.append(opeps.contract(a, w).ordered([("m",), ("n",)]))
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("M,K1,K2,N,batch,trans", [
+    (300, 3, 8, 50, 2, False),     # row-major A, ragged M and N
+    (260, 16, 1, 64, 1, False),    # K-major A (first site of a row)
+    (77, 5, 3, 33, 2, False),      # odd K2: generic loader, odd M
+    (129, 4, 16, 1, 1, True),      # last site: transposed store, N = 1
+    (1, 1, 1, 7, 3, False),        # degenerate
+    (512, 32, 32, 64, 1, True),    # full-depth K = 1024
+])
+def test_site_contraction_parity(ps, prec, M, K1, K2, N, batch, trans):
+    import torch
+    say(f"site {prec} M={M} K1={K1} K2={K2} N={N} batch={batch} trans={trans}")
+    rng = np.random.default_rng(M * 7 + K1 + N)
+    A = (rng.standard_normal((batch, K1 * M * K2)) + 1j * rng.standard_normal((batch, K1 * M * K2)))
+    W = rng.standard_normal((K1 * K2, N)) + 1j * rng.standard_normal((K1 * K2, N))
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    if prec != "fp64":   # the FP32 path sees the inputs rounded to FP32
+        A = A.astype(np.complex64).astype(np.complex128)
+        W = W.astype(np.complex64).astype(np.complex128)
+    Ad = torch.from_numpy(A.reshape(-1)).to(dt).cuda()
+    C = ps.contract_site(prec, Ad, W, M, K1, K2, N, batch=batch, transpose_out=trans).cpu().numpy()
+    ref = _oracle_step(A, W, M, K1, K2, N)
+    if trans:
+        ref = ref.transpose(0, 2, 1)
+    C = C.reshape(ref.shape)
+    tol = 1e-12 if prec == "fp64" else 2e-6 * np.log2(2 * K1 * K2)
+    assert np.max(np.abs(C - ref)) <= tol * np.max(np.abs(ref))
+
+
+def test_site_contraction_full_size_sampled(ps):
+    """Hot step at the 6x6 (1+40+1) shape: M = 32^4, K = N = 32^2, sampled outputs."""
+    import torch
+    M, K1, K2, N = 32 ** 4, 32, 32, 1024
+    say(f"full-size site M={M} K={K1 * K2} N={N}")
+    g = torch.Generator(device="cuda").manual_seed(0)
+    A = torch.randn(K1 * M * K2, dtype=torch.complex64, device="cuda", generator=g)
+    rng = np.random.default_rng(1)
+    W = (rng.standard_normal((K1 * K2, N)) + 1j * rng.standard_normal((K1 * K2, N))).astype(np.complex64)
+    C = ps.contract_site("fp32", A, W.astype(np.complex128), M, K1, K2, N)
+    torch.cuda.synchronize()
+    ms = rng.integers(0, M, 48)
+    ns = rng.integers(0, N, 48)
+    A3 = A.view(K1, M, K2)
+    for m, n in zip(ms, ns):
+        row = A3[:, int(m), :].reshape(-1).cpu().numpy().astype(np.complex128)   # (k1, k2)
+        ref = np.sum(row * W[:, int(n)].astype(np.complex128))
+        got = complex(C[int(m) * N + int(n)].item())
+        scale = np.sqrt(np.sum(np.abs(row) ** 2) * np.sum(np.abs(W[:, int(n)]) ** 2))
+        assert abs(got - ref) <= 2e-6 * np.log2(2 * K1 * K2) * scale
+    del A, C
+
+
+# ---------------------------------------------------------------- amplitudes
+
+def _run(ps, circuit, bits, prec, **kw):
+    P = ps.Peps(circuit)
+    pl = ps.Plan(P, prec=prec, max_batch=len(bits), **kw)
+    return pl.amplitudes(bits), pl
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_3x3_all_amplitudes(ps, prec):
+    g, bits, ref = _golden("rqc_3x3_d8_s0.json")
+    c = rqcgen.generate(3, 3, 8, 0)
+    assert c.sha256() == g["sha256"]
+    say(f"3x3 d8 all 512, {prec}")
+    a, _ = _run(ps, c, bits, prec)
+    _, erms = _errors(a, ref, 9)
+    assert np.max(erms) <= (1e-10 if prec == "fp64" else 1e-5)
+    assert abs(np.sum(np.abs(a) ** 2) - 1) < (1e-12 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_4x5_eight_seeds(ps, prec):
+    worst = 0
+    for seed in range(8):
+        g, bits, ref = _golden(f"rqc_4x5_d24_s{seed}.json")
+        c = rqcgen.generate(4, 5, 24, seed)
+        assert c.sha256() == g["sha256"]
+        say(f"4x5 d24 seed {seed}, {prec}, 64 bitstrings")
+        a, pl = _run(ps, c, bits, prec)
+        assert pl.stats()["sweep"] == 2   # columns: boundary of 4 legs
+        _, erms = _errors(a, ref, 20)
+        worst = max(worst, np.max(erms))
+    say(f"4x5 worst eps_rms {worst:.3e}")
+    assert worst <= (1e-10 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_5x5_batch_256(ps, prec):
+    g, bits, ref = _golden("rqc_5x5_d32_s0.json")
+    c = rqcgen.generate(5, 5, 32, 0)
+    say(f"5x5 d32, 256 bitstrings in one call, {prec}")
+    a, _ = _run(ps, c, bits, prec, mem_budget=48 << 30)
+    erel, erms = _errors(a, ref, 25)
+    say(f"5x5 {prec}: max eps_rms {np.max(erms):.3e}, max eps_rel {np.max(erel):.3e}, median eps_rel {np.median(erel):.3e}")
+    assert np.max(erms) <= (1e-10 if prec == "fp64" else 1e-5)
+
+
+def test_general_gates_and_degenerate_lattices(ps):
+    cases = [rqcgen.generate_general(3, 3, 4, 2, "U2"), rqcgen.generate_general(2, 4, 3, 3, "U2"),
+             rqcgen.generate(1, 5, 8, 1), rqcgen.generate(4, 1, 8, 2), rqcgen.generate(1, 1, 3, 0),
+             rqcgen.generate(3, 4, 0, 0), rqcgen.generate(3, 4, 13, 5)]
+    for c in cases:
+        n = c.lv * c.lh
+        bits = rqcgen.all_bitstrings(n) if n <= 10 else rqcgen.bitstrings(c.lv, c.lh, 0, 64)
+        ref = sv.amplitudes(sv.run(c), bits)
+        for prec in ("fp64", "fp32"):
+            say(f"{c.family} {c.lv}x{c.lh} d{c.depth} {prec}")
+            a, _ = _run(ps, c, bits, prec)
+            _, erms = _errors(a, ref, n)
+            assert np.max(erms) <= (1e-10 if prec == "fp64" else 1e-5), (c.lv, c.lh, c.family, prec)
+
+
+def test_shared_prefix_batch_matches_single(ps):
+    c = rqcgen.generate(4, 4, 16, 3)
+    base = rqcgen.bitstrings(4, 4, 3, 1)[0]
+    var = rqcgen.last_row_variants(base, 4, 4, [0, 1, 2, 3])
+    ref = sv.amplitudes(sv.run(c), var)
+    P = ps.Peps(c)
+    pl = ps.Plan(P, prec="fp64", max_batch=16)
+    a = pl.amplitudes(var)
+    single = np.array([pl.amplitudes(v[None])[0] for v in var[:4]])
+    assert np.max(np.abs(a - ref)) * 2 ** 8 <= 1e-10
+    assert np.array_equal(a[:4], single)   # same arithmetic whether batched or not
+
+
+def test_deterministic(ps):
+    c = rqcgen.generate(5, 5, 16, 1)
+    bits = rqcgen.bitstrings(5, 5, 1, 8)
+    a1, pl = _run(ps, c, bits, "fp32")
+    a2 = pl.amplitudes(bits)
+    assert np.array_equal(a1, a2)
+
+
+def test_errors(ps):
+    import ctypes
+    c = rqcgen.generate(3, 3, 8, 0)
+    pl = ps.Plan(ps.Peps(c), prec="fp32")
+    bad = np.zeros((1, 9), dtype=np.uint8)
+    bad[0, 3] = 2
+    with pytest.raises(ps.PsimError) as e:
+        pl.amplitudes(bad)
+    assert e.value.status == ps.PSIM_EINVAL
+    ws = pl.workspace()
+    out = (ctypes.c_double * 2)()
+    bits = (ctypes.c_uint8 * 9)()
+    st = ps.lib().psim_amplitudes(pl._h, bits, 1, ctypes.c_void_p(ws.data_ptr()), 16, None, out)
+    assert st == ps.PSIM_EINVAL and b"workspace" in ps.lib().psim_last_error()

@@ -1,0 +1,114 @@
+"""Host-side checks of libpsim: exported symbols, the builder's structure and
+the planner's exact work count, against the oracle's independent count."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import rqcgen
+from oracle import complexity as cx
+from oracle import peps as opeps
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def ps():
+    import paper_1905_08394_amd as ps
+    return ps
+
+
+def test_library_exports_every_declared_symbol(ps):
+    with open(os.path.join(ROOT, "include", "psim.h")) as f:
+        header = f.read()
+    declared = set(re.findall(r"^\s*(?:psim_status|void|const char \*)\s*(psim_\w+)\s*\(", header, re.M))
+    assert declared >= {"psim_build", "psim_plan", "psim_amplitudes", "psim_contract_site"}
+    L = ctypes.CDLL(ps.LIB_PATH)
+    for name in declared:
+        assert hasattr(L, name), name
+    assert set(ps.EXPORTED) == declared
+    assert "gfx950" in ps.version()
+
+
+@pytest.mark.parametrize("lv,lh,d,seed", [(3, 3, 8, 0), (4, 5, 24, 1), (5, 5, 32, 0), (3, 4, 13, 2)])
+def test_builder_bond_dims_match_oracle(ps, lv, lh, d, seed):
+    c = rqcgen.generate(lv, lh, d, seed)
+    info = ps.Peps(c).info()
+    od = opeps.bond_dims(opeps.build(c))
+    want = [od[("h", r, col)] for r in range(lv) for col in range(lh - 1)] + \
+           [od[("v", r, col)] for r in range(lv - 1) for col in range(lh)]
+    assert info["bond_dims"] == want
+    assert info["chi"] == max(want)
+    if d % 8 == 0:
+        assert info["chi"] == cx.chi_bound(d)
+
+
+def test_builder_general_gates(ps):
+    c = rqcgen.generate_general(3, 3, 3, 4, "U2")
+    info = ps.Peps(c).info()
+    od = opeps.bond_dims(opeps.build(c))
+    assert sorted(info["bond_dims"]) == sorted(od.values())
+    assert info["chi"] > 2  # generic 2q gates have operator-Schmidt rank 4
+
+
+def test_builder_errors(ps):
+    bad = rqcgen.Circuit(3, 3, 1, 0, [rqcgen.Gate(0, "CZ", 0, 4)])   # diagonal pair
+    with pytest.raises(ps.PsimError) as e:
+        ps.Peps(bad)
+    assert e.value.status == ps.PSIM_EINVAL and "neighbour" in str(e.value)
+    with pytest.raises(ps.PsimError):
+        ps.Peps(rqcgen.Circuit(2, 2, 1, 0, [rqcgen.Gate(0, "H", 9)]))
+    with pytest.raises(ps.PsimError):
+        ps.Peps(rqcgen.Circuit(2, 2, 1, 0, [rqcgen.Gate(0, "U1", 0)]))   # no matrix
+    with pytest.raises(ps.PsimError):
+        ps.Peps(rqcgen.Circuit(2, 2, 1, 0, [rqcgen.Gate(2, "H", 0), rqcgen.Gate(1, "H", 1)]))
+
+
+@pytest.mark.parametrize("lv,lh,d", [(3, 3, 8), (4, 5, 24), (5, 4, 24), (5, 5, 32), (6, 6, 40), (7, 7, 40), (3, 4, 13)])
+def test_planner_exact_cmac_matches_oracle_count(ps, lv, lh, d):
+    c = rqcgen.generate(lv, lh, d, 0)
+    P = ps.Peps(c)
+    try:
+        s = ps.Plan(P, prec="fp32", host_only=True, mem_budget=1 << 62).stats()
+    except ps.PsimError:
+        pytest.fail("planning failed")
+    dims = opeps.bond_dims(opeps.build(c))
+    scheme = "rows" if lh <= lv else "cols"
+    assert s["cmac_per_amplitude"] == cx.row_scheme_cmac(lv, lh, dims, scheme)
+    assert s["L"] == min(lv, lh)
+    assert s["sweep"] == (1 if lh <= lv else 2)
+    if d % 8 == 0 and min(lv, lh) > 2:
+        assert s["cmac_per_amplitude"] >= cx.generic_time(lv, lh, d)
+
+
+def test_planner_memory_budget(ps):
+    P = ps.Peps(rqcgen.generate(6, 6, 40, 0))
+    with pytest.raises(ps.PsimError) as e:
+        ps.Plan(P, prec="fp32", host_only=True, mem_budget=1 << 30)
+    assert e.value.status == ps.PSIM_ENOMEM and "bytes" in str(e.value)
+    s = ps.Plan(P, prec="fp32", host_only=True, mem_budget=64 << 30, max_batch=16).stats()
+    assert s["workspace_bytes"] <= 64 << 30
+    # boundary 32^6 complex64 is 8 GiB; the unsliced peak tensor would be 32^7
+    assert s["peak_tensor_elems"] == 32 ** 7
+    with pytest.raises(ps.PsimError) as e:
+        ps.Plan(ps.Peps(rqcgen.generate(7, 7, 40, 0)), prec="fp32", host_only=True)
+    assert e.value.status == ps.PSIM_ENOMEM
+
+
+def test_planner_unsupported_precision(ps):
+    P = ps.Peps(rqcgen.generate(3, 3, 8, 0))
+    with pytest.raises(ps.PsimError) as e:
+        ps.Plan(P, prec="bf16x3", host_only=True)
+    assert e.value.status == ps.PSIM_EUNSUPPORTED
+
+
+def test_host_only_plan_cannot_run(ps):
+    P = ps.Peps(rqcgen.generate(3, 3, 8, 0))
+    pl = ps.Plan(P, prec="fp32", host_only=True)
+    L = ps.lib()
+    out = (ctypes.c_double * 2)()
+    bits = (ctypes.c_uint8 * 9)()
+    st = L.psim_amplitudes(pl._h, bits, 1, ctypes.c_void_p(16), 1 << 20, None, out)
+    assert st == ps.PSIM_EINVAL
