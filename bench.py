@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark: exact amplitudes of a 6x6 (1+40+1) random circuit on one MI355X.
+
+One step = one psim_amplitudes call on a batch of 16 bitstrings that share
+rows 1-5 and differ in the last row (the whole hot path: every row of the
+row scheme, every site contraction, rescaling, final assembly).  The value
+is seconds per amplitude; the line also carries the contraction TFLOP/s
+(8 real flops per complex multiply-add of the exact row-scheme count), the
+hot kernel's roofline (interior-site contraction, eq. S4, timed with HIP
+events on its launch stream), and the CPU oracle timed on a bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--prec fp32|fp64] [--compare-fp64]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "seconds/amplitude + contraction TFLOP/s (% MFMA peak), 6x6 d40, FP32-MFMA vs FP64"
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}   # MI355X dense MFMA, FP32 / FP64
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_interior_site_6x6_d40_fp32.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    with open(os.path.join(ROOT, "paper_1905_08394_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def workload(lattice, depth, seed=0):
+    import rqcgen
+    c = rqcgen.generate(lattice, lattice, depth, seed)
+    base = rqcgen.bitstrings(lattice, lattice, seed, 1)[0]
+    cols = list(range(lattice - 4, lattice))
+    return c, rqcgen.last_row_variants(base, lattice, lattice, cols)
+
+
+def run_gpu(args, prec, circuit, bits):
+    import torch
+    import paper_1905_08394_amd as ps
+    peps = ps.Peps(circuit)
+    plan = ps.Plan(peps, prec=prec, mem_budget=args.mem_gib << 30, max_batch=len(bits))
+    peps.close()
+    stats = plan.stats()
+    plan.workspace()                               # allocate before timing
+    stream = torch.cuda.current_stream()
+    # prime the code objects with a tiny circuit (not a step)
+    import rqcgen
+    small = ps.Plan(ps.Peps(rqcgen.generate(3, 3, 8, 0)), prec=prec)
+    small.amplitudes(rqcgen.bitstrings(3, 3, 0, 1))
+    small.close()
+    for w in range(args.warmup):
+        log(f"warmup {w + 1}/{args.warmup} ({prec})")
+        plan.amplitudes(bits)
+    plan.profile_start()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        amps = plan.amplitudes(bits, stream=stream.cuda_stream)
+        log(f"step {k + 1}/{args.steps} ({prec}) done at {time.perf_counter() - t0:.2f}s")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = plan.profile_read()
+    plan.profile_stop()
+    plan.close()
+    return amps, elapsed, prof, stats
+
+
+def golden_errors(bits, amps, lattice, depth):
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", f"rqc_{lattice}x{lattice}_d{depth}_s0.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        g = json.load(f)
+    gb = np.array(g["bits"], dtype=np.uint8)
+    ref = np.array(g["amps_re"]) + 1j * np.array(g["amps_im"])
+    idx = [int(np.where((gb == b).all(axis=1))[0][0]) for b in bits]
+    r = ref[idx]
+    d = np.abs(amps - r)
+    n = lattice * lattice
+    return {"max_eps_rel": float(np.max(d / np.abs(r))), "median_eps_rel": float(np.median(d / np.abs(r))),
+            "max_eps_rms": float(np.max(d) * 2 ** (n / 2)), "n": int(len(r))}
+
+
+def cpu_baseline(circuit, bits, target_seconds):
+    """The oracle's row scheme (numpy FP64) on (v, w) slices of one interior row."""
+    import numpy as np
+    from oracle import complexity as cx
+    from oracle import peps as op
+    L = circuit.lh
+    P = op.build(circuit)
+    dims = op.bond_dims(P)
+    D = dims[("v", 1, 0)]
+    sites = op.projected_sites(P, bits[0])
+    rng = np.random.default_rng(0)
+    labels = [("v", 1, c) for c in range(L - 1)]   # boundary after row 1, last leg fixed (v)
+    shape = [dims[x] for x in labels]
+    Fv = op.LT(rng.standard_normal(shape) + 1j * rng.standard_normal(shape), labels)
+    row = 2
+    # one (v, w) task: v = last input leg, w = first output leg; 1/D^2 of the row's work
+    t0 = time.perf_counter()
+    tasks = 0
+    while True:
+        op.row_transfer(Fv, sites, row, L, fixed={("v", 1, L - 1): tasks % D, ("v", 2, 0): tasks % D})
+        tasks += 1
+        if time.perf_counter() - t0 >= target_seconds:
+            break
+    t = time.perf_counter() - t0
+    per_row = cx.row_scheme_cmac_per_row(L, L, dims)
+    task_cmac = per_row[row] / (D * D)
+    # batch: rows 0..L-2 once, the last row once per bitstring
+    batch_cmac = sum(per_row[:-1]) + len(bits) * per_row[-1]
+    s_per_amp = t / tasks * batch_cmac / task_cmac / len(bits)
+    threads = int(os.environ.get("OPENBLAS_NUM_THREADS", os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    return {"value": s_per_amp, "unit": "s/amplitude", "cores": min(threads, os.cpu_count() or 1),
+            "kind": "oracle",
+            "sample": f"{tasks} (v,w) slice(s) of one interior row of the 6x6 (1+40+1) row scheme "
+                      f"(oracle.peps.row_transfer, numpy complex128, {t:.1f} s), extrapolated by exact "
+                      f"multiply-add counts to the 16-bitstring batch ({batch_cmac:.3e} CMAC)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--lattice", type=int, default=6)
+    ap.add_argument("--depth", type=int, default=40)
+    ap.add_argument("--mem-gib", type=int, default=0, help="workspace budget (0: 96 GiB fp32, 128 GiB fp64)")
+    ap.add_argument("--compare-fp64", action="store_true", help="also time the FP64 path on the same batch")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1).",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.mem_gib == 0:
+        args.mem_gib = 96 if args.prec == "fp32" else 128
+
+    import torch
+    torch.cuda.set_device(0)
+    circuit, bits = workload(args.lattice, args.depth)
+    log(f"workload {args.lattice}x{args.lattice} (1+{args.depth}+1), {len(bits)} bitstrings, {args.prec}")
+    amps, elapsed, prof, stats = run_gpu(args, args.prec, circuit, bits)
+    n_amp = args.steps * len(bits)
+    cmac = sum(v["cmac"] for v in prof.values())
+    tflops = 8 * cmac / elapsed / 1e12
+    hot = prof["interior_site"]
+    hot_tflops = 8 * hot["cmac"] / (hot["ms"] / 1e3) / 1e12 if hot["ms"] > 0 else None
+    peak = PEAK_TFLOPS[args.prec]
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE) and args.prec == "fp32" and args.lattice == 6:
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_source_sha256") == kernel_source_hash():
+            traffic = tr.get("bytes_per_launch")
+    per_launch_cmac = hot["cmac"] / max(hot["launches"], 1)
+    out = {
+        "metric": METRIC,
+        "value": elapsed / n_amp,
+        "unit": "s/amplitude",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.prec == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.lattice}x{args.lattice} lattice, random circuit depth (1+{args.depth}+1), "
+                               f"D={stats['chi']}, exact row-scheme amplitudes of {len(bits)} bitstrings "
+                               f"sharing rows 1-{args.lattice - 1} (last-row variants)",
+                   "precision": "complex64 storage, FP32 MFMA (4M)" if args.prec == "fp32" else
+                                "complex128 storage, FP64 MFMA",
+                   "bitstrings_per_step": len(bits), "seed": 0, "v_chunk": stats["v_chunk"],
+                   "workspace_gib": round(stats["workspace_bytes"] / 2 ** 30, 2)},
+        "contraction_tflops": tflops,
+        "pct_mfma_peak": tflops / peak,
+        "s_per_single_amplitude": elapsed / args.steps,
+        "kernel_ms": {k: round(v["ms"], 3) for k, v in prof.items()},
+        "roofline": {
+            "bound": "mfma", "achieved": hot_tflops, "peak": peak, "unit": "TFLOP/s",
+            "frac": (hot_tflops / peak) if hot_tflops else None, "traffic": traffic,
+            "kernel": "site_gemm (interior site, eq. S4)",
+            "flops_per_launch": 8 * per_launch_cmac, "launches": hot["launches"],
+            "avg_launch_ms": hot["ms"] / max(hot["launches"], 1),
+        },
+    }
+    err = golden_errors(bits, amps, args.lattice, args.depth)
+    if err:
+        out["vs_oracle"] = err
+    if args.compare_fp64 and args.prec == "fp32":
+        a64 = argparse.Namespace(**vars(args))
+        a64.mem_gib = 128
+        amps64, el64, prof64, _ = run_gpu(a64, "fp64", circuit, bits)
+        h64 = prof64["interior_site"]
+        out["fp64"] = {"s_per_amplitude": el64 / n_amp, "speedup_fp32_over_fp64": el64 / elapsed,
+                       "contraction_tflops": 8 * sum(v["cmac"] for v in prof64.values()) / el64 / 1e12,
+                       "hot_kernel_tflops": 8 * h64["cmac"] / (h64["ms"] / 1e3) / 1e12,
+                       "pct_fp64_mfma_peak": 8 * sum(v["cmac"] for v in prof64.values()) / el64 / 1e12 / 78.6}
+        e64 = golden_errors(bits, amps64, args.lattice, args.depth)
+        if e64:
+            out["fp64"]["vs_oracle"] = e64
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(circuit, bits, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -150,6 +150,22 @@ psim_status psim_contract_site(int32_t prec, int64_t batch, int64_t M, int64_t K
                                const void *d_A, int64_t a_batch_stride, const double *W,
                                void *d_C, int32_t transpose_out, void *hip_stream);
 
+/* Per-kernel-class timing of psim_amplitudes, measured with HIP events
+ * recorded on the caller's stream around every launch (adds two event
+ * records per launch while enabled).  Classes: 0 = first site of a row
+ * (K-major A), 1 = interior sites (eq. S4, the hot step), 2 = last site of a
+ * row (v summed, transposed store), 3 = per-row rescale.  op = 1 resets and
+ * enables, op = 2 reads the accumulated totals into out[4] (nullable for
+ * op 1/0), op = 0 disables.  cmac is the algorithmic complex multiply-add
+ * count of the timed launches. */
+typedef struct {
+  double ms;          /* summed kernel time */
+  int64_t launches;
+  double cmac;
+} psim_kernel_stats;
+
+psim_status psim_profile(psim_plan_t *plan, int32_t op, psim_kernel_stats *out);
+
 /* Message for the last failing call on this thread; valid until the next
  * psim_* call on the same thread.  Never NULL. */
 const char *psim_last_error(void);

@@ -99,6 +99,42 @@ def row_scheme_cmac(lv: int, lh: int, dims: Dict[Tuple[str, int, int], int],
     return total
 
 
+def row_scheme_cmac_per_row(lv: int, lh: int, dims: Dict[Tuple[str, int, int], int]):
+    """Exact CMAC of the row scheme (top-down, left to right) split by row."""
+    out = []
+    for r in range(lv):
+        out.append(_count_prefix(lv, lh, dims, r + 1) - (_count_prefix(lv, lh, dims, r) if r else 0))
+    return out
+
+
+def _count_prefix(lv, lh, dims, n_rows):
+    from .peps import site_order
+    order = [p for p in site_order(lv, lh, "rows") if p[0] < n_rows]
+    acc = None
+    total = 0
+    for (r, c) in order:
+        s = {}
+        if c > 0:
+            s[("h", r, c - 1)] = dims[("h", r, c - 1)]
+        if c + 1 < lh:
+            s[("h", r, c)] = dims[("h", r, c)]
+        if r > 0:
+            s[("v", r - 1, c)] = dims[("v", r - 1, c)]
+        if r + 1 < lv:
+            s[("v", r, c)] = dims[("v", r, c)]
+        if acc is None:
+            acc = dict(s)
+            continue
+        shared = [k for k in s if k in acc]
+        total += math.prod(acc.values()) * math.prod(v for k, v in s.items() if k not in shared)
+        for k in shared:
+            del acc[k]
+        for k, v in s.items():
+            if k not in shared:
+                acc[k] = v
+    return total
+
+
 def uniform_dims(lv: int, lh: int, D: int) -> Dict[Tuple[str, int, int], int]:
     out = {}
     for r in range(lv):

@@ -22,7 +22,8 @@ KIND = {"H": 0, "T": 1, "SX": 2, "SY": 3, "CZ": 4, "U1": 5, "U2": 6}
 PREC = {"fp64": 0, "fp32": 1, "fp32_4m": 1, "fp32_3m": 2, "bf16x3": 3}
 PLAN_HOST_ONLY = 1
 EXPORTED = ("psim_build", "psim_peps_info", "psim_peps_free", "psim_plan", "psim_plan_info", "psim_plan_free",
-            "psim_amplitudes", "psim_contract_site", "psim_last_error", "psim_version")
+            "psim_amplitudes", "psim_contract_site", "psim_profile", "psim_last_error", "psim_version")
+KERNEL_CLASSES = ("first_site", "interior_site", "last_site", "rescale")
 
 
 class PsimError(RuntimeError):
@@ -53,6 +54,10 @@ class PlanStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class KernelStats(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double), ("launches", ctypes.c_int64), ("cmac", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -80,10 +85,11 @@ def lib(need_torch: bool = True) -> ctypes.CDLL:
     L.psim_amplitudes.argtypes = [vp, ctypes.POINTER(ctypes.c_uint8), sz, vp, sz, vp, ctypes.POINTER(ctypes.c_double)]
     L.psim_contract_site.argtypes = [i32, i64, i64, i64, i64, i64, vp, i64, ctypes.POINTER(ctypes.c_double), vp,
                                      i32, vp]
+    L.psim_profile.argtypes = [vp, i32, ctypes.POINTER(KernelStats)]
     L.psim_last_error.restype = ctypes.c_char_p
     L.psim_version.restype = ctypes.c_char_p
     for f in ("psim_build", "psim_peps_info", "psim_plan", "psim_plan_info", "psim_amplitudes",
-              "psim_contract_site"):
+              "psim_contract_site", "psim_profile"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -183,6 +189,18 @@ class Plan:
                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(st),
                                      out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out[0::2] + 1j * out[1::2]
+
+    def profile_start(self):
+        _check(lib().psim_profile(self._h, 1, None))
+
+    def profile_read(self) -> dict:
+        out = (KernelStats * 4)()
+        _check(lib().psim_profile(self._h, 2, out))
+        return {name: {"ms": out[i].ms, "launches": out[i].launches, "cmac": out[i].cmac}
+                for i, name in enumerate(KERNEL_CLASSES)}
+
+    def profile_stop(self):
+        _check(lib().psim_profile(self._h, 0, None))
 
     def close(self):
         if getattr(self, "_h", None):

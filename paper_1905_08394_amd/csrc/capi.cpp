@@ -164,6 +164,23 @@ psim_status psim_contract_site(int32_t prec, int64_t batch, int64_t M, int64_t K
   });
 }
 
+psim_status psim_profile(psim_plan_t* pl, int32_t op, psim_kernel_stats* out) {
+  return guarded([&] {
+    if (!pl) fail(PSIM_EINVAL, "plan is NULL");
+    if (op == 1) {
+      pl->profile = true;
+      for (auto& k : pl->prof) k = psim_kernel_stats{};
+    } else if (op == 2) {
+      if (!out) fail(PSIM_EINVAL, "out is NULL");
+      for (int i = 0; i < 4; ++i) out[i] = pl->prof[i];
+    } else if (op == 0) {
+      pl->profile = false;
+    } else {
+      fail(PSIM_EINVAL, "op must be 0, 1 or 2");
+    }
+  });
+}
+
 const char* psim_last_error(void) { return g_last_error.c_str(); }
 
 const char* psim_version(void) { return "psim 0.1 (gfx950)"; }

@@ -11,7 +11,10 @@
 // component, and the exponents are carried along the trie; the amplitude is
 // mantissa * 2^(row exponents + site-matrix exponents), assembled in FP64.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <unordered_map>
@@ -175,6 +178,32 @@ void run_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, si
   const int32_t zero = 0;
   hip_check(hipMemcpyAsync(d_exp[1], &zero, 4, hipMemcpyHostToDevice, st), "upload exponent");
 
+  // ------------------------------------------------------------ event timing (optional)
+  struct Timed {
+    hipEvent_t a, b;
+    int cls;
+    double cmac;
+  };
+  std::vector<Timed> timed;
+  auto tstart = [&](int cls, double cmac) {
+    if (!pl->profile) return;
+    Timed t{};
+    t.cls = cls;
+    t.cmac = cmac;
+    hip_check(hipEventCreate(&t.a), "hipEventCreate");
+    hip_check(hipEventCreate(&t.b), "hipEventCreate");
+    hip_check(hipEventRecord(t.a, st), "hipEventRecord");
+    timed.push_back(t);
+  };
+  auto tstop = [&]() {
+    if (!pl->profile) return;
+    hip_check(hipEventRecord(timed.back().b, st), "hipEventRecord");
+  };
+
+  const char* env_log = std::getenv("PSIM_LOG");
+  const bool log_rows = env_log && env_log[0] == '1';
+  const auto t_begin = std::chrono::steady_clock::now();
+
   // ------------------------------------------------------------ rows
   for (int i = 0; i < R; ++i) {
     const Level& lev = pl->levels[i];
@@ -236,13 +265,23 @@ void run_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, si
               g.sA_node = (int64_t)c * g.sA_v;
             }
           }
+          tstart(s.kind, (double)g.nodes * g.Bz * g.M * g.K1 * g.K2 * g.N);
           launch_site_gemm(g, st);
+          tstop();
         }
         if (L == 1) break;  // the single site consumed every v at once
       }
     }
     // exact power-of-two rescale of every node's boundary; exponents along the trie
+    tstart(3, 0.0);
     launch_rowscale(prec, Fcur, lev.F_elems, nodes, d_parent[i], d_exp[(i + 1) % 2], d_exp[i % 2], d_max, st);
+    tstop();
+    if (log_rows) {  // progress for long runs: wait for the row, then report it
+      hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+      std::fprintf(stderr, "psim: row %d/%d done (%lld nodes) at %.2f s\n", i + 1, R, (long long)nodes,
+                   std::chrono::duration<double>(std::chrono::steady_clock::now() - t_begin).count());
+      std::fflush(stderr);
+    }
   }
 
   // ------------------------------------------------------------ results
@@ -252,6 +291,15 @@ void run_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, si
   hip_check(hipMemcpyAsync(vals.data(), dF[(R - 1) % 2], vals.size(), hipMemcpyDeviceToHost, st), "download");
   hip_check(hipMemcpyAsync(ex.data(), d_exp[(R - 1) % 2], ex.size() * 4, hipMemcpyDeviceToHost, st), "download");
   hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+  for (Timed& t : timed) {
+    float ms = 0;
+    hip_check(hipEventElapsedTime(&ms, t.a, t.b), "hipEventElapsedTime");
+    pl->prof[t.cls].ms += ms;
+    pl->prof[t.cls].launches += 1;
+    pl->prof[t.cls].cmac += t.cmac;
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
   for (size_t b = 0; b < n; ++b) {
     const int32_t leaf = t.leaf[b];
     double re, im;

@@ -101,6 +101,8 @@ struct psim_plan_s {
   int elem_bytes = 8;
   void* d_ones = nullptr;                // device scalar 1 (the empty boundary before row 0)
   bool in_subbatch = false;              // scheduler re-entry guard
+  bool profile = false;                  // time launches with events
+  psim_kernel_stats prof[4] = {};
 };
 
 namespace psim {
