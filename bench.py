@@ -128,6 +128,32 @@ def cpu_baseline(circuit, bits, target_seconds):
                       f"multiply-add counts to the 16-bitstring batch ({batch_cmac:.3e} CMAC)"}
 
 
+def counters_program(reps=3):
+    """Short program for rocprofv3 --pmc passes: a plain 4 GiB device copy (to
+    calibrate FETCH_SIZE / WRITE_SIZE) and the interior-site contraction at the
+    launch shape the 6x6 (1+40+1) bench runs (two v values of M = 32^4,
+    K = N = 32^2 complex64)."""
+    import numpy as np
+    import torch
+    import paper_1905_08394_amd as ps
+    n = 1 << 30                                   # 4 GiB of float32
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    M, K1, K2, N, batch = 32 ** 4, 32, 32, 1024, 2
+    A = torch.randn(batch * K1 * M * K2, dtype=torch.complex64, device="cuda")
+    rng = np.random.default_rng(0)
+    W = rng.standard_normal((K1 * K2, N)) + 1j * rng.standard_normal((K1 * K2, N))
+    for r in range(reps):
+        ps.contract_site("fp32", A, W, M, K1, K2, N, batch=batch)
+        log(f"hot step {r + 1}/{reps}")
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": 4 * n, "hot_step_algorithmic_bytes":
+                      2 * batch * K1 * M * K2 * 8 + K1 * K2 * N * 4 * 4, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,7 +166,11 @@ def main():
     ap.add_argument("--compare-fp64", action="store_true", help="also time the FP64 path on the same batch")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--counters", action="store_true", help="short program for rocprofv3 --pmc passes")
     args = ap.parse_args()
+    if args.counters:
+        counters_program()
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1).",

@@ -104,7 +104,7 @@ template <>
 struct V16<double> { typedef f64x2 t; static constexpr int n = 2; };
 
 // ---------------------------------------------------------------- kernel
-template <typename T, int BM, int BN, int BK, int AMODE>
+template <typename T, int BM, int BN, int BK, int AMODE, bool TRANS>
 __global__ __launch_bounds__(256) void site_gemm(KArgs p) {
   typedef Mfma<T> MF;
   typedef typename V16<T>::t vec_t;
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(256) void site_gemm(KArgs p) {
         const long long col = n0 + wc * WN + bj * MF::MB + MF::out_col(lane);
         if (row < p.M && col < p.Nr) {
           const T v = acc[bi][bj][r];
-          if (!p.trans_out) {
+          if constexpr (!TRANS) {
             C[row * p.Nr + col] = v;
           } else {
             T* dst = C + 2 * ((col >> 1) * p.M + row) + (col & 1);
@@ -379,6 +379,11 @@ void hip_check(int err, const char* what) {
     fail(PSIM_EDEVICE, std::string(what) + ": " + hipGetErrorString((hipError_t)err));
 }
 
+template <typename T, int BM, int BN, int BK, int AMODE, bool TRANS>
+static void launch(const KArgs& a, long long blocks, hipStream_t st) {
+  hipLaunchKernelGGL((site_gemm<T, BM, BN, BK, AMODE, TRANS>), dim3((unsigned)blocks), dim3(256), 0, st, a);
+}
+
 void launch_site_gemm(const GemmLaunch& g, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   if (g.M < 1 || g.K1 < 1 || g.K2 < 1 || g.N < 1 || g.nodes < 1 || g.Bz < 1)
@@ -412,21 +417,21 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
   // batch entries = nodes * Bz; the kernel splits z = node * Bz + v
   const long long Z = g.nodes * g.Bz;
   if (g.prec == PSIM_FP64) {
-    if (g.K2 == 1 && g.K1 > 1) {
-      KArgs b = a;
-      b.MT = (b.M + 64 - 1) / 64;
-      b.NT = (b.Nr + 64 - 1) / 64;
-      b.T = b.MT * b.NT * Z;
-      const long long blocks = (b.T + 7) / 8 * 8;
-      hipLaunchKernelGGL((site_gemm<double, 64, 64, 16, KMAJOR>), dim3((unsigned)blocks), dim3(256), 0, st, b);
-    } else {
-      KArgs b = a;
-      b.MT = (b.M + 64 - 1) / 64;
-      b.NT = (b.Nr + 64 - 1) / 64;
-      b.T = b.MT * b.NT * Z;
-      const long long blocks = (b.T + 7) / 8 * 8;
-      hipLaunchKernelGGL((site_gemm<double, 64, 64, 16, GENERIC>), dim3((unsigned)blocks), dim3(256), 0, st, b);
-    }
+    KArgs b = a;
+    b.MT = (b.M + 64 - 1) / 64;
+    b.NT = (b.Nr + 64 - 1) / 64;
+    b.T = b.MT * b.NT * Z;
+    const long long blocks = (b.T + 7) / 8 * 8;
+    if (blocks > 0x7fffffffLL) fail(PSIM_EUNSUPPORTED, "grid too large");
+    const bool kmajor = g.K2 == 1 && g.K1 > 1;
+    if (kmajor && g.trans_out)
+      launch<double, 64, 64, 16, KMAJOR, true>(b, blocks, st);
+    else if (kmajor)
+      launch<double, 64, 64, 16, KMAJOR, false>(b, blocks, st);
+    else if (g.trans_out)
+      launch<double, 64, 64, 16, GENERIC, true>(b, blocks, st);
+    else
+      launch<double, 64, 64, 16, GENERIC, false>(b, blocks, st);
   } else {
     KArgs b = a;
     b.MT = (b.M + 128 - 1) / 128;
@@ -436,12 +441,17 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
     if (blocks > 0x7fffffffLL) fail(PSIM_EUNSUPPORTED, "grid too large");
     // 16-byte vector loads need every batch entry's A to start 16-byte aligned
     const bool even_base = ((uintptr_t)g.A % 16 == 0) && (g.sA_node % 2 == 0) && (g.sA_v % 2 == 0);
-    if (g.K2 % 2 == 0 && even_base)
-      hipLaunchKernelGGL((site_gemm<float, 128, 128, 32, ROWMAJOR>), dim3((unsigned)blocks), dim3(256), 0, st, b);
-    else if (g.K2 == 1 && g.M % 2 == 0 && g.K1 > 1 && even_base)
-      hipLaunchKernelGGL((site_gemm<float, 128, 128, 32, KMAJOR>), dim3((unsigned)blocks), dim3(256), 0, st, b);
+    const int mode = (g.K2 % 2 == 0 && even_base) ? ROWMAJOR
+                     : (g.K2 == 1 && g.M % 2 == 0 && g.K1 > 1 && even_base) ? KMAJOR : GENERIC;
+    if (mode == ROWMAJOR)
+      g.trans_out ? launch<float, 128, 128, 32, ROWMAJOR, true>(b, blocks, st)
+                  : launch<float, 128, 128, 32, ROWMAJOR, false>(b, blocks, st);
+    else if (mode == KMAJOR)
+      g.trans_out ? launch<float, 128, 128, 32, KMAJOR, true>(b, blocks, st)
+                  : launch<float, 128, 128, 32, KMAJOR, false>(b, blocks, st);
     else
-      hipLaunchKernelGGL((site_gemm<float, 128, 128, 32, GENERIC>), dim3((unsigned)blocks), dim3(256), 0, st, b);
+      g.trans_out ? launch<float, 128, 128, 32, GENERIC, true>(b, blocks, st)
+                  : launch<float, 128, 128, 32, GENERIC, false>(b, blocks, st);
   }
   hip_check(hipGetLastError(), "site_gemm launch");
 }
