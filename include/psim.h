@@ -92,6 +92,7 @@ typedef struct {
   int32_t v_chunk;            /* v-slices processed together in interior rows */
   int32_t sweep;              /* 1 = rows, 2 = columns */
   int32_t prec;
+  int32_t hot_cfg;            /* tile candidate used by the costliest site contraction (0 = default) */
 } psim_plan_stats;
 
 typedef struct psim_peps_s psim_peps_t;
@@ -149,6 +150,17 @@ psim_status psim_amplitudes(psim_plan_t *plan, const uint8_t *bits, size_t n_bit
 psim_status psim_contract_site(int32_t prec, int64_t batch, int64_t M, int64_t K1, int64_t K2, int64_t N,
                                const void *d_A, int64_t a_batch_stride, const double *W,
                                void *d_C, int32_t transpose_out, void *hip_stream);
+
+/* Autotuner: for every distinct interior-site contraction shape of the plan
+ * (eq. S4 steps), time each tile candidate of the FP32 row-major kernel
+ * (reps launches each, HIP events on hip_stream) on scratch data inside the
+ * caller's workspace (>= psim_plan_stats.workspace_bytes, contents are
+ * overwritten), and keep the fastest for psim_amplitudes.  best_ms
+ * (nullable) receives the chosen time of the costliest shape.  Plans in other
+ * precisions keep their single kernel configuration (PSIM_OK, nothing timed).
+ * Errors: EINVAL for a short workspace or reps < 1, EDEVICE. */
+psim_status psim_tune(psim_plan_t *plan, void *d_workspace, size_t workspace_bytes, void *hip_stream,
+                      int32_t reps, double *best_ms);
 
 /* Per-kernel-class timing of psim_amplitudes, measured with HIP events
  * recorded on the caller's stream around every launch (adds two event

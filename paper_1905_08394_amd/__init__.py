@@ -22,7 +22,8 @@ KIND = {"H": 0, "T": 1, "SX": 2, "SY": 3, "CZ": 4, "U1": 5, "U2": 6}
 PREC = {"fp64": 0, "fp32": 1, "fp32_4m": 1, "fp32_3m": 2, "bf16x3": 3}
 PLAN_HOST_ONLY = 1
 EXPORTED = ("psim_build", "psim_peps_info", "psim_peps_free", "psim_plan", "psim_plan_info", "psim_plan_free",
-            "psim_amplitudes", "psim_contract_site", "psim_profile", "psim_last_error", "psim_version")
+            "psim_amplitudes", "psim_contract_site", "psim_tune", "psim_profile", "psim_last_error",
+            "psim_version")
 KERNEL_CLASSES = ("first_site", "interior_site", "last_site", "rescale")
 
 
@@ -48,7 +49,7 @@ class PlanStats(ctypes.Structure):
                 ("peak_tensor_elems", ctypes.c_uint64), ("cmac_per_amplitude", ctypes.c_double),
                 ("n_gemm_steps", ctypes.c_int64), ("L", ctypes.c_int32), ("R", ctypes.c_int32),
                 ("chi", ctypes.c_int32), ("v_chunk", ctypes.c_int32), ("sweep", ctypes.c_int32),
-                ("prec", ctypes.c_int32)]
+                ("prec", ctypes.c_int32), ("hot_cfg", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -86,10 +87,11 @@ def lib(need_torch: bool = True) -> ctypes.CDLL:
     L.psim_contract_site.argtypes = [i32, i64, i64, i64, i64, i64, vp, i64, ctypes.POINTER(ctypes.c_double), vp,
                                      i32, vp]
     L.psim_profile.argtypes = [vp, i32, ctypes.POINTER(KernelStats)]
+    L.psim_tune.argtypes = [vp, vp, sz, vp, i32, ctypes.POINTER(ctypes.c_double)]
     L.psim_last_error.restype = ctypes.c_char_p
     L.psim_version.restype = ctypes.c_char_p
     for f in ("psim_build", "psim_peps_info", "psim_plan", "psim_plan_info", "psim_amplitudes",
-              "psim_contract_site", "psim_profile"):
+              "psim_contract_site", "psim_profile", "psim_tune"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -189,6 +191,16 @@ class Plan:
                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(st),
                                      out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out[0::2] + 1j * out[1::2]
+
+    def tune(self, reps: int = 2, stream=None) -> float:
+        """Pick the fastest tile candidate per interior-step shape (psim_tune)."""
+        import torch
+        ws = self.workspace()
+        st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        best = ctypes.c_double()
+        _check(lib().psim_tune(self._h, ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(st), reps,
+                               ctypes.byref(best)))
+        return best.value
 
     def profile_start(self):
         _check(lib().psim_profile(self._h, 1, None))

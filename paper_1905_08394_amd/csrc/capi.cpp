@@ -13,6 +13,7 @@ psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o);
 void free_plan(psim_plan_t* pl);
 void run_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, size_t ws_bytes, void* stream,
                     double* out);
+void tune_plan(psim_plan_t* pl, void* ws, size_t ws_bytes, void* stream, int reps, double* best_ms);
 
 namespace psim {
 
@@ -104,6 +105,11 @@ psim_status psim_plan_info(const psim_plan_t* pl, psim_plan_stats* s) {
       if (lev.Dv > 1) o.v_chunk = std::min(o.v_chunk, lev.vchunk);
     o.sweep = pl->sweep;
     o.prec = pl->opts.prec;
+    double worst = -1;
+    for (const auto& st : pl->steps) {
+      const double cm = (double)st.M * st.K1 * st.K2 * st.N * (st.kind == 2 ? 1 : pl->levels[st.i].Dv);
+      if (cm > worst) { worst = cm; o.hot_cfg = st.kind == 1 ? st.cfg : 0; }
+    }
     *s = o;
   });
 }
@@ -122,7 +128,8 @@ psim_status psim_contract_site(int32_t prec, int64_t batch, int64_t M, int64_t K
                                const void* dA, int64_t a_batch_stride, const double* W, void* dC,
                                int32_t transpose_out, void* stream) {
   return guarded([&] {
-    if (prec != PSIM_FP64 && prec != PSIM_FP32_4M) fail(PSIM_EUNSUPPORTED, "precision not available");
+    if (prec != PSIM_FP64 && prec != PSIM_FP32_4M && prec != PSIM_FP32_3M)
+      fail(PSIM_EUNSUPPORTED, "precision not available");
     if (batch < 1 || M < 1 || K1 < 1 || K2 < 1 || N < 1) fail(PSIM_EINVAL, "non-positive size");
     if (!dA || !W || !dC) fail(PSIM_EINVAL, "NULL buffer");
     const int eb = prec == PSIM_FP64 ? 16 : 8;
@@ -161,6 +168,13 @@ psim_status psim_contract_site(int32_t prec, int64_t batch, int64_t M, int64_t K
       throw;
     }
     hip_check(hipFree(dW), "hipFree(W)");
+  });
+}
+
+psim_status psim_tune(psim_plan_t* pl, void* ws, size_t ws_bytes, void* stream, int32_t reps, double* best_ms) {
+  return guarded([&] {
+    if (!pl) fail(PSIM_EINVAL, "plan is NULL");
+    tune_plan(pl, ws, ws_bytes, stream, reps, best_ms);
   });
 }
 

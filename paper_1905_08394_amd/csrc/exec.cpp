@@ -64,7 +64,105 @@ Trie build_trie(const psim_plan_t& pl, const uint8_t* bits, size_t n) {
   return t;
 }
 
+// Workspace layout: per-level trie tables, exponents, row maxima, the two
+// boundary buffers (even / odd rows) and the two intermediate buffers.
+struct WsLayout {
+  std::vector<int32_t*> parent;
+  std::vector<uint8_t*> tau;
+  int32_t* exp[2];
+  uint32_t* mx;
+  char* F[2];
+  char* G[2];
+};
+
+WsLayout layout(const psim_plan_t& pl, void* ws) {
+  auto al = [](uint64_t x) { return (x + 255) / 256 * 256; };
+  char* p = (char*)(((uintptr_t)ws + 255) / 256 * 256);
+  WsLayout w;
+  const int R = pl.R, L = pl.L;
+  w.parent.resize(R);
+  w.tau.resize(R);
+  int64_t nmax_all = 1;
+  for (int i = 0; i < R; ++i) {
+    const Level& lev = pl.levels[i];
+    w.parent[i] = (int32_t*)p;
+    p += al((uint64_t)lev.nmax * 4);
+    w.tau[i] = (uint8_t*)p;
+    p += al((uint64_t)lev.nmax * L);
+    nmax_all = std::max(nmax_all, lev.nmax);
+  }
+  w.exp[0] = (int32_t*)p; p += al((uint64_t)nmax_all * 4);
+  w.exp[1] = (int32_t*)p; p += al((uint64_t)nmax_all * 4);
+  w.mx = (uint32_t*)p; p += al((uint64_t)nmax_all * 4);
+  w.F[0] = p + pl.levels[0].F_off;
+  w.F[1] = p + (R > 1 ? pl.levels[1].F_off : 0);
+  p += pl.ws_F;
+  w.G[0] = p;
+  w.G[1] = p + pl.ws_G / 2;
+  return w;
+}
+
 }  // namespace
+
+void tune_plan(psim_plan_t* pl, void* ws, size_t ws_bytes, void* stream, int reps, double* best_ms) {
+  if (pl->host_only) fail(PSIM_EINVAL, "plan was made with PSIM_PLAN_HOST_ONLY");
+  if (!ws || ws_bytes < pl->ws_total) fail(PSIM_EINVAL, "workspace is NULL or smaller than the plan needs");
+  if (reps < 1) fail(PSIM_EINVAL, "reps must be at least 1");
+  if (best_ms) *best_ms = 0;
+  if (pl->opts.prec != PSIM_FP32_4M) return;
+  hip_check(hipSetDevice(pl->opts.device), "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  WsLayout W = layout(*pl, ws);
+  const int L = pl->L;
+  double worst_cmac = 0;
+  // distinct shapes of the interior-site contractions
+  std::map<std::vector<int64_t>, std::vector<size_t>> shapes;
+  for (size_t x = 0; x < pl->steps.size(); ++x) {
+    const Step& s = pl->steps[x];
+    if (s.kind != 1 || s.K2 % 2) continue;
+    const Level& lev = pl->levels[s.i];
+    shapes[{s.M, s.K1, s.K2, s.N, (int64_t)lev.vchunk}].push_back(x);
+  }
+  hipEvent_t a, b;
+  hip_check(hipEventCreate(&a), "hipEventCreate");
+  hip_check(hipEventCreate(&b), "hipEventCreate");
+  for (auto& kv : shapes) {
+    const Step& s = pl->steps[kv.second.front()];
+    const int c = pl->levels[s.i].vchunk;
+    GemmLaunch g;
+    g.prec = pl->opts.prec;
+    g.A = W.G[0];
+    g.C = W.G[1];
+    g.W0 = g.W1 = pl->w[((size_t)s.i * L + s.j) * 2].ptr;
+    g.ldw = pl->w[((size_t)s.i * L + s.j) * 2].ld;
+    g.M = s.M; g.K1 = s.K1; g.K2 = s.K2; g.N = s.N;
+    g.nodes = 1; g.Bz = c;
+    g.sA_v = s.K1 * s.M * s.K2; g.sA_node = c * g.sA_v;
+    g.sC_v = s.g_out; g.sC_node = c * s.g_out;
+    int best = 0;
+    double best_t = 1e300;
+    for (int cfg = 0; cfg < fp32_config_count(); ++cfg) {
+      g.cfg = cfg;
+      launch_site_gemm(g, st);  // warm
+      hip_check(hipEventRecord(a, st), "hipEventRecord");
+      for (int r = 0; r < reps; ++r) launch_site_gemm(g, st);
+      hip_check(hipEventRecord(b, st), "hipEventRecord");
+      hip_check(hipEventSynchronize(b), "hipEventSynchronize");
+      float ms = 0;
+      hip_check(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
+      const double t = ms / reps;
+      if (t < best_t) { best_t = t; best = cfg; }
+    }
+    for (size_t x : kv.second) pl->steps[x].cfg = best;
+    const double cm = (double)c * s.M * s.K1 * s.K2 * s.N;
+    if (cm > worst_cmac) {
+      worst_cmac = cm;
+      if (best_ms) *best_ms = best_t;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+}
 
 void run_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, size_t ws_bytes, void* stream,
                     double* out) {
@@ -144,28 +242,13 @@ void run_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, si
   Trie t = build_trie(*pl, bits, n);
 
   // ------------------------------------------------------------ workspace
-  auto al = [](uint64_t x) { return (x + 255) / 256 * 256; };
-  char* base = (char*)(((uintptr_t)ws + 255) / 256 * 256);
-  char* p = base;
-  std::vector<int32_t*> d_parent(R);
-  std::vector<uint8_t*> d_tau(R);
-  int64_t nmax_all = 1;
-  for (int i = 0; i < R; ++i) {
-    const Level& lev = pl->levels[i];
-    d_parent[i] = (int32_t*)p;
-    p += al((uint64_t)lev.nmax * 4);
-    d_tau[i] = (uint8_t*)p;
-    p += al((uint64_t)lev.nmax * L);
-    nmax_all = std::max(nmax_all, lev.nmax);
-  }
-  int32_t* d_exp[2];
-  d_exp[0] = (int32_t*)p; p += al((uint64_t)nmax_all * 4);
-  d_exp[1] = (int32_t*)p; p += al((uint64_t)nmax_all * 4);
-  uint32_t* d_max = (uint32_t*)p; p += al((uint64_t)nmax_all * 4);
-  // boundaries of even / odd levels
-  char* dF[2] = {p + pl->levels[0].F_off, p + (R > 1 ? pl->levels[1].F_off : 0)};
-  p += pl->ws_F;
-  char* dG[2] = {p, p + pl->ws_G / 2};
+  WsLayout W = layout(*pl, ws);
+  std::vector<int32_t*>& d_parent = W.parent;
+  std::vector<uint8_t*>& d_tau = W.tau;
+  int32_t** d_exp = W.exp;
+  uint32_t* d_max = W.mx;
+  char** dF = W.F;
+  char** dG = W.G;
 
   for (int i = 0; i < R; ++i) {
     if ((int64_t)t.parent[i].size() > pl->levels[i].cap) fail(PSIM_EINTERNAL, "trie larger than planned");
@@ -221,6 +304,7 @@ void run_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, si
           const DevMatrix& w1 = pl->w[((size_t)i * L + j) * 2 + 1];
           GemmLaunch g;
           g.prec = prec;
+          g.cfg = s.kind == 1 ? s.cfg : 0;
           g.W0 = w0.ptr;
           g.W1 = w1.ptr;
           g.ldw = w0.ld;

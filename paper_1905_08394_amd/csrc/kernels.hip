@@ -104,25 +104,35 @@ template <>
 struct V16<double> { typedef f64x2 t; static constexpr int n = 2; };
 
 // ---------------------------------------------------------------- kernel
-template <typename T, int BM, int BN, int BK, int AMODE, bool TRANS>
+// SCH = 4: the 4M scheme above.  SCH = 3 (FP32 only): the Gauss 3M scheme,
+//   T1 = Ar Wr, T2 = Ai Wi, T3 = (Ar + Ai)(Wr + Wi),  Re C = T1 - T2,  Im C = T3 - T1 - T2,
+// three real MFMA products per complex multiply-add instead of four.  The
+// LDS A tile is the same interleaved (re, im) tile; each lane reads four
+// consecutive complex k (8 floats), splits re / im in registers and forms
+// re + im there.  W is packed as P[n][2k] = Re W[k][n], P[n][2k+1] = Im W[k][n].
+template <typename T, int BM, int BN, int BK, int AMODE, bool TRANS, int SCH>
 __global__ __launch_bounds__(256) void site_gemm(KArgs p) {
   typedef Mfma<T> MF;
   typedef typename V16<T>::t vec_t;
+  static_assert(SCH == 4 || (SCH == 3 && sizeof(T) == 4), "3M is FP32 only");
   constexpr int VN = V16<T>::n;          // reals per 16-byte vector
   constexpr int LDS_LD = BK + VN;        // padded row length (reals)
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int MBLK = WM / MF::MB, NBLK = WN / MF::MB;
+  constexpr int NBLK3 = WN / 2 / MF::MB;  // 3M: complex columns per wave / 32
   constexpr int GROUPS = BK / 8;
+  constexpr int BROWS = SCH == 4 ? BN : BN / 2;   // rows of the packed W per tile
   // A tile: BM x BK reals = BM * BK / VN vectors
   constexpr int A_VECS = BM * BK / VN / 256;
-  constexpr int B_VECS = BN * BK / VN / 256;
+  constexpr int B_VECS = BROWS * BK / VN / 256;
   static_assert(A_VECS * VN * 256 == BM * BK, "A tile");
-  static_assert(B_VECS * VN * 256 == BN * BK, "B tile");
+  static_assert(B_VECS * VN * 256 == BROWS * BK, "B tile");
+  static_assert(SCH == 4 || (NBLK3 >= 1 && BK % 16 == 0), "3M tile");
   // GENERIC loader works on single complex numbers (2 reals)
   constexpr int A_CPLX = BM * BK / 2 / 256;
 
   __shared__ __attribute__((aligned(16))) T sA[2][BM * LDS_LD];
-  __shared__ __attribute__((aligned(16))) T sB[2][BN * LDS_LD];
+  __shared__ __attribute__((aligned(16))) T sB[2][BROWS * LDS_LD];
 
   const long long per_xcd = (p.T + 7) / 8;
   const long long bid = blockIdx.x;
@@ -139,6 +149,7 @@ __global__ __launch_bounds__(256) void site_gemm(KArgs p) {
   const T* __restrict__ W = (const T*)(tauv ? p.W1 : p.W0) + p.w_koff_r;
   T* __restrict__ C = (T*)p.C + 2 * (node * p.sC_node + vb * p.sC_v);
   const long long m0 = mt * BM, n0 = nt * BN;
+  const long long brow0 = nt * BROWS;  // first packed-W row of this tile
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
@@ -231,7 +242,7 @@ __global__ __launch_bounds__(256) void site_gemm(KArgs p) {
     for (int it = 0; it < B_VECS; ++it) {
       const int lin = it * 256 + tid;
       const int row = lin / (BK / VN), kq = lin % (BK / VN);
-      rb[it] = *(const vec_t*)(W + (n0 + row) * p.ldw + kr0 + kq * VN);
+      rb[it] = *(const vec_t*)(W + (brow0 + row) * p.ldw + kr0 + kq * VN);
     }
   };
   auto store_b = [&](int buf) {
@@ -244,13 +255,25 @@ __global__ __launch_bounds__(256) void site_gemm(KArgs p) {
     }
   };
 
-  typename MF::acc_t acc[MBLK][NBLK];
+  typename MF::acc_t acc[SCH == 4 ? MBLK : 1][SCH == 4 ? NBLK : 1];
+  typename MF::acc_t acc3[SCH == 3 ? MBLK : 1][SCH == 3 ? NBLK3 : 1][3];
+  if constexpr (SCH == 4) {
 #pragma unroll
-  for (int bi = 0; bi < MBLK; ++bi)
+    for (int bi = 0; bi < MBLK; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < NBLK; ++bj)
+      for (int bj = 0; bj < NBLK; ++bj)
 #pragma unroll
-      for (int r = 0; r < MF::NACC; ++r) acc[bi][bj][r] = 0;
+        for (int r = 0; r < MF::NACC; ++r) acc[bi][bj][r] = 0;
+  } else {
+#pragma unroll
+    for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < NBLK3; ++bj)
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+          for (int r = 0; r < MF::NACC; ++r) acc3[bi][bj][q][r] = 0;
+  }
 
   const long long nk = (p.Kr + BK - 1) / BK;
   load_a(0);
@@ -272,21 +295,56 @@ __global__ __launch_bounds__(256) void site_gemm(KArgs p) {
     }
     const T* a_s = sA[cur];
     const T* b_s = sB[cur];
+    if constexpr (SCH == 4) {
 #pragma unroll
-    for (int g = 0; g < GROUPS; ++g) {
-      typename MF::frag_t af[MBLK], bf[NBLK];
-#pragma unroll
-      for (int bi = 0; bi < MBLK; ++bi)
-        af[bi] = *(const typename MF::frag_t*)(a_s + (wr * WM + bi * MF::MB + frow) * LDS_LD + g * 8 + fk);
-#pragma unroll
-      for (int bj = 0; bj < NBLK; ++bj)
-        bf[bj] = *(const typename MF::frag_t*)(b_s + (wc * WN + bj * MF::MB + frow) * LDS_LD + g * 8 + fk);
-#pragma unroll
-      for (int s = 0; s < MF::KV; ++s)
+      for (int g = 0; g < GROUPS; ++g) {
+        typename MF::frag_t af[MBLK], bf[NBLK];
 #pragma unroll
         for (int bi = 0; bi < MBLK; ++bi)
+          af[bi] = *(const typename MF::frag_t*)(a_s + (wr * WM + bi * MF::MB + frow) * LDS_LD + g * 8 + fk);
 #pragma unroll
-          for (int bj = 0; bj < NBLK; ++bj) MF::mma(af[bi], bf[bj], acc[bi][bj], s);
+        for (int bj = 0; bj < NBLK; ++bj)
+          bf[bj] = *(const typename MF::frag_t*)(b_s + (wc * WN + bj * MF::MB + frow) * LDS_LD + g * 8 + fk);
+#pragma unroll
+        for (int s = 0; s < MF::KV; ++s)
+#pragma unroll
+          for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < NBLK; ++bj) MF::mma(af[bi], bf[bj], acc[bi][bj], s);
+      }
+    } else {
+      // groups of 8 complex k (16 floats); lane half h covers complex k 4h .. 4h+3
+      const int f8 = (lane / MF::MB) * 8;
+#pragma unroll
+      for (int g = 0; g < BK / 16; ++g) {
+        f32x4 ar[MBLK], ai[MBLK], as[MBLK], br[NBLK3], bim[NBLK3], bs[NBLK3];
+#pragma unroll
+        for (int bi = 0; bi < MBLK; ++bi) {
+          const T* q = a_s + (wr * WM + bi * MF::MB + frow) * LDS_LD + g * 16 + f8;
+          const f32x4 x0 = *(const f32x4*)q, x1 = *(const f32x4*)(q + 4);
+          ar[bi] = f32x4{x0[0], x0[2], x1[0], x1[2]};
+          ai[bi] = f32x4{x0[1], x0[3], x1[1], x1[3]};
+          as[bi] = ar[bi] + ai[bi];
+        }
+#pragma unroll
+        for (int bj = 0; bj < NBLK3; ++bj) {
+          const T* q = b_s + (wc * (WN / 2) + bj * MF::MB + frow) * LDS_LD + g * 16 + f8;
+          const f32x4 x0 = *(const f32x4*)q, x1 = *(const f32x4*)(q + 4);
+          br[bj] = f32x4{x0[0], x0[2], x1[0], x1[2]};
+          bim[bj] = f32x4{x0[1], x0[3], x1[1], x1[3]};
+          bs[bj] = br[bj] + bim[bj];
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < NBLK3; ++bj) {
+              acc3[bi][bj][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[bi][s], br[bj][s], acc3[bi][bj][0], 0, 0, 0);
+              acc3[bi][bj][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[bi][s], bim[bj][s], acc3[bi][bj][1], 0, 0, 0);
+              acc3[bi][bj][2] = __builtin_amdgcn_mfma_f32_32x32x2f32(as[bi][s], bs[bj][s], acc3[bi][bj][2], 0, 0, 0);
+            }
+      }
     }
     if (more) {
       store_a(cur ^ 1);
@@ -296,24 +354,46 @@ __global__ __launch_bounds__(256) void site_gemm(KArgs p) {
   }
 
   // ------------------------------------------------------------ epilogue
+  if constexpr (SCH == 4) {
 #pragma unroll
-  for (int bi = 0; bi < MBLK; ++bi)
+    for (int bi = 0; bi < MBLK; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < NBLK; ++bj)
+      for (int bj = 0; bj < NBLK; ++bj)
 #pragma unroll
-      for (int r = 0; r < MF::NACC; ++r) {
-        const long long row = m0 + wr * WM + bi * MF::MB + MF::out_row(lane, r);
-        const long long col = n0 + wc * WN + bj * MF::MB + MF::out_col(lane);
-        if (row < p.M && col < p.Nr) {
-          const T v = acc[bi][bj][r];
-          if constexpr (!TRANS) {
-            C[row * p.Nr + col] = v;
-          } else {
-            T* dst = C + 2 * ((col >> 1) * p.M + row) + (col & 1);
-            *dst = p.beta ? *dst + v : v;
+        for (int r = 0; r < MF::NACC; ++r) {
+          const long long row = m0 + wr * WM + bi * MF::MB + MF::out_row(lane, r);
+          const long long col = n0 + wc * WN + bj * MF::MB + MF::out_col(lane);
+          if (row < p.M && col < p.Nr) {
+            const T v = acc[bi][bj][r];
+            if constexpr (!TRANS) {
+              C[row * p.Nr + col] = v;
+            } else {
+              T* dst = C + 2 * ((col >> 1) * p.M + row) + (col & 1);
+              *dst = p.beta ? *dst + v : v;
+            }
           }
         }
-      }
+  } else {
+    const long long c0 = n0 / 2;  // first complex column of the tile
+#pragma unroll
+    for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < NBLK3; ++bj)
+#pragma unroll
+        for (int r = 0; r < MF::NACC; ++r) {
+          const long long row = m0 + wr * WM + bi * MF::MB + MF::out_row(lane, r);
+          const long long col = c0 + wc * (WN / 2) + bj * MF::MB + MF::out_col(lane);
+          if (row < p.M && col < p.N) {
+            const T t1 = acc3[bi][bj][0][r], t2 = acc3[bi][bj][1][r], t3 = acc3[bi][bj][2][r];
+            f32x2 v = {t1 - t2, t3 - t1 - t2};
+            f32x2* dst = (f32x2*)(C + 2 * (TRANS ? col * p.M + row : row * p.N + col));
+            if constexpr (TRANS) {
+              if (p.beta) v += *dst;
+            }
+            *dst = v;
+          }
+        }
+  }
 }
 
 // ---------------------------------------------------------------- rescale
@@ -379,9 +459,18 @@ void hip_check(int err, const char* what) {
     fail(PSIM_EDEVICE, std::string(what) + ": " + hipGetErrorString((hipError_t)err));
 }
 
-template <typename T, int BM, int BN, int BK, int AMODE, bool TRANS>
+// Tile candidates (BM x BN real outputs per workgroup, BK reals per stage) of
+// the FP32 row-major interior-site kernel; index 0 is the default.
+struct FCfg {
+  int bm, bn, bk;
+};
+static const FCfg kFp32Configs[] = {{128, 128, 32}, {256, 128, 16}, {128, 256, 16},
+                                    {256, 256, 16}, {128, 128, 64}, {256, 128, 32}};
+int fp32_config_count() { return (int)(sizeof(kFp32Configs) / sizeof(kFp32Configs[0])); }
+
+template <typename T, int BM, int BN, int BK, int AMODE, bool TRANS, int SCH = 4>
 static void launch(const KArgs& a, long long blocks, hipStream_t st) {
-  hipLaunchKernelGGL((site_gemm<T, BM, BN, BK, AMODE, TRANS>), dim3((unsigned)blocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL((site_gemm<T, BM, BN, BK, AMODE, TRANS, SCH>), dim3((unsigned)blocks), dim3(256), 0, st, a);
 }
 
 void launch_site_gemm(const GemmLaunch& g, void* stream) {
@@ -443,7 +532,33 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
     const bool even_base = ((uintptr_t)g.A % 16 == 0) && (g.sA_node % 2 == 0) && (g.sA_v % 2 == 0);
     const int mode = (g.K2 % 2 == 0 && even_base) ? ROWMAJOR
                      : (g.K2 == 1 && g.M % 2 == 0 && g.K1 > 1 && even_base) ? KMAJOR : GENERIC;
-    if (mode == ROWMAJOR)
+    if (g.prec == PSIM_FP32_3M) {
+      if (mode == ROWMAJOR)
+        g.trans_out ? launch<float, 128, 128, 32, ROWMAJOR, true, 3>(b, blocks, st)
+                    : launch<float, 128, 128, 32, ROWMAJOR, false, 3>(b, blocks, st);
+      else if (mode == KMAJOR)
+        g.trans_out ? launch<float, 128, 128, 32, KMAJOR, true, 3>(b, blocks, st)
+                    : launch<float, 128, 128, 32, KMAJOR, false, 3>(b, blocks, st);
+      else
+        g.trans_out ? launch<float, 128, 128, 32, GENERIC, true, 3>(b, blocks, st)
+                    : launch<float, 128, 128, 32, GENERIC, false, 3>(b, blocks, st);
+    } else if (mode == ROWMAJOR && !g.trans_out && g.cfg > 0) {
+      // tile candidates of the hot (interior-site) kernel; see kFp32Configs
+      const FCfg& c = kFp32Configs[g.cfg];
+      b.MT = (b.M + c.bm - 1) / c.bm;
+      b.NT = (b.Nr + c.bn - 1) / c.bn;
+      b.T = b.MT * b.NT * Z;
+      const long long bl = (b.T + 7) / 8 * 8;
+      if (bl > 0x7fffffffLL) fail(PSIM_EUNSUPPORTED, "grid too large");
+      switch (g.cfg) {
+        case 1: launch<float, 256, 128, 16, ROWMAJOR, false>(b, bl, st); break;
+        case 2: launch<float, 128, 256, 16, ROWMAJOR, false>(b, bl, st); break;
+        case 3: launch<float, 256, 256, 16, ROWMAJOR, false>(b, bl, st); break;
+        case 4: launch<float, 128, 128, 64, ROWMAJOR, false>(b, bl, st); break;
+        case 5: launch<float, 256, 128, 32, ROWMAJOR, false>(b, bl, st); break;
+        default: fail(PSIM_EINVAL, "unknown kernel config");
+      }
+    } else if (mode == ROWMAJOR)
       g.trans_out ? launch<float, 128, 128, 32, ROWMAJOR, true>(b, blocks, st)
                   : launch<float, 128, 128, 32, ROWMAJOR, false>(b, blocks, st);
     else if (mode == KMAJOR)

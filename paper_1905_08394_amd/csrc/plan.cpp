@@ -41,8 +41,7 @@ int64_t packed_ld(int prec, int64_t K) {
   return round_up(2 * K, 32) + 32;
 }
 int64_t packed_rows(int prec, int64_t N) {
-  (void)prec;
-  return round_up(2 * N, 256);
+  return prec == PSIM_FP32_3M ? round_up(N, 128) : round_up(2 * N, 256);
 }
 
 // Real expansion of a complex K x N matrix for the 4M scheme, stored
@@ -53,7 +52,17 @@ int64_t packed_rows(int prec, int64_t N) {
 void pack_site_matrix(int prec, const cd* W, int64_t K, int64_t N, std::vector<char>& out, int64_t& ld) {
   ld = packed_ld(prec, K);
   const int64_t rows = packed_rows(prec, N);
-  if (prec == PSIM_FP64) {
+  if (prec == PSIM_FP32_3M) {
+    // 3M: one row per complex column n, (Re, Im) of W[k][n] interleaved along k
+    out.assign((size_t)(rows * ld) * sizeof(float), 0);
+    float* P = reinterpret_cast<float*>(out.data());
+    for (int64_t k = 0; k < K; ++k)
+      for (int64_t n = 0; n < N; ++n) {
+        const cd w = W[k * N + n];
+        P[n * ld + 2 * k] = (float)w.real();
+        P[n * ld + 2 * k + 1] = (float)w.imag();
+      }
+  } else if (prec == PSIM_FP64) {
     out.assign((size_t)(rows * ld) * sizeof(double), 0);
     double* P = reinterpret_cast<double*>(out.data());
     for (int64_t k = 0; k < K; ++k)
@@ -134,7 +143,7 @@ psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o) {
   if (!P) fail(PSIM_EINVAL, "peps is NULL");
   psim_plan_opts opts{};
   if (o) opts = *o;
-  if (opts.prec != PSIM_FP64 && opts.prec != PSIM_FP32_4M)
+  if (opts.prec != PSIM_FP64 && opts.prec != PSIM_FP32_4M && opts.prec != PSIM_FP32_3M)
     fail(PSIM_EUNSUPPORTED, "precision " + std::to_string(opts.prec) + " is not available in this build");
   if (opts.mem_budget_bytes == 0) opts.mem_budget_bytes = 200ull << 30;
   if (opts.max_batch <= 0) opts.max_batch = 1;

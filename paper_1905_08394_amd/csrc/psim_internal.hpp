@@ -62,6 +62,7 @@ struct Step {
   int kind = 0;          // 0 first site, 1 interior, 2 last site (K1 = v chunk)
   int64_t M = 1, K1 = 1, K2 = 1, N = 1;
   int64_t g_out = 0;     // elements of the output per (node, v) (kind 0/1)
+  int cfg = 0;           // kernel tile candidate chosen by the tuner
 };
 
 struct Level {
@@ -131,7 +132,9 @@ struct GemmLaunch {
   int32_t Bz = 1;                     // batch entries per node
   int32_t trans_out = 0;
   int32_t beta = 0;
+  int32_t cfg = 0;                    // tile candidate of the FP32 row-major kernel (0 = default)
 };
+int fp32_config_count();
 void launch_site_gemm(const GemmLaunch& g, void* stream);
 void launch_rowscale(int prec, void* F, int64_t elems_per_node, int64_t nodes, const int32_t* parent,
                      const int32_t* exp_prev, int32_t* exp_cur, uint32_t* scratch_max, void* stream);
