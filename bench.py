@@ -22,8 +22,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "seconds/amplitude + contraction TFLOP/s (% MFMA peak), 6x6 d40, FP32-MFMA vs FP64"
-PEAK_TFLOPS = {"fp32": 157.3, "fp32_3m": 157.3, "fp64": 78.6}   # MI355X dense MFMA, FP32 / FP64
-ISSUED_PER_CMAC = {"fp32": 8, "fp32_3m": 6, "fp64": 8}            # real MFMA flops per complex multiply-add
+# MI355X dense MFMA peaks (TFLOP/s) of the arithmetic each path issues
+PEAK_TFLOPS = {"fp32": 157.3, "fp32_3m": 157.3, "fp64": 78.6, "bf16x3": 2500.0}
+ISSUED_PER_CMAC = {"fp32": 8, "fp32_3m": 6, "fp64": 8, "bf16x3": 24}   # real MFMA flops per complex multiply-add
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_interior_site_6x6_d40_fp32.json")
 
 
@@ -165,7 +166,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp32_3m", "fp64"])
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp32_3m", "fp64", "bf16x3"])
     ap.add_argument("--lattice", type=int, default=6)
     ap.add_argument("--depth", type=int, default=40)
     ap.add_argument("--mem-gib", type=int, default=0, help="workspace budget (0: 96 GiB fp32, 128 GiB fp64)")
@@ -215,14 +216,16 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.prec == "fp64" else "f32",
+        "dtype": {"fp64": "f64", "bf16x3": "bf16x3"}.get(args.prec, "f32"),
         "data": "synthetic",
         "config": {"workload": f"{args.lattice}x{args.lattice} lattice, random circuit depth (1+{args.depth}+1), "
                                f"D={stats['chi']}, exact row-scheme amplitudes of {len(bits)} bitstrings "
                                f"sharing rows 1-{args.lattice - 1} (last-row variants)",
                    "precision": {"fp32": "complex64 storage, FP32 MFMA (4M)",
                                  "fp32_3m": "complex64 storage, FP32 MFMA (3M, Gauss)",
-                                 "fp64": "complex128 storage, FP64 MFMA"}[args.prec],
+                                 "fp64": "complex128 storage, FP64 MFMA",
+                                 "bf16x3": "complex64 storage, BF16 hi/lo split, 3 BF16 MFMA products, "
+                                           "FP32 accumulation"}[args.prec],
                    "bitstrings_per_step": len(bits), "seed": 0, "v_chunk": stats["v_chunk"],
                    "hot_tile_config": stats["hot_cfg"],
                    "workspace_gib": round(stats["workspace_bytes"] / 2 ** 30, 2)},

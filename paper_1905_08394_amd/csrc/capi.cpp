@@ -128,7 +128,7 @@ psim_status psim_contract_site(int32_t prec, int64_t batch, int64_t M, int64_t K
                                const void* dA, int64_t a_batch_stride, const double* W, void* dC,
                                int32_t transpose_out, void* stream) {
   return guarded([&] {
-    if (prec != PSIM_FP64 && prec != PSIM_FP32_4M && prec != PSIM_FP32_3M)
+    if (prec != PSIM_FP64 && prec != PSIM_FP32_4M && prec != PSIM_FP32_3M && prec != PSIM_BF16X3)
       fail(PSIM_EUNSUPPORTED, "precision not available");
     if (batch < 1 || M < 1 || K1 < 1 || K2 < 1 || N < 1) fail(PSIM_EINVAL, "non-positive size");
     if (!dA || !W || !dC) fail(PSIM_EINVAL, "NULL buffer");
@@ -138,15 +138,24 @@ psim_status psim_contract_site(int32_t prec, int64_t batch, int64_t M, int64_t K
     const int64_t K = K1 * K2;
     std::vector<cd> Wc((size_t)(K * N));
     for (int64_t x = 0; x < K * N; ++x) Wc[x] = cd(W[2 * x], W[2 * x + 1]);
-    std::vector<char> packed;
-    int64_t ld = 0;
-    pack_site_matrix(prec, Wc.data(), K, N, packed, ld);
+    std::vector<char> packed, packed_b;
+    int64_t ld = 0, ld_b = 0, plane_b = 0;
+    pack_site_matrix(prec == PSIM_BF16X3 ? PSIM_FP32_4M : prec, Wc.data(), K, N, packed, ld);
+    if (prec == PSIM_BF16X3) pack_site_matrix_bf16(Wc.data(), K, N, packed_b, ld_b, plane_b);
     void* dW = nullptr;
-    hip_check(hipMalloc(&dW, packed.size()), "hipMalloc(W)");
+    void* dWb = nullptr;
+    hip_check(hipMalloc(&dW, packed.size() + packed_b.size()), "hipMalloc(W)");
     try {
       hipStream_t st = (hipStream_t)stream;
       hip_check(hipMemcpyAsync(dW, packed.data(), packed.size(), hipMemcpyHostToDevice, st), "upload W");
+      if (!packed_b.empty()) {
+        dWb = (char*)dW + packed.size();
+        hip_check(hipMemcpyAsync(dWb, packed_b.data(), packed_b.size(), hipMemcpyHostToDevice, st), "upload W");
+      }
       GemmLaunch g;
+      g.Wb0 = dWb;
+      g.ldwb = ld_b;
+      g.planeb = plane_b;
       g.prec = prec;
       g.A = dA;
       g.C = dC;

@@ -305,6 +305,12 @@ void run_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, si
           GemmLaunch g;
           g.prec = prec;
           g.cfg = s.kind == 1 ? s.cfg : 0;
+          if (s.kind == 1 && w0.ptr_b) {
+            g.Wb0 = w0.ptr_b;
+            g.Wb1 = w1.ptr_b;
+            g.ldwb = w0.ld_b;
+            g.planeb = w0.plane_b;
+          }
           g.W0 = w0.ptr;
           g.W1 = w1.ptr;
           g.ldw = w0.ld;

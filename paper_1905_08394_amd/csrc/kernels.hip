@@ -56,6 +56,7 @@ struct KArgs {
   long long ldw, w_koff_r;
   long long sA_node, sA_v, sC_node, sC_v;
   long long MT, NT, T;
+  long long plane;    // BF16x3: elements between the hi and lo planes of W
   int Bz, trans_out, beta;
 };
 
@@ -396,6 +397,161 @@ __global__ __launch_bounds__(256) void site_gemm(KArgs p) {
   }
 }
 
+// ---------------------------------------------------------------- BF16x3
+// Split-precision variant of the 4M kernel for row-major A and a plain store:
+// every FP32 operand x is split as x = hi + lo with hi = bf16(x) and
+// lo = bf16(x - hi) (round to nearest even), and
+//   a b ~= a_hi b_hi + a_hi b_lo + a_lo b_hi
+// is accumulated in FP32 with v_mfma_f32_32x32x16_bf16 (the a_lo b_lo term,
+// ~2^-18 relative, is dropped).  W arrives pre-split (two bf16 planes of the
+// transposed 4M expansion); A is split while it is staged into LDS.  Lane
+// half h of a 32x32x16 MFMA supplies 8 consecutive k (k = 8h .. 8h+7).
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void site_gemm_bf16x3(KArgs p) {
+  constexpr int BK = 16;                 // reals per stage: one MFMA k-step
+  constexpr int LD = BK + 8;             // padded LDS row (bf16), 48 bytes
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int MBLK = WM / 32, NBLK = WN / 32;
+  constexpr int A_VECS = BM * BK / 4 / 256;     // float4 loads of A per thread
+  constexpr int B_VECS = BN * BK / 8 / 256;     // 16-byte loads per bf16 plane per thread
+  static_assert(A_VECS >= 1 && A_VECS * 4 * 256 == BM * BK, "A tile");
+  static_assert(B_VECS >= 1 && B_VECS * 8 * 256 == BN * BK, "B tile");
+
+  __shared__ __attribute__((aligned(16))) __bf16 sAh[2][BM * LD];
+  __shared__ __attribute__((aligned(16))) __bf16 sAl[2][BM * LD];
+  __shared__ __attribute__((aligned(16))) __bf16 sBh[2][BN * LD];
+  __shared__ __attribute__((aligned(16))) __bf16 sBl[2][BN * LD];
+
+  const long long per_xcd = (p.T + 7) / 8;
+  const long long bid = blockIdx.x;
+  const long long t = (bid % 8) * per_xcd + bid / 8;
+  if (t >= p.T) return;
+  const long long nt = t % p.NT;
+  const long long rest = t / p.NT;
+  const long long mt = rest % p.MT;
+  const long long z = rest / p.MT;
+  const long long node = z / p.Bz, vb = z % p.Bz;
+  const long long ablk = p.a_index ? (long long)p.a_index[node] : node;
+  const float* __restrict__ A = (const float*)p.A + 2 * (ablk * p.sA_node + vb * p.sA_v);
+  const int tauv = p.tau ? (int)p.tau[node * p.tau_stride] : 0;
+  // bf16 planes: hi at W, lo at W + plane (elements); p.ldw is the row length in bf16
+  const __bf16* __restrict__ Wh = (const __bf16*)(tauv ? p.W1 : p.W0) + p.w_koff_r;
+  const __bf16* __restrict__ Wl = Wh + p.plane;
+  float* __restrict__ C = (float*)p.C + 2 * (node * p.sC_node + vb * p.sC_v);
+  const long long m0 = mt * BM, n0 = nt * BN;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  const long long sK1 = p.M * p.K2;
+  const unsigned K2u = (unsigned)p.K2;
+
+  f32x4 ra[A_VECS];
+  f32x4 rbh[B_VECS], rbl[B_VECS];  // 16 bytes = 8 bf16 each
+
+  auto load = [&](long long kr0) {
+#pragma unroll
+    for (int it = 0; it < A_VECS; ++it) {
+      const int lin = it * 256 + tid;
+      const int row = lin / (BK / 4), kq = lin % (BK / 4);
+      const long long m = m0 + row, kr = kr0 + kq * 4;
+      f32x4 v = {};
+      if (m < p.M && kr < p.Kr) {
+        const unsigned k = (unsigned)(kr >> 1);
+        const unsigned k1 = k / K2u, k2 = k - k1 * K2u;
+        v = *(const f32x4*)(A + 2 * ((long long)k1 * sK1 + m * p.K2 + k2));
+      }
+      ra[it] = v;
+    }
+#pragma unroll
+    for (int it = 0; it < B_VECS; ++it) {
+      const int lin = it * 256 + tid;
+      const int row = lin / (BK / 8), kq = lin % (BK / 8);
+      const long long off = (n0 + row) * p.ldw + kr0 + kq * 8;
+      rbh[it] = *(const f32x4*)(Wh + off);
+      rbl[it] = *(const f32x4*)(Wl + off);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int it = 0; it < A_VECS; ++it) {
+      const int lin = it * 256 + tid;
+      const int row = lin / (BK / 4), kq = lin % (BK / 4);
+      bf16x4 hi, lo;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        hi[e] = (__bf16)ra[it][e];
+        lo[e] = (__bf16)(ra[it][e] - (float)hi[e]);
+      }
+      *(bf16x4*)(&sAh[buf][row * LD + kq * 4]) = hi;
+      *(bf16x4*)(&sAl[buf][row * LD + kq * 4]) = lo;
+    }
+#pragma unroll
+    for (int it = 0; it < B_VECS; ++it) {
+      const int lin = it * 256 + tid;
+      const int row = lin / (BK / 8), kq = lin % (BK / 8);
+      *(f32x4*)(&sBh[buf][row * LD + kq * 8]) = rbh[it];
+      *(f32x4*)(&sBl[buf][row * LD + kq * 8]) = rbl[it];
+    }
+  };
+
+  f32x16 acc[MBLK][NBLK];
+#pragma unroll
+  for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < NBLK; ++bj)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[bi][bj][r] = 0;
+
+  const long long nk = (p.Kr + BK - 1) / BK;
+  load(0);
+  store(0);
+  __syncthreads();
+  const int frow = lane & 31, fk = (lane >> 5) * 8;
+  for (long long kt = 0; kt < nk; ++kt) {
+    const int cur = (int)(kt & 1);
+    const bool more = kt + 1 < nk;
+    if (more) load((kt + 1) * BK);
+    bf16x8 ah[MBLK], al[MBLK], bh[NBLK], bl[NBLK];
+#pragma unroll
+    for (int bi = 0; bi < MBLK; ++bi) {
+      const int o = (wr * WM + bi * 32 + frow) * LD + fk;
+      ah[bi] = *(const bf16x8*)(&sAh[cur][o]);
+      al[bi] = *(const bf16x8*)(&sAl[cur][o]);
+    }
+#pragma unroll
+    for (int bj = 0; bj < NBLK; ++bj) {
+      const int o = (wc * WN + bj * 32 + frow) * LD + fk;
+      bh[bj] = *(const bf16x8*)(&sBh[cur][o]);
+      bl[bj] = *(const bf16x8*)(&sBl[cur][o]);
+    }
+#pragma unroll
+    for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < NBLK; ++bj) {
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[bi], bh[bj], acc[bi][bj], 0, 0, 0);
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bl[bj], acc[bi][bj], 0, 0, 0);
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bh[bj], acc[bi][bj], 0, 0, 0);
+      }
+    if (more) store(cur ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < NBLK; ++bj)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const long long row = m0 + wr * WM + bi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const long long col = n0 + wc * WN + bj * 32 + (lane & 31);
+        if (row < p.M && col < p.Nr) C[row * p.Nr + col] = acc[bi][bj][r];
+      }
+}
+
 // ---------------------------------------------------------------- rescale
 // Per node: largest binary exponent of any component (as exponent + 4096,
 // so that unsigned atomicMax orders it), 0 when the node is all zeros.
@@ -532,7 +688,24 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
     const bool even_base = ((uintptr_t)g.A % 16 == 0) && (g.sA_node % 2 == 0) && (g.sA_v % 2 == 0);
     const int mode = (g.K2 % 2 == 0 && even_base) ? ROWMAJOR
                      : (g.K2 == 1 && g.M % 2 == 0 && g.K1 > 1 && even_base) ? KMAJOR : GENERIC;
-    if (g.prec == PSIM_FP32_3M) {
+    if (g.prec == PSIM_BF16X3 && mode == ROWMAJOR && !g.trans_out && g.Wb0) {
+      // split-precision kernel on the pre-split planes
+      b.W0 = g.Wb0;
+      b.W1 = g.Wb1 ? g.Wb1 : g.Wb0;
+      b.ldw = g.ldwb;
+      b.plane = g.planeb;
+      const bool big = g.cfg != 1;
+      const int bm = big ? 256 : 128, bn = 256;
+      b.MT = (b.M + bm - 1) / bm;
+      b.NT = (b.Nr + bn - 1) / bn;
+      b.T = b.MT * b.NT * Z;
+      const long long bl = (b.T + 7) / 8 * 8;
+      if (bl > 0x7fffffffLL) fail(PSIM_EUNSUPPORTED, "grid too large");
+      if (big)
+        hipLaunchKernelGGL((site_gemm_bf16x3<256, 256>), dim3((unsigned)bl), dim3(256), 0, st, b);
+      else
+        hipLaunchKernelGGL((site_gemm_bf16x3<128, 256>), dim3((unsigned)bl), dim3(256), 0, st, b);
+    } else if (g.prec == PSIM_FP32_3M) {
       if (mode == ROWMAJOR)
         g.trans_out ? launch<float, 128, 128, 32, ROWMAJOR, true, 3>(b, blocks, st)
                     : launch<float, 128, 128, 32, ROWMAJOR, false, 3>(b, blocks, st);

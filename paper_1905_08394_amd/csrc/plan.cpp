@@ -88,6 +88,42 @@ void pack_site_matrix(int prec, const cd* W, int64_t K, int64_t N, std::vector<c
   }
 }
 
+// bfloat16 by round-to-nearest-even of an FP32 value (IEEE binary32 with the
+// low 16 bits rounded away); NaN stays NaN.
+static uint16_t bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+static float bf16_to_float(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+// BF16x3: the FP32 4M expansion split into hi = bf16(x) and lo = bf16(x - hi)
+// planes, each stored like pack_site_matrix's FP32 layout (P[n'][k']).
+void pack_site_matrix_bf16(const cd* W, int64_t K, int64_t N, std::vector<char>& out, int64_t& ld, int64_t& plane) {
+  std::vector<char> f32;
+  int64_t ld32 = 0;
+  pack_site_matrix(PSIM_FP32_4M, W, K, N, f32, ld32);
+  ld = ld32;
+  const int64_t rows = packed_rows(PSIM_FP32_4M, N);
+  plane = rows * ld;
+  out.assign((size_t)(2 * plane) * 2, 0);
+  const float* P = reinterpret_cast<const float*>(f32.data());
+  uint16_t* H = reinterpret_cast<uint16_t*>(out.data());
+  uint16_t* Lo = H + plane;
+  for (int64_t x = 0; x < plane; ++x) {
+    const uint16_t h = bf16_rne(P[x]);
+    H[x] = h;
+    Lo[x] = bf16_rne(P[x] - bf16_to_float(h));
+  }
+}
+
 namespace {
 
 // contraction-frame site (i, j) -> original site and leg sizes
@@ -143,7 +179,7 @@ psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o) {
   if (!P) fail(PSIM_EINVAL, "peps is NULL");
   psim_plan_opts opts{};
   if (o) opts = *o;
-  if (opts.prec != PSIM_FP64 && opts.prec != PSIM_FP32_4M && opts.prec != PSIM_FP32_3M)
+  if (opts.prec != PSIM_FP64 && opts.prec != PSIM_FP32_4M && opts.prec != PSIM_FP32_3M && opts.prec != PSIM_BF16X3)
     fail(PSIM_EUNSUPPORTED, "precision " + std::to_string(opts.prec) + " is not available in this build");
   if (opts.mem_budget_bytes == 0) opts.mem_budget_bytes = 200ull << 30;
   if (opts.max_batch <= 0) opts.max_batch = 1;
@@ -308,12 +344,21 @@ psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o) {
           dm.exp2 = exponent_of_max(W);
           const double sc = std::ldexp(1.0, -dm.exp2);  // exact power of two
           for (cd& x : W) x *= sc;
-          pack_site_matrix(opts.prec, W.data(), (int64_t)c.du * c.dl, (int64_t)c.dd * c.dr, buf, dm.ld);
+          const int pack_prec = opts.prec == PSIM_BF16X3 ? PSIM_FP32_4M : opts.prec;
+          pack_site_matrix(pack_prec, W.data(), (int64_t)c.du * c.dl, (int64_t)c.dd * c.dr, buf, dm.ld);
           pl->weights_bytes += buf.size();
           if (!pl->host_only) {
             hip_check(hipSetDevice(opts.device), "hipSetDevice");
             hip_check(hipMalloc(&dm.ptr, buf.size()), "hipMalloc(site matrix)");
             hip_check(hipMemcpy(dm.ptr, buf.data(), buf.size(), hipMemcpyHostToDevice), "hipMemcpy(site matrix)");
+          }
+          if (opts.prec == PSIM_BF16X3) {  // interior sites also get the split planes
+            pack_site_matrix_bf16(W.data(), (int64_t)c.du * c.dl, (int64_t)c.dd * c.dr, buf, dm.ld_b, dm.plane_b);
+            pl->weights_bytes += buf.size();
+            if (!pl->host_only) {
+              hip_check(hipMalloc(&dm.ptr_b, buf.size()), "hipMalloc(site matrix)");
+              hip_check(hipMemcpy(dm.ptr_b, buf.data(), buf.size(), hipMemcpyHostToDevice), "hipMemcpy(site matrix)");
+            }
           }
         }
       }
@@ -323,8 +368,10 @@ psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o) {
       hip_check(hipDeviceSynchronize(), "fill ones");
     }
   } catch (...) {
-    for (auto& dm : pl->w)
+    for (auto& dm : pl->w) {
       if (dm.ptr) (void)hipFree(dm.ptr);
+      if (dm.ptr_b) (void)hipFree(dm.ptr_b);
+    }
     if (pl->d_ones) (void)hipFree(pl->d_ones);
     delete pl;
     throw;
@@ -334,8 +381,10 @@ psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o) {
 
 void free_plan(psim_plan_t* pl) {
   if (!pl) return;
-  for (auto& dm : pl->w)
+  for (auto& dm : pl->w) {
     if (dm.ptr) (void)hipFree(dm.ptr);
+    if (dm.ptr_b) (void)hipFree(dm.ptr_b);
+  }
   if (pl->d_ones) (void)hipFree(pl->d_ones);
   delete pl;
 }

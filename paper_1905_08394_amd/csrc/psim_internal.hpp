@@ -80,6 +80,8 @@ struct DevMatrix {
   void* ptr = nullptr;   // packed, on device
   int64_t ld = 0;        // leading dimension (real elements) of the packed layout
   int exp2 = 0;          // site matrix was scaled by 2^-exp2
+  void* ptr_b = nullptr; // BF16x3 plans: hi and lo bf16 planes of the 4M expansion
+  int64_t ld_b = 0, plane_b = 0;
 };
 
 }  // namespace psim
@@ -112,6 +114,7 @@ namespace psim {
 int64_t packed_ld(int prec, int64_t K);
 int64_t packed_rows(int prec, int64_t N);
 void pack_site_matrix(int prec, const cd* W, int64_t K, int64_t N, std::vector<char>& out, int64_t& ld);
+void pack_site_matrix_bf16(const cd* W, int64_t K, int64_t N, std::vector<char>& out, int64_t& ld, int64_t& plane);
 
 // kernels.hip: launch interface (host side)
 struct GemmLaunch {
@@ -133,6 +136,9 @@ struct GemmLaunch {
   int32_t trans_out = 0;
   int32_t beta = 0;
   int32_t cfg = 0;                    // tile candidate of the FP32 row-major kernel (0 = default)
+  const void* Wb0 = nullptr;          // BF16x3: pre-split bf16 planes of W (hi then lo)
+  const void* Wb1 = nullptr;
+  int64_t ldwb = 0, planeb = 0;
 };
 int fp32_config_count();
 void launch_site_gemm(const GemmLaunch& g, void* stream);

@@ -97,11 +97,14 @@ def test_planner_memory_budget(ps):
     assert e.value.status == ps.PSIM_ENOMEM
 
 
-def test_planner_unsupported_precision(ps):
+def test_planner_precisions(ps):
     P = ps.Peps(rqcgen.generate(3, 3, 8, 0))
-    with pytest.raises(ps.PsimError) as e:
-        ps.Plan(P, prec="bf16x3", host_only=True)
-    assert e.value.status == ps.PSIM_EUNSUPPORTED
+    for prec in ("fp64", "fp32", "fp32_3m", "bf16x3"):
+        assert ps.Plan(P, prec=prec, host_only=True).stats()["prec"] == ps.PREC[prec]
+    L = ps.lib()
+    o = ps.PlanOpts(7, ps.PLAN_HOST_ONLY, 0, 1, 0, 0, 0)
+    h = ctypes.c_void_p()
+    assert L.psim_plan(P._h, ctypes.byref(o), ctypes.byref(h)) == ps.PSIM_EUNSUPPORTED
 
 
 def test_host_only_plan_cannot_run(ps):
