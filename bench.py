@@ -49,7 +49,8 @@ def run_gpu(args, prec, circuit, bits):
     import torch
     import paper_1905_08394_amd as ps
     peps = ps.Peps(circuit)
-    plan = ps.Plan(peps, prec=prec, mem_budget=args.mem_gib << 30, max_batch=len(bits))
+    plan = ps.Plan(peps, prec=prec, mem_budget=args.mem_gib << 30, max_batch=len(bits),
+                   split_acc=args.split_acc and prec == "fp32")
     peps.close()
     stats = plan.stats()
     plan.workspace()                               # allocate before timing
@@ -173,6 +174,7 @@ def main():
     ap.add_argument("--compare-fp64", action="store_true", help="also time the FP64 path on the same batch")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-tune", dest="tune", action="store_false", help="skip the tile autotuner")
+    ap.add_argument("--split-acc", action="store_true", help="FP32 4M with per-stage partial sums")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--counters", action="store_true", help="short program for rocprofv3 --pmc passes")
     args = ap.parse_args()
@@ -218,6 +220,7 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "bf16x3": "bf16x3"}.get(args.prec, "f32"),
         "data": "synthetic",
+        "split_accumulation": bool(args.split_acc and args.prec == "fp32"),
         "config": {"workload": f"{args.lattice}x{args.lattice} lattice, random circuit depth (1+{args.depth}+1), "
                                f"D={stats['chi']}, exact row-scheme amplitudes of {len(bits)} bitstrings "
                                f"sharing rows 1-{args.lattice - 1} (last-row variants)",

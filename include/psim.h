@@ -67,7 +67,12 @@ typedef enum {
 } psim_precision;
 
 typedef enum {
-  PSIM_PLAN_HOST_ONLY = 1  /* plan the contraction on the host only (no device, cannot run) */
+  PSIM_PLAN_HOST_ONLY = 1,  /* plan the contraction on the host only (no device, cannot run) */
+  PSIM_PLAN_SPLIT_ACC = 2,  /* FP32 4M: accumulate each K stage separately before adding it to the
+                               running sum (smaller rounding error, same work) */
+  PSIM_PLAN_GRAPH = 4       /* psim_amplitudes captures its row sweep into a HIP graph the first time
+                               a (workspace, prefix-trie shape) pair is seen and replays it afterwards;
+                               ignored while profiling or when PSIM_LOG=1 */
 } psim_plan_flags;
 
 typedef struct {

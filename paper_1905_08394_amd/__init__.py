@@ -21,6 +21,8 @@ PSIM_OK, PSIM_EINVAL, PSIM_ENOMEM, PSIM_EDEVICE, PSIM_EUNSUPPORTED, PSIM_EINTERN
 KIND = {"H": 0, "T": 1, "SX": 2, "SY": 3, "CZ": 4, "U1": 5, "U2": 6}
 PREC = {"fp64": 0, "fp32": 1, "fp32_4m": 1, "fp32_3m": 2, "bf16x3": 3}
 PLAN_HOST_ONLY = 1
+PLAN_SPLIT_ACC = 2
+PLAN_GRAPH = 4
 EXPORTED = ("psim_build", "psim_peps_info", "psim_peps_free", "psim_plan", "psim_plan_info", "psim_plan_free",
             "psim_amplitudes", "psim_contract_site", "psim_tune", "psim_profile", "psim_last_error",
             "psim_version")
@@ -153,9 +155,11 @@ class Plan:
     """Contraction plan with packed site matrices on the device (psim_plan)."""
 
     def __init__(self, peps: Peps, prec: str = "fp32", mem_budget: int = 0, max_batch: int = 1, sweep: int = 0,
-                 device: int = 0, host_only: bool = False):
+                 device: int = 0, host_only: bool = False, split_acc: bool = False, graph: bool = False):
         L = lib()
-        o = PlanOpts(PREC[prec], PLAN_HOST_ONLY if host_only else 0, mem_budget, max_batch, sweep, device, 0)
+        flags = (PLAN_HOST_ONLY if host_only else 0) | (PLAN_SPLIT_ACC if split_acc else 0) | \
+            (PLAN_GRAPH if graph else 0)
+        o = PlanOpts(PREC[prec], flags, mem_budget, max_batch, sweep, device, 0)
         h = ctypes.c_void_p()
         _check(L.psim_plan(peps._h, ctypes.byref(o), ctypes.byref(h)))
         self._h = h

@@ -109,7 +109,7 @@ void tune_plan(psim_plan_t* pl, void* ws, size_t ws_bytes, void* stream, int rep
   if (!ws || ws_bytes < pl->ws_total) fail(PSIM_EINVAL, "workspace is NULL or smaller than the plan needs");
   if (reps < 1) fail(PSIM_EINVAL, "reps must be at least 1");
   if (best_ms) *best_ms = 0;
-  if (pl->opts.prec != PSIM_FP32_4M) return;
+  if (pl->opts.prec != PSIM_FP32_4M || (pl->opts.flags & PSIM_PLAN_SPLIT_ACC)) return;
   hip_check(hipSetDevice(pl->opts.device), "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
   WsLayout W = layout(*pl, ws);
@@ -287,8 +287,35 @@ void run_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, si
   const bool log_rows = env_log && env_log[0] == '1';
   const auto t_begin = std::chrono::steady_clock::now();
 
+  // ------------------------------------------------------------ graph replay (optional)
+  // The launch sequence below depends only on the workspace address and the
+  // number of nodes per level; the tables it reads were uploaded above.
+  const bool use_graph = (pl->opts.flags & PSIM_PLAN_GRAPH) && !pl->profile && !log_rows;
+  hipGraphExec_t gexec = nullptr;
+  bool capturing = false;
+  std::vector<int64_t> gkey;
+  if (use_graph) {
+    gkey.push_back((int64_t)(uintptr_t)ws);
+    for (int i = 0; i < R; ++i) gkey.push_back((int64_t)t.parent[i].size());
+    auto it = pl->graphs.find(gkey);
+    if (it != pl->graphs.end()) {
+      gexec = (hipGraphExec_t)it->second;
+    } else {
+      if (!pl->cap_stream) {
+        hipStream_t cs;
+        hip_check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
+        pl->cap_stream = cs;
+      }
+      hip_check(hipStreamBeginCapture((hipStream_t)pl->cap_stream, hipStreamCaptureModeRelaxed),
+                "hipStreamBeginCapture");
+      capturing = true;
+    }
+  }
+  hipStream_t ust = st;  // stream the uploads and results use
+  if (capturing) st = (hipStream_t)pl->cap_stream;
+
   // ------------------------------------------------------------ rows
-  for (int i = 0; i < R; ++i) {
+  for (int i = 0; i < R && !gexec; ++i) {
     const Level& lev = pl->levels[i];
     const int64_t nodes = (int64_t)t.parent[i].size();
     const void* Fprev = i == 0 ? pl->d_ones : (const void*)dF[(i - 1) % 2];
@@ -305,6 +332,7 @@ void run_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, si
           GemmLaunch g;
           g.prec = prec;
           g.cfg = s.kind == 1 ? s.cfg : 0;
+          g.split = (pl->opts.flags & PSIM_PLAN_SPLIT_ACC) ? 1 : 0;
           if (s.kind == 1 && w0.ptr_b) {
             g.Wb0 = w0.ptr_b;
             g.Wb1 = w1.ptr_b;
@@ -373,6 +401,17 @@ void run_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, si
       std::fflush(stderr);
     }
   }
+
+  if (capturing) {
+    hipGraph_t graph = nullptr;
+    const hipError_t e1 = hipStreamEndCapture(st, &graph);
+    st = ust;
+    hip_check(e1, "hipStreamEndCapture");
+    hip_check(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    (void)hipGraphDestroy(graph);
+    pl->graphs[gkey] = (void*)gexec;
+  }
+  if (gexec) hip_check(hipGraphLaunch(gexec, st), "hipGraphLaunch");
 
   // ------------------------------------------------------------ results
   const int64_t leaves = (int64_t)t.parent[R - 1].size();

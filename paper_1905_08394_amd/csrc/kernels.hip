@@ -111,8 +111,12 @@ struct V16<double> { typedef f64x2 t; static constexpr int n = 2; };
 // LDS A tile is the same interleaved (re, im) tile; each lane reads four
 // consecutive complex k (8 floats), splits re / im in registers and forms
 // re + im there.  W is packed as P[n][2k] = Re W[k][n], P[n][2k+1] = Im W[k][n].
-template <typename T, int BM, int BN, int BK, int AMODE, bool TRANS, int SCH>
-__global__ __launch_bounds__(256) void site_gemm(KArgs p) {
+// SPLIT (FP32 4M only): each stage of BK real k accumulates into a fresh
+// partial sum that is then added to the running accumulator, so the FP32
+// rounding of the K-loop sum grows like sqrt(BK) + sqrt(K/BK) instead of
+// sqrt(K) (about 3x smaller at K = 2048).
+template <typename T, int BM, int BN, int BK, int AMODE, bool TRANS, int SCH, bool SPLIT>
+__device__ __forceinline__ void site_gemm_body(const KArgs& p) {
   typedef Mfma<T> MF;
   typedef typename V16<T>::t vec_t;
   static_assert(SCH == 4 || (SCH == 3 && sizeof(T) == 4), "3M is FP32 only");
@@ -297,6 +301,15 @@ __global__ __launch_bounds__(256) void site_gemm(KArgs p) {
     const T* a_s = sA[cur];
     const T* b_s = sB[cur];
     if constexpr (SCH == 4) {
+      typename MF::acc_t part[SPLIT ? MBLK : 1][SPLIT ? NBLK : 1];
+      if constexpr (SPLIT) {
+#pragma unroll
+        for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < NBLK; ++bj)
+#pragma unroll
+            for (int r = 0; r < MF::NACC; ++r) part[bi][bj][r] = 0;
+      }
 #pragma unroll
       for (int g = 0; g < GROUPS; ++g) {
         typename MF::frag_t af[MBLK], bf[NBLK];
@@ -311,7 +324,18 @@ __global__ __launch_bounds__(256) void site_gemm(KArgs p) {
 #pragma unroll
           for (int bi = 0; bi < MBLK; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < NBLK; ++bj) MF::mma(af[bi], bf[bj], acc[bi][bj], s);
+            for (int bj = 0; bj < NBLK; ++bj) {
+              if constexpr (SPLIT)
+                MF::mma(af[bi], bf[bj], part[bi][bj], s);
+              else
+                MF::mma(af[bi], bf[bj], acc[bi][bj], s);
+            }
+      }
+      if constexpr (SPLIT) {
+#pragma unroll
+        for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < NBLK; ++bj) acc[bi][bj] += part[bi][bj];
       }
     } else {
       // groups of 8 complex k (16 floats); lane half h covers complex k 4h .. 4h+3
@@ -395,6 +419,17 @@ __global__ __launch_bounds__(256) void site_gemm(KArgs p) {
           }
         }
   }
+}
+
+template <typename T, int BM, int BN, int BK, int AMODE, bool TRANS, int SCH>
+__global__ __launch_bounds__(256) void site_gemm(KArgs p) {
+  site_gemm_body<T, BM, BN, BK, AMODE, TRANS, SCH, false>(p);
+}
+
+// split-accumulation variant, held to two waves per SIMD
+template <typename T, int BM, int BN, int BK, int AMODE, bool TRANS>
+__global__ __launch_bounds__(256, 2) void site_gemm_split(KArgs p) {
+  site_gemm_body<T, BM, BN, BK, AMODE, TRANS, 4, true>(p);
 }
 
 // ---------------------------------------------------------------- BF16x3
@@ -624,9 +659,12 @@ static const FCfg kFp32Configs[] = {{128, 128, 32}, {256, 128, 16}, {128, 256, 1
                                     {256, 256, 16}, {128, 128, 64}, {256, 128, 32}};
 int fp32_config_count() { return (int)(sizeof(kFp32Configs) / sizeof(kFp32Configs[0])); }
 
-template <typename T, int BM, int BN, int BK, int AMODE, bool TRANS, int SCH = 4>
+template <typename T, int BM, int BN, int BK, int AMODE, bool TRANS, int SCH = 4, bool SPLIT = false>
 static void launch(const KArgs& a, long long blocks, hipStream_t st) {
-  hipLaunchKernelGGL((site_gemm<T, BM, BN, BK, AMODE, TRANS, SCH>), dim3((unsigned)blocks), dim3(256), 0, st, a);
+  if constexpr (SPLIT)
+    hipLaunchKernelGGL((site_gemm_split<T, BM, BN, BK, AMODE, TRANS>), dim3((unsigned)blocks), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((site_gemm<T, BM, BN, BK, AMODE, TRANS, SCH>), dim3((unsigned)blocks), dim3(256), 0, st, a);
 }
 
 void launch_site_gemm(const GemmLaunch& g, void* stream) {
@@ -688,7 +726,17 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
     const bool even_base = ((uintptr_t)g.A % 16 == 0) && (g.sA_node % 2 == 0) && (g.sA_v % 2 == 0);
     const int mode = (g.K2 % 2 == 0 && even_base) ? ROWMAJOR
                      : (g.K2 == 1 && g.M % 2 == 0 && g.K1 > 1 && even_base) ? KMAJOR : GENERIC;
-    if (g.prec == PSIM_BF16X3 && mode == ROWMAJOR && !g.trans_out && g.Wb0) {
+    if (g.split && g.prec == PSIM_FP32_4M) {
+      if (mode == ROWMAJOR)
+        g.trans_out ? launch<float, 128, 128, 32, ROWMAJOR, true, 4, true>(b, blocks, st)
+                    : launch<float, 128, 128, 32, ROWMAJOR, false, 4, true>(b, blocks, st);
+      else if (mode == KMAJOR)
+        g.trans_out ? launch<float, 128, 128, 32, KMAJOR, true, 4, true>(b, blocks, st)
+                    : launch<float, 128, 128, 32, KMAJOR, false, 4, true>(b, blocks, st);
+      else
+        g.trans_out ? launch<float, 128, 128, 32, GENERIC, true, 4, true>(b, blocks, st)
+                    : launch<float, 128, 128, 32, GENERIC, false, 4, true>(b, blocks, st);
+    } else if (g.prec == PSIM_BF16X3 && mode == ROWMAJOR && !g.trans_out && g.Wb0) {
       // split-precision kernel on the pre-split planes
       b.W0 = g.Wb0;
       b.W1 = g.Wb1 ? g.Wb1 : g.Wb0;

@@ -381,6 +381,8 @@ psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o) {
 
 void free_plan(psim_plan_t* pl) {
   if (!pl) return;
+  for (auto& kv : pl->graphs) (void)hipGraphExecDestroy((hipGraphExec_t)kv.second);
+  if (pl->cap_stream) (void)hipStreamDestroy((hipStream_t)pl->cap_stream);
   for (auto& dm : pl->w) {
     if (dm.ptr) (void)hipFree(dm.ptr);
     if (dm.ptr_b) (void)hipFree(dm.ptr_b);

@@ -3,6 +3,7 @@
 
 #include <complex>
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -106,6 +107,10 @@ struct psim_plan_s {
   bool in_subbatch = false;              // scheduler re-entry guard
   bool profile = false;                  // time launches with events
   psim_kernel_stats prof[4] = {};
+  // PSIM_PLAN_GRAPH: instantiated graphs of the row sweep, keyed by workspace
+  // address and node count per level, and the stream they are captured on
+  std::map<std::vector<int64_t>, void*> graphs;
+  void* cap_stream = nullptr;
 };
 
 namespace psim {
@@ -136,6 +141,7 @@ struct GemmLaunch {
   int32_t trans_out = 0;
   int32_t beta = 0;
   int32_t cfg = 0;                    // tile candidate of the FP32 row-major kernel (0 = default)
+  int32_t split = 0;                  // FP32 4M: per-stage partial sums (more accurate K-loop)
   const void* Wb0 = nullptr;          // BF16x3: pre-split bf16 planes of W (hi then lo)
   const void* Wb1 = nullptr;
   int64_t ldwb = 0, planeb = 0;

@@ -47,8 +47,14 @@ def _golden(name):
     return g, np.array(g["bits"], dtype=np.uint8), np.array(g["amps_re"]) + 1j * np.array(g["amps_im"])
 
 
-AMP_BAR = {"fp64": 1e-10, "fp32": 1e-5, "fp32_3m": 1e-5, "bf16x3": 1e-3}
-ALL_PREC = ["fp64", "fp32", "fp32_3m", "bf16x3"]
+AMP_BAR = {"fp64": 1e-10, "fp32": 1e-5, "fp32s": 1e-5, "fp32_3m": 1e-5, "bf16x3": 1e-3}
+ALL_PREC = ["fp64", "fp32", "fp32s", "fp32_3m", "bf16x3"]   # fp32s: 4M with split accumulation
+
+
+def _plan(ps, peps, prec, **kw):
+    if prec == "fp32s":
+        return ps.Plan(peps, prec="fp32", split_acc=True, **kw)
+    return ps.Plan(peps, prec=prec, **kw)
 
 
 def _errors(a, r, n):
@@ -69,7 +75,7 @@ def _oracle_step(A, W, M, K1, K2, N):
     return np.stack(out)
 
 
-@pytest.mark.parametrize("prec", ALL_PREC)
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_3m", "bf16x3"])
 @pytest.mark.parametrize("M,K1,K2,N,batch,trans", [
     (300, 3, 8, 50, 2, False),     # row-major A, ragged M and N
     (260, 16, 1, 64, 1, False),    # K-major A (first site of a row)
@@ -126,7 +132,7 @@ def test_site_contraction_full_size_sampled(ps):
 
 def _run(ps, circuit, bits, prec, **kw):
     P = ps.Peps(circuit)
-    pl = ps.Plan(P, prec=prec, max_batch=len(bits), **kw)
+    pl = _plan(ps, P, prec, max_batch=len(bits), **kw)
     return pl.amplitudes(bits), pl
 
 
@@ -234,7 +240,7 @@ def test_6x6_d40_vs_oracle(ps, prec):
     assert c.sha256() == g["sha256"]
     say(f"6x6 (1+40+1), 16 bitstrings, {prec}")
     P = ps.Peps(c)
-    pl = ps.Plan(P, prec=prec, mem_budget=(128 if prec == "fp64" else 96) << 30, max_batch=16)
+    pl = _plan(ps, P, prec, mem_budget=(128 if prec == "fp64" else 96) << 30, max_batch=16)
     P.close()
     pl.tune(reps=1)
     a = pl.amplitudes(bits)
@@ -242,3 +248,20 @@ def test_6x6_d40_vs_oracle(ps, prec):
     say(f"6x6 {prec}: max eps_rel {np.max(erel):.3e}, median {np.median(erel):.3e}, max eps_rms {np.max(erms):.3e}")
     assert np.max(erel) <= AMP_BAR[prec]
     pl.close()
+
+
+def test_graph_replay_matches_eager(ps):
+    """PSIM_PLAN_GRAPH: captured row sweeps replayed several times, with eager
+    work in between, give bit-identical amplitudes."""
+    for lv, lh, d, n in ((5, 5, 16, 32), (4, 5, 24, 64), (3, 3, 8, 512)):
+        c = rqcgen.generate(lv, lh, d, 2)
+        P = ps.Peps(c)
+        eager = ps.Plan(P, prec="fp32", max_batch=n)
+        graph = ps.Plan(P, prec="fp32", max_batch=n, graph=True)
+        for rep in range(3):
+            bits = rqcgen.bitstrings(lv, lh, rep % 2, n) if n < 2 ** (lv * lh) else rqcgen.all_bitstrings(lv * lh)
+            want = eager.amplitudes(bits)
+            for _ in range(3):
+                got = graph.amplitudes(bits)
+                assert np.array_equal(got, want), (lv, lh, rep)
+                eager.amplitudes(bits[: max(1, n // 4)])
