@@ -120,6 +120,9 @@ __device__ __forceinline__ void site_gemm_body(const KArgs& p) {
   typedef Mfma<T> MF;
   typedef typename V16<T>::t vec_t;
   static_assert(SCH == 4 || (SCH == 3 && sizeof(T) == 4), "3M is FP32 only");
+  // transposed FP32 stores: compute C^T blocks so that lanes run along m and
+  // each lane stores (Re, Im) pairs contiguous with its neighbours
+  constexpr bool SWAP = TRANS && sizeof(T) == 4 && !SPLIT;
   constexpr int VN = V16<T>::n;          // reals per 16-byte vector
   constexpr int LDS_LD = BK + VN;        // padded row length (reals)
   constexpr int WM = BM / 2, WN = BN / 2;
@@ -327,6 +330,8 @@ __device__ __forceinline__ void site_gemm_body(const KArgs& p) {
             for (int bj = 0; bj < NBLK; ++bj) {
               if constexpr (SPLIT)
                 MF::mma(af[bi], bf[bj], part[bi][bj], s);
+              else if constexpr (SWAP)
+                MF::mma(bf[bj], af[bi], acc[bi][bj], s);  // block holds C^T: rows n', columns m
               else
                 MF::mma(af[bi], bf[bj], acc[bi][bj], s);
             }
@@ -365,9 +370,15 @@ __device__ __forceinline__ void site_gemm_body(const KArgs& p) {
           for (int bi = 0; bi < MBLK; ++bi)
 #pragma unroll
             for (int bj = 0; bj < NBLK3; ++bj) {
-              acc3[bi][bj][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[bi][s], br[bj][s], acc3[bi][bj][0], 0, 0, 0);
-              acc3[bi][bj][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[bi][s], bim[bj][s], acc3[bi][bj][1], 0, 0, 0);
-              acc3[bi][bj][2] = __builtin_amdgcn_mfma_f32_32x32x2f32(as[bi][s], bs[bj][s], acc3[bi][bj][2], 0, 0, 0);
+              if constexpr (SWAP) {  // C^T blocks: rows n, columns m
+                acc3[bi][bj][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(br[bj][s], ar[bi][s], acc3[bi][bj][0], 0, 0, 0);
+                acc3[bi][bj][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(bim[bj][s], ai[bi][s], acc3[bi][bj][1], 0, 0, 0);
+                acc3[bi][bj][2] = __builtin_amdgcn_mfma_f32_32x32x2f32(bs[bj][s], as[bi][s], acc3[bi][bj][2], 0, 0, 0);
+              } else {
+                acc3[bi][bj][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[bi][s], br[bj][s], acc3[bi][bj][0], 0, 0, 0);
+                acc3[bi][bj][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[bi][s], bim[bj][s], acc3[bi][bj][1], 0, 0, 0);
+                acc3[bi][bj][2] = __builtin_amdgcn_mfma_f32_32x32x2f32(as[bi][s], bs[bj][s], acc3[bi][bj][2], 0, 0, 0);
+              }
             }
       }
     }
@@ -379,7 +390,42 @@ __device__ __forceinline__ void site_gemm_body(const KArgs& p) {
   }
 
   // ------------------------------------------------------------ epilogue
-  if constexpr (SCH == 4) {
+  if constexpr (SWAP && SCH == 4) {
+    // block (bi, bj) holds C^T: lane -> m, registers r / r+1 -> (Re, Im) of one n
+#pragma unroll
+    for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < NBLK; ++bj)
+#pragma unroll
+        for (int r = 0; r < MF::NACC; r += 2) {
+          const long long m = m0 + wr * WM + bi * MF::MB + (lane & 31);
+          const long long nr = n0 + wc * WN + bj * MF::MB + MF::out_row(lane, r);  // even
+          if (m < p.M && nr < p.Nr) {
+            f32x2 v = {acc[bi][bj][r], acc[bi][bj][r + 1]};
+            f32x2* dst = (f32x2*)(C + 2 * ((nr >> 1) * p.M + m));
+            if (p.beta) v += *dst;
+            *dst = v;
+          }
+        }
+  } else if constexpr (SWAP && SCH == 3) {
+    const long long c0 = n0 / 2;
+#pragma unroll
+    for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < NBLK3; ++bj)
+#pragma unroll
+        for (int r = 0; r < MF::NACC; ++r) {
+          const long long m = m0 + wr * WM + bi * MF::MB + (lane & 31);
+          const long long n = c0 + wc * (WN / 2) + bj * MF::MB + MF::out_row(lane, r);
+          if (m < p.M && n < p.N) {
+            const T t1 = acc3[bi][bj][0][r], t2 = acc3[bi][bj][1][r], t3 = acc3[bi][bj][2][r];
+            f32x2 v = {t1 - t2, t3 - t1 - t2};
+            f32x2* dst = (f32x2*)(C + 2 * (n * p.M + m));
+            if (p.beta) v += *dst;
+            *dst = v;
+          }
+        }
+  } else if constexpr (SCH == 4) {
 #pragma unroll
     for (int bi = 0; bi < MBLK; ++bi)
 #pragma unroll
@@ -779,6 +825,17 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
         case 5: launch<float, 256, 128, 32, ROWMAJOR, false>(b, bl, st); break;
         default: fail(PSIM_EINVAL, "unknown kernel config");
       }
+    } else if (g.trans_out && g.N <= 32 && mode != GENERIC) {
+      // last site of a row: few output columns, tall M -> 256 x 64 tiles
+      b.MT = (b.M + 256 - 1) / 256;
+      b.NT = (b.Nr + 64 - 1) / 64;
+      b.T = b.MT * b.NT * Z;
+      const long long bl = (b.T + 7) / 8 * 8;
+      if (bl > 0x7fffffffLL) fail(PSIM_EUNSUPPORTED, "grid too large");
+      if (mode == ROWMAJOR)
+        launch<float, 256, 64, 16, ROWMAJOR, true>(b, bl, st);
+      else
+        launch<float, 256, 64, 16, KMAJOR, true>(b, bl, st);
     } else if (mode == ROWMAJOR)
       g.trans_out ? launch<float, 128, 128, 32, ROWMAJOR, true>(b, blocks, st)
                   : launch<float, 128, 128, 32, ROWMAJOR, false>(b, blocks, st);

@@ -80,12 +80,33 @@ def big():
             "variant_cols": cols, "seconds": time.time() - t})
 
 
+def fig2():
+    """8x8 (1+25+1), the lattice of the paper's Porter-Thomas figure: eight
+    amplitudes by the oracle's row scheme (largest tensor 8^8 x 16 elements)."""
+    c = rqcgen.generate(8, 8, 25, 0)
+    bits = rqcgen.bitstrings(8, 8, 0, 8)
+    t = time.time()
+    P = peps.build(c)
+    amps = []
+    for i, b in enumerate(bits):
+        amps.append(peps.amplitude(P, b, "rows"))
+        print(f"[{time.time() - t:6.0f}s] 8x8 amplitude {i + 1}/8", flush=True)
+    # an independent order for the first two
+    for i in range(2):
+        a2 = peps.amplitude(P, bits[i], "rows_bu")
+        assert abs(a2 - amps[i]) <= 1e-12 * abs(amps[i]), (a2, amps[i])
+    _write("rqc_8x8_d25_s0.json", c, bits, np.array(amps), "peps-row-scheme", {"seconds": time.time() - t})
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--big", action="store_true")
     ap.add_argument("--only-big", action="store_true")
+    ap.add_argument("--fig2", action="store_true", help="8x8 (1+25+1) amplitudes")
     a = ap.parse_args()
-    if not a.only_big:
+    if a.fig2:
+        fig2()
+    elif not a.only_big:
         small()
     if a.big or a.only_big:
         big()

@@ -83,6 +83,9 @@ def _oracle_step(A, W, M, K1, K2, N):
     (129, 4, 16, 1, 1, True),      # last site: transposed store, N = 1
     (1, 1, 1, 7, 3, False),        # degenerate
     (512, 32, 32, 64, 1, True),    # full-depth K = 1024
+    (258, 8, 1, 20, 2, True),      # K-major A with a transposed store (single-column lattice sites)
+    (99, 3, 3, 5, 1, True),        # generic loader, transposed store
+    (1000, 2, 32, 32, 1, True),    # last site of a 6x6 row: v chunk 2, N = 32
 ])
 def test_site_contraction_parity(ps, prec, M, K1, K2, N, batch, trans):
     import torch
@@ -265,3 +268,31 @@ def test_graph_replay_matches_eager(ps):
                 got = graph.amplitudes(bits)
                 assert np.array_equal(got, want), (lv, lh, rep)
                 eager.amplitudes(bits[: max(1, n // 4)])
+
+
+# ---------------------------------------------------------------- 8x8 (1+25+1)
+
+@pytest.mark.timeout(600)
+def test_8x8_d25_vs_oracle_and_porter_thomas(ps):
+    """The lattice and depth of the paper's Porter-Thomas figure: eight
+    amplitudes against the oracle (FP32 eps_rms <= 1e-5), then 2048 random
+    bitstrings whose scaled probabilities x = 2^64 |a|^2 must follow Exp(1)
+    (mean, second moment and KS statistic within sampling error)."""
+    from oracle import stats
+    g, bits, ref = _golden("rqc_8x8_d25_s0.json")
+    c = rqcgen.generate(8, 8, 25, 0)
+    assert c.sha256() == g["sha256"]
+    P = ps.Peps(c)
+    pl = ps.Plan(P, prec="fp32", max_batch=2048, mem_budget=64 << 30)
+    a = pl.amplitudes(bits)
+    erel, erms = _errors(a, ref, 64)
+    say(f"8x8 fp32 vs oracle: max eps_rms {np.max(erms):.3e}, max eps_rel {np.max(erel):.3e}")
+    assert np.max(erms) <= 1e-5
+    sample = rqcgen.bitstrings(8, 8, 1, 2048)
+    x = stats.scaled_probabilities(pl.amplitudes(sample), 64)
+    s = stats.porter_thomas_summary(x)
+    say(f"8x8 Porter-Thomas over 2048 amplitudes: {s}")
+    # sampling error of the mean of Exp(1) over 2048 draws is 0.022
+    assert abs(s["mean"] - 1) < 0.1
+    assert abs(s["second_moment"] - 2) < 0.5
+    assert s["ks_pvalue"] > 1e-3
