@@ -166,6 +166,46 @@ def counters_program(prec="fp32_3m", reps=3):
                       2 * batch * K1 * M * K2 * 8 + K1 * K2 * N * 4 * 4, "reps": reps}), flush=True)
 
 
+def fig2_program(args):
+    """The paper's Fig. 2 experiment on our synthetic circuits: amplitudes of
+    random bitstrings of an 8x8 (1+25+1) circuit (the paper used 10 000; the
+    default here is 2048), the statistics of x = 2^N |a|^2
+    against the Porter-Thomas law, and a histogram of ln x next to the
+    log-transformed Porter-Thomas density exp(y - e^y)."""
+    import numpy as np
+    import torch
+    import paper_1905_08394_amd as ps
+    import rqcgen
+    from oracle import stats
+    n = args.fig2_count
+    c = rqcgen.generate(8, 8, 25, 0)
+    bits = rqcgen.bitstrings(8, 8, 7, n)
+    peps = ps.Peps(c)
+    chunk = 512
+    plan = ps.Plan(peps, prec=args.prec, max_batch=chunk, mem_budget=args.mem_gib << 30)
+    plan.workspace()
+    plan.amplitudes(bits[:16])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    parts = []
+    for s0 in range(0, n, chunk):
+        parts.append(plan.amplitudes(bits[s0:s0 + chunk]))
+        log(f"fig2 {args.prec}: {min(n, s0 + chunk)}/{n} amplitudes at {time.perf_counter() - t0:.1f}s")
+    amps = np.concatenate(parts)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    x = stats.scaled_probabilities(amps, 64)
+    summ = stats.porter_thomas_summary(x)
+    edges = np.linspace(-8, 3, 23)
+    hist, _ = np.histogram(np.log(x), bins=edges, density=True)
+    mids = 0.5 * (edges[1:] + edges[:-1])
+    print(json.dumps({"workload": f"8x8 (1+25+1), seed 0, {n} random bitstrings", "prec": args.prec,
+                      "seconds": t, "s_per_amplitude": t / n, "cmac_per_amplitude": plan.stats()["cmac_per_amplitude"],
+                      "porter_thomas": summ,
+                      "log_histogram": [[round(float(m), 3), round(float(h), 4), round(float(stats.log_pt_density(m)), 4)]
+                                        for m, h in zip(mids, hist)]}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,7 +222,13 @@ def main():
     ap.add_argument("--split-acc", action="store_true", help="FP32 4M with per-stage partial sums")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--counters", action="store_true", help="short program for rocprofv3 --pmc passes")
+    ap.add_argument("--fig2", action="store_true", help="8x8 (1+25+1) Porter-Thomas experiment")
+    ap.add_argument("--fig2-count", type=int, default=2048)
     args = ap.parse_args()
+    if args.fig2:
+        args.mem_gib = args.mem_gib or 64
+        fig2_program(args)
+        return
     if args.counters:
         counters_program(args.prec)
         return
