@@ -82,7 +82,8 @@ typedef struct {
   int32_t max_batch;          /* most bitstrings per psim_amplitudes call; 0 = 1 */
   int32_t sweep;              /* 0 = along the short side (Fig. S2(a)), 1 = rows, 2 = columns */
   int32_t device;             /* HIP device ordinal */
-  int32_t reserved;
+  int32_t tile_cfg;           /* FP32 interior-site tile candidate: 0 = default, k > 0 = candidate k
+                                 (4M: 1..5, 3M: 1..2); psim_tune may replace it */
 } psim_plan_opts;
 
 typedef struct {

@@ -43,7 +43,7 @@ class _Gate(ctypes.Structure):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("flags", ctypes.c_int32), ("mem_budget_bytes", ctypes.c_uint64),
                 ("max_batch", ctypes.c_int32), ("sweep", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("tile_cfg", ctypes.c_int32)]
 
 
 class PlanStats(ctypes.Structure):
@@ -155,11 +155,12 @@ class Plan:
     """Contraction plan with packed site matrices on the device (psim_plan)."""
 
     def __init__(self, peps: Peps, prec: str = "fp32", mem_budget: int = 0, max_batch: int = 1, sweep: int = 0,
-                 device: int = 0, host_only: bool = False, split_acc: bool = False, graph: bool = False):
+                 device: int = 0, host_only: bool = False, split_acc: bool = False, graph: bool = False,
+                 tile_cfg: int = 0):
         L = lib()
         flags = (PLAN_HOST_ONLY if host_only else 0) | (PLAN_SPLIT_ACC if split_acc else 0) | \
             (PLAN_GRAPH if graph else 0)
-        o = PlanOpts(PREC[prec], flags, mem_budget, max_batch, sweep, device, 0)
+        o = PlanOpts(PREC[prec], flags, mem_budget, max_batch, sweep, device, tile_cfg)
         h = ctypes.c_void_p()
         _check(L.psim_plan(peps._h, ctypes.byref(o), ctypes.byref(h)))
         self._h = h

@@ -109,7 +109,9 @@ void tune_plan(psim_plan_t* pl, void* ws, size_t ws_bytes, void* stream, int rep
   if (!ws || ws_bytes < pl->ws_total) fail(PSIM_EINVAL, "workspace is NULL or smaller than the plan needs");
   if (reps < 1) fail(PSIM_EINVAL, "reps must be at least 1");
   if (best_ms) *best_ms = 0;
-  if (pl->opts.prec != PSIM_FP32_4M || (pl->opts.flags & PSIM_PLAN_SPLIT_ACC)) return;
+  if ((pl->opts.prec != PSIM_FP32_4M && pl->opts.prec != PSIM_FP32_3M) || (pl->opts.flags & PSIM_PLAN_SPLIT_ACC))
+    return;
+  const int ncfg = pl->opts.prec == PSIM_FP32_3M ? fp32_3m_config_count() : fp32_config_count();
   hip_check(hipSetDevice(pl->opts.device), "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
   WsLayout W = layout(*pl, ws);
@@ -141,7 +143,7 @@ void tune_plan(psim_plan_t* pl, void* ws, size_t ws_bytes, void* stream, int rep
     g.sC_v = s.g_out; g.sC_node = c * s.g_out;
     int best = 0;
     double best_t = 1e300;
-    for (int cfg = 0; cfg < fp32_config_count(); ++cfg) {
+    for (int cfg = 0; cfg < ncfg; ++cfg) {
       g.cfg = cfg;
       launch_site_gemm(g, st);  // warm
       hip_check(hipEventRecord(a, st), "hipEventRecord");
@@ -330,7 +332,7 @@ void run_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, si
           const DevMatrix& w0 = pl->w[((size_t)i * L + j) * 2];
           const DevMatrix& w1 = pl->w[((size_t)i * L + j) * 2 + 1];
           GemmLaunch g;
-          g.prec = prec;
+          g.prec = (prec == PSIM_FP32_3M && s.kind == 2) ? PSIM_FP32_4M : prec;  // see the packing
           g.cfg = s.kind == 1 ? s.cfg : 0;
           g.split = (pl->opts.flags & PSIM_PLAN_SPLIT_ACC) ? 1 : 0;
           if (s.kind == 1 && w0.ptr_b) {

@@ -40,7 +40,10 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-enum AMode { ROWMAJOR = 0, KMAJOR = 1, GENERIC = 2 };
+// ROWFAST: ROWMAJOR for launches where every tile is interior (M % BM == 0,
+// 2K % BK == 0) and a stage never straddles two k1 values (2 K2 % BK == 0):
+// no bounds checks, one k1/k2 split per stage.
+enum AMode { ROWMAJOR = 0, KMAJOR = 1, GENERIC = 2, ROWFAST = 3 };
 
 struct KArgs {
   const void* A;
@@ -165,12 +168,22 @@ __device__ __forceinline__ void site_gemm_body(const KArgs& p) {
   const long long sK1 = p.M * p.K2;    // complex stride of k1 in A
   const unsigned K2u = (unsigned)p.K2;
 
-  vec_t ra[AMODE == GENERIC ? 1 : A_VECS];
+  vec_t ra[AMODE == GENERIC ? 1 : A_VECS];  // ROWMAJOR / ROWFAST / KMAJOR staging
   T rc[AMODE == GENERIC ? A_CPLX * 2 : 1];
   vec_t rb[B_VECS];
 
   auto load_a = [&](long long kr0) {
-    if constexpr (AMODE == ROWMAJOR) {
+    if constexpr (AMODE == ROWFAST) {
+      const long long k = kr0 >> 1;
+      const long long k1 = k / p.K2, k2 = k - k1 * p.K2;
+      const T* base = A + 2 * (k1 * sK1 + m0 * p.K2 + k2);
+#pragma unroll
+      for (int it = 0; it < A_VECS; ++it) {
+        const int lin = it * 256 + tid;
+        const int row = lin / (BK / VN), kq = lin % (BK / VN);
+        ra[it] = *(const vec_t*)(base + 2 * (long long)row * p.K2 + kq * VN);
+      }
+    } else if constexpr (AMODE == ROWMAJOR) {
 #pragma unroll
       for (int it = 0; it < A_VECS; ++it) {
         const int lin = it * 256 + tid;
@@ -216,7 +229,7 @@ __device__ __forceinline__ void site_gemm_body(const KArgs& p) {
   };
   auto store_a = [&](int buf) {
     T* s = sA[buf];
-    if constexpr (AMODE == ROWMAJOR) {
+    if constexpr (AMODE == ROWMAJOR || AMODE == ROWFAST) {
 #pragma unroll
       for (int it = 0; it < A_VECS; ++it) {
         const int lin = it * 256 + tid;
@@ -490,7 +503,7 @@ __global__ __launch_bounds__(256, 2) void site_gemm_split(KArgs p) {
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-template <int BM, int BN>
+template <int BM, int BN, bool FAST>
 __global__ __launch_bounds__(256) void site_gemm_bf16x3(KArgs p) {
   constexpr int BK = 16;                 // reals per stage: one MFMA k-step
   constexpr int LD = BK + 8;             // padded LDS row (bf16), 48 bytes
@@ -534,18 +547,30 @@ __global__ __launch_bounds__(256) void site_gemm_bf16x3(KArgs p) {
   f32x4 rbh[B_VECS], rbl[B_VECS];  // 16 bytes = 8 bf16 each
 
   auto load = [&](long long kr0) {
+    if constexpr (FAST) {  // interior tile, stage inside one k1 (see ROWFAST)
+      const long long k = kr0 >> 1;
+      const long long k1 = k / p.K2, k2 = k - k1 * p.K2;
+      const float* base = A + 2 * (k1 * sK1 + m0 * p.K2 + k2);
 #pragma unroll
-    for (int it = 0; it < A_VECS; ++it) {
-      const int lin = it * 256 + tid;
-      const int row = lin / (BK / 4), kq = lin % (BK / 4);
-      const long long m = m0 + row, kr = kr0 + kq * 4;
-      f32x4 v = {};
-      if (m < p.M && kr < p.Kr) {
-        const unsigned k = (unsigned)(kr >> 1);
-        const unsigned k1 = k / K2u, k2 = k - k1 * K2u;
-        v = *(const f32x4*)(A + 2 * ((long long)k1 * sK1 + m * p.K2 + k2));
+      for (int it = 0; it < A_VECS; ++it) {
+        const int lin = it * 256 + tid;
+        const int row = lin / (BK / 4), kq = lin % (BK / 4);
+        ra[it] = *(const f32x4*)(base + 2 * (long long)row * p.K2 + kq * 4);
       }
-      ra[it] = v;
+    } else {
+#pragma unroll
+      for (int it = 0; it < A_VECS; ++it) {
+        const int lin = it * 256 + tid;
+        const int row = lin / (BK / 4), kq = lin % (BK / 4);
+        const long long m = m0 + row, kr = kr0 + kq * 4;
+        f32x4 v = {};
+        if (m < p.M && kr < p.Kr) {
+          const unsigned k = (unsigned)(kr >> 1);
+          const unsigned k1 = k / K2u, k2 = k - k1 * K2u;
+          v = *(const f32x4*)(A + 2 * ((long long)k1 * sK1 + m * p.K2 + k2));
+        }
+        ra[it] = v;
+      }
     }
 #pragma unroll
     for (int it = 0; it < B_VECS; ++it) {
@@ -704,6 +729,10 @@ struct FCfg {
 static const FCfg kFp32Configs[] = {{128, 128, 32}, {256, 128, 16}, {128, 256, 16},
                                     {256, 256, 16}, {128, 128, 64}, {256, 128, 32}};
 int fp32_config_count() { return (int)(sizeof(kFp32Configs) / sizeof(kFp32Configs[0])); }
+// 3M candidates: 0 = 128 x 128 x 32 (two waves per SIMD), 1 = 256 x 128 x 32,
+// 2 = 128 x 256 x 32 (one wave per SIMD, twice the work per LDS stage)
+static const FCfg kFp32_3mConfigs[] = {{128, 128, 32}, {256, 128, 32}, {128, 256, 32}};
+int fp32_3m_config_count() { return (int)(sizeof(kFp32_3mConfigs) / sizeof(kFp32_3mConfigs[0])); }
 
 template <typename T, int BM, int BN, int BK, int AMODE, bool TRANS, int SCH = 4, bool SPLIT = false>
 static void launch(const KArgs& a, long long blocks, hipStream_t st) {
@@ -772,8 +801,15 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
     const bool even_base = ((uintptr_t)g.A % 16 == 0) && (g.sA_node % 2 == 0) && (g.sA_v % 2 == 0);
     const int mode = (g.K2 % 2 == 0 && even_base) ? ROWMAJOR
                      : (g.K2 == 1 && g.M % 2 == 0 && g.K1 > 1 && even_base) ? KMAJOR : GENERIC;
+    // interior-only tiles of bm rows and bk reals per stage
+    auto fast = [&](int bm, int bk) {
+      return mode == ROWMAJOR && g.M % bm == 0 && (2 * g.K1 * g.K2) % bk == 0 && (2 * g.K2) % bk == 0;
+    };
     if (g.split && g.prec == PSIM_FP32_4M) {
-      if (mode == ROWMAJOR)
+      if (fast(128, 32))
+        g.trans_out ? launch<float, 128, 128, 32, ROWFAST, true, 4, true>(b, blocks, st)
+                    : launch<float, 128, 128, 32, ROWFAST, false, 4, true>(b, blocks, st);
+      else if (mode == ROWMAJOR)
         g.trans_out ? launch<float, 128, 128, 32, ROWMAJOR, true, 4, true>(b, blocks, st)
                     : launch<float, 128, 128, 32, ROWMAJOR, false, 4, true>(b, blocks, st);
       else if (mode == KMAJOR)
@@ -795,12 +831,35 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
       b.T = b.MT * b.NT * Z;
       const long long bl = (b.T + 7) / 8 * 8;
       if (bl > 0x7fffffffLL) fail(PSIM_EUNSUPPORTED, "grid too large");
-      if (big)
-        hipLaunchKernelGGL((site_gemm_bf16x3<256, 256>), dim3((unsigned)bl), dim3(256), 0, st, b);
+      const bool f = g.M % bm == 0 && (2 * g.K1 * g.K2) % 16 == 0 && (2 * g.K2) % 16 == 0;
+      if (big && f)
+        hipLaunchKernelGGL((site_gemm_bf16x3<256, 256, true>), dim3((unsigned)bl), dim3(256), 0, st, b);
+      else if (big)
+        hipLaunchKernelGGL((site_gemm_bf16x3<256, 256, false>), dim3((unsigned)bl), dim3(256), 0, st, b);
+      else if (f)
+        hipLaunchKernelGGL((site_gemm_bf16x3<128, 256, true>), dim3((unsigned)bl), dim3(256), 0, st, b);
       else
-        hipLaunchKernelGGL((site_gemm_bf16x3<128, 256>), dim3((unsigned)bl), dim3(256), 0, st, b);
+        hipLaunchKernelGGL((site_gemm_bf16x3<128, 256, false>), dim3((unsigned)bl), dim3(256), 0, st, b);
+    } else if (g.prec == PSIM_FP32_3M && !g.trans_out && g.cfg > 0 && mode == ROWMAJOR) {
+      const FCfg& c = kFp32_3mConfigs[g.cfg];
+      b.MT = (b.M + c.bm - 1) / c.bm;
+      b.NT = (b.Nr + c.bn - 1) / c.bn;
+      b.T = b.MT * b.NT * Z;
+      const long long bl = (b.T + 7) / 8 * 8;
+      if (bl > 0x7fffffffLL) fail(PSIM_EUNSUPPORTED, "grid too large");
+      const bool f = fast(c.bm, c.bk);
+      switch (g.cfg) {
+        case 1: f ? launch<float, 256, 128, 32, ROWFAST, false, 3>(b, bl, st)
+                  : launch<float, 256, 128, 32, ROWMAJOR, false, 3>(b, bl, st); break;
+        case 2: f ? launch<float, 128, 256, 32, ROWFAST, false, 3>(b, bl, st)
+                  : launch<float, 128, 256, 32, ROWMAJOR, false, 3>(b, bl, st); break;
+        default: fail(PSIM_EINVAL, "unknown kernel config");
+      }
     } else if (g.prec == PSIM_FP32_3M) {
-      if (mode == ROWMAJOR)
+      if (fast(128, 32))
+        g.trans_out ? launch<float, 128, 128, 32, ROWFAST, true, 3>(b, blocks, st)
+                    : launch<float, 128, 128, 32, ROWFAST, false, 3>(b, blocks, st);
+      else if (mode == ROWMAJOR)
         g.trans_out ? launch<float, 128, 128, 32, ROWMAJOR, true, 3>(b, blocks, st)
                     : launch<float, 128, 128, 32, ROWMAJOR, false, 3>(b, blocks, st);
       else if (mode == KMAJOR)
@@ -817,12 +876,18 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
       b.T = b.MT * b.NT * Z;
       const long long bl = (b.T + 7) / 8 * 8;
       if (bl > 0x7fffffffLL) fail(PSIM_EUNSUPPORTED, "grid too large");
+      const bool f = fast(c.bm, c.bk);
       switch (g.cfg) {
-        case 1: launch<float, 256, 128, 16, ROWMAJOR, false>(b, bl, st); break;
-        case 2: launch<float, 128, 256, 16, ROWMAJOR, false>(b, bl, st); break;
-        case 3: launch<float, 256, 256, 16, ROWMAJOR, false>(b, bl, st); break;
-        case 4: launch<float, 128, 128, 64, ROWMAJOR, false>(b, bl, st); break;
-        case 5: launch<float, 256, 128, 32, ROWMAJOR, false>(b, bl, st); break;
+        case 1: f ? launch<float, 256, 128, 16, ROWFAST, false>(b, bl, st)
+                  : launch<float, 256, 128, 16, ROWMAJOR, false>(b, bl, st); break;
+        case 2: f ? launch<float, 128, 256, 16, ROWFAST, false>(b, bl, st)
+                  : launch<float, 128, 256, 16, ROWMAJOR, false>(b, bl, st); break;
+        case 3: f ? launch<float, 256, 256, 16, ROWFAST, false>(b, bl, st)
+                  : launch<float, 256, 256, 16, ROWMAJOR, false>(b, bl, st); break;
+        case 4: f ? launch<float, 128, 128, 64, ROWFAST, false>(b, bl, st)
+                  : launch<float, 128, 128, 64, ROWMAJOR, false>(b, bl, st); break;
+        case 5: f ? launch<float, 256, 128, 32, ROWFAST, false>(b, bl, st)
+                  : launch<float, 256, 128, 32, ROWMAJOR, false>(b, bl, st); break;
         default: fail(PSIM_EINVAL, "unknown kernel config");
       }
     } else if (g.trans_out && g.N <= 32 && mode != GENERIC) {
@@ -836,7 +901,10 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
         launch<float, 256, 64, 16, ROWMAJOR, true>(b, bl, st);
       else
         launch<float, 256, 64, 16, KMAJOR, true>(b, bl, st);
-    } else if (mode == ROWMAJOR)
+    } else if (fast(128, 32))
+      g.trans_out ? launch<float, 128, 128, 32, ROWFAST, true>(b, blocks, st)
+                  : launch<float, 128, 128, 32, ROWFAST, false>(b, blocks, st);
+    else if (mode == ROWMAJOR)
       g.trans_out ? launch<float, 128, 128, 32, ROWMAJOR, true>(b, blocks, st)
                   : launch<float, 128, 128, 32, ROWMAJOR, false>(b, blocks, st);
     else if (mode == KMAJOR)

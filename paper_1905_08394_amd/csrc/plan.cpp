@@ -183,6 +183,10 @@ psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o) {
     fail(PSIM_EUNSUPPORTED, "precision " + std::to_string(opts.prec) + " is not available in this build");
   if (opts.mem_budget_bytes == 0) opts.mem_budget_bytes = 200ull << 30;
   if (opts.max_batch <= 0) opts.max_batch = 1;
+  if (opts.tile_cfg < 0 ||
+      (opts.tile_cfg > 0 && !((opts.prec == PSIM_FP32_4M && opts.tile_cfg < fp32_config_count()) ||
+                              (opts.prec == PSIM_FP32_3M && opts.tile_cfg < fp32_3m_config_count()))))
+    fail(PSIM_EINVAL, "tile_cfg " + std::to_string(opts.tile_cfg) + " is not a candidate of this precision");
   int sweep = opts.sweep;
   if (sweep == 0) sweep = (P->lh <= P->lv) ? 1 : 2;
   if (sweep != 1 && sweep != 2) fail(PSIM_EINVAL, "sweep must be 0, 1 or 2");
@@ -240,6 +244,7 @@ psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o) {
           st.M = M;
           st.N = (int64_t)c.dd * c.dr;
           st.g_out = st.M * st.N;
+          st.cfg = opts.tile_cfg;
           lev.Gmax = std::max(lev.Gmax, st.g_out);
           if (!(i == 0 && j == 0)) cmac += (double)lev.Dv * st.M * st.K1 * st.K2 * st.N;
         }
@@ -344,7 +349,11 @@ psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o) {
           dm.exp2 = exponent_of_max(W);
           const double sc = std::ldexp(1.0, -dm.exp2);  // exact power of two
           for (cd& x : W) x *= sc;
-          const int pack_prec = opts.prec == PSIM_BF16X3 ? PSIM_FP32_4M : opts.prec;
+          // the last site of a row always runs the 4M transposed-store kernel
+          // in FP32 plans (its 256 x 64 tile suits the few output columns)
+          const bool last = (j == L - 1);
+          const int pack_prec =
+              (opts.prec == PSIM_BF16X3 || (opts.prec == PSIM_FP32_3M && last)) ? PSIM_FP32_4M : opts.prec;
           pack_site_matrix(pack_prec, W.data(), (int64_t)c.du * c.dl, (int64_t)c.dd * c.dr, buf, dm.ld);
           pl->weights_bytes += buf.size();
           if (!pl->host_only) {

@@ -147,6 +147,7 @@ struct GemmLaunch {
   int64_t ldwb = 0, planeb = 0;
 };
 int fp32_config_count();
+int fp32_3m_config_count();
 void launch_site_gemm(const GemmLaunch& g, void* stream);
 void launch_rowscale(int prec, void* F, int64_t elems_per_node, int64_t nodes, const int32_t* parent,
                      const int32_t* exp_prev, int32_t* exp_cur, uint32_t* scratch_max, void* stream);

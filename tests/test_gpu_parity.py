@@ -86,6 +86,7 @@ def _oracle_step(A, W, M, K1, K2, N):
     (258, 8, 1, 20, 2, True),      # K-major A with a transposed store (single-column lattice sites)
     (99, 3, 3, 5, 1, True),        # generic loader, transposed store
     (1000, 2, 32, 32, 1, True),    # last site of a 6x6 row: v chunk 2, N = 32
+    (256, 4, 16, 48, 2, False),    # interior tiles only: the bounds-check-free loader
 ])
 def test_site_contraction_parity(ps, prec, M, K1, K2, N, batch, trans):
     import torch
@@ -296,3 +297,17 @@ def test_8x8_d25_vs_oracle_and_normalisation(ps):
     s = stats.porter_thomas_summary(x)
     say(f"8x8 statistics over 2048 amplitudes: {s}")
     assert abs(s["mean"] - 1) < 5 * np.sqrt(max(s["second_moment"] - 1, 1e-12) / 2048)
+
+
+@pytest.mark.parametrize("prec,cfg", [("fp32", c) for c in range(1, 6)] + [("fp32_3m", c) for c in range(1, 3)])
+def test_tile_candidates(ps, prec, cfg):
+    """Every tile candidate the autotuner may pick gives the oracle's amplitudes
+    (5x5 (1+32+1), 256 bitstrings; FP32 bar eps_rms <= 1e-5)."""
+    g, bits, ref = _golden("rqc_5x5_d32_s0.json")
+    c = rqcgen.generate(5, 5, 32, 0)
+    P = ps.Peps(c)
+    pl = ps.Plan(P, prec=prec, max_batch=256, mem_budget=48 << 30, tile_cfg=cfg)
+    assert pl.stats()["hot_cfg"] == cfg
+    a = pl.amplitudes(bits)
+    _, erms = _errors(a, ref, 25)
+    assert np.max(erms) <= AMP_BAR[prec]

@@ -115,3 +115,12 @@ def test_host_only_plan_cannot_run(ps):
     bits = (ctypes.c_uint8 * 9)()
     st = L.psim_amplitudes(pl._h, bits, 1, ctypes.c_void_p(16), 1 << 20, None, out)
     assert st == ps.PSIM_EINVAL
+
+
+def test_tile_cfg_validation(ps):
+    P = ps.Peps(rqcgen.generate(3, 3, 8, 0))
+    assert ps.Plan(P, prec="fp32", host_only=True, tile_cfg=5).stats()["hot_cfg"] in (0, 5)
+    for prec, bad in (("fp32", 6), ("fp32_3m", 3), ("fp64", 1), ("fp32", -1)):
+        with pytest.raises(ps.PsimError) as e:
+            ps.Plan(P, prec=prec, host_only=True, tile_cfg=bad)
+        assert e.value.status == ps.PSIM_EINVAL
