@@ -184,6 +184,45 @@ typedef struct {
 
 psim_status psim_profile(psim_plan_t *plan, int32_t op, psim_kernel_stats *out);
 
+/* Several plans run together: different circuits, lattice sizes and depths
+ * in one sweep (the batching of independent amplitude computations that the
+ * paper's row scheme allows, supplement S-II, Fig. S2(a); every plan's
+ * amplitude is still eq. (7)).  The plans are borrowed: they must outlive the
+ * group and not be used by another call while a group call runs.  The group
+ * owns a small device array of launch descriptors (psim_group_stats).
+ * Errors: EINVAL for a NULL or empty plan list, a host-only plan, or plans
+ * on different devices; ENOMEM / EDEVICE on allocation failure. */
+typedef struct psim_group_s psim_group_t;
+
+typedef struct {
+  int32_t n_plans;
+  uint64_t descriptor_bytes;   /* device memory the group holds */
+  int64_t grouped_launches;    /* merged launches issued so far (several problems, one grid) */
+} psim_group_stats;
+
+psim_status psim_group(psim_plan_t *const *plans, int32_t n_plans, psim_group_t **out);
+
+psim_status psim_group_info(const psim_group_t *group, psim_group_stats *out);
+
+/* Amplitudes for every plan of the group in one interleaved sweep.  Arrays
+ * are indexed by plan: bits[p] (host, n_bitstrings[p] * lv*lh bytes of plan
+ * p), d_workspaces[p] (device, at least workspace_bytes[p] >= that plan's
+ * psim_plan_stats.workspace_bytes; the workspaces of plans with bitstrings
+ * must not overlap), out_amp[p] (host, 2*n_bitstrings[p] doubles).  A plan
+ * with n_bitstrings[p] = 0 is skipped.  Step k of the sweep issues the k-th
+ * device operation of every plan; FP32 (4M / 3M, default tiles, no split
+ * accumulation) site contractions of one step that use the same kernel are
+ * merged into one launch over all their tiles, everything else is launched
+ * per plan.  Each plan's results equal psim_amplitudes' bit for bit.
+ * Enqueues on hip_stream and synchronises it.
+ * Errors: as psim_amplitudes, for the first failing plan (its index in the
+ * message); EINVAL for overlapping workspaces. */
+psim_status psim_group_amplitudes(psim_group_t *group, const uint8_t *const *bits, const size_t *n_bitstrings,
+                                  void *const *d_workspaces, const size_t *workspace_bytes, void *hip_stream,
+                                  double *const *out_amp);
+
+void psim_group_free(psim_group_t *group);
+
 /* Message for the last failing call on this thread; valid until the next
  * psim_* call on the same thread.  Never NULL. */
 const char *psim_last_error(void);

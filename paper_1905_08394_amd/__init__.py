@@ -24,8 +24,8 @@ PLAN_HOST_ONLY = 1
 PLAN_SPLIT_ACC = 2
 PLAN_GRAPH = 4
 EXPORTED = ("psim_build", "psim_peps_info", "psim_peps_free", "psim_plan", "psim_plan_info", "psim_plan_free",
-            "psim_amplitudes", "psim_contract_site", "psim_tune", "psim_profile", "psim_last_error",
-            "psim_version")
+            "psim_amplitudes", "psim_contract_site", "psim_tune", "psim_profile", "psim_group", "psim_group_info",
+            "psim_group_amplitudes", "psim_group_free", "psim_last_error", "psim_version")
 KERNEL_CLASSES = ("first_site", "interior_site", "last_site", "rescale")
 
 
@@ -61,6 +61,11 @@ class KernelStats(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double), ("launches", ctypes.c_int64), ("cmac", ctypes.c_double)]
 
 
+class GroupStats(ctypes.Structure):
+    _fields_ = [("n_plans", ctypes.c_int32), ("descriptor_bytes", ctypes.c_uint64),
+                ("grouped_launches", ctypes.c_int64)]
+
+
 _lib = None
 
 
@@ -90,10 +95,18 @@ def lib(need_torch: bool = True) -> ctypes.CDLL:
                                      i32, vp]
     L.psim_profile.argtypes = [vp, i32, ctypes.POINTER(KernelStats)]
     L.psim_tune.argtypes = [vp, vp, sz, vp, i32, ctypes.POINTER(ctypes.c_double)]
+    L.psim_group.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
+    L.psim_group_info.argtypes = [vp, ctypes.POINTER(GroupStats)]
+    L.psim_group_amplitudes.argtypes = [vp, ctypes.POINTER(ctypes.POINTER(ctypes.c_uint8)), ctypes.POINTER(sz),
+                                        ctypes.POINTER(vp), ctypes.POINTER(sz), vp,
+                                        ctypes.POINTER(ctypes.POINTER(ctypes.c_double))]
+    L.psim_group_free.argtypes = [vp]
+    L.psim_group_free.restype = None
     L.psim_last_error.restype = ctypes.c_char_p
     L.psim_version.restype = ctypes.c_char_p
     for f in ("psim_build", "psim_peps_info", "psim_plan", "psim_plan_info", "psim_amplitudes",
-              "psim_contract_site", "psim_profile", "psim_tune"):
+              "psim_contract_site", "psim_profile", "psim_tune", "psim_group", "psim_group_info",
+              "psim_group_amplitudes"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -224,6 +237,64 @@ class Plan:
             lib().psim_plan_free(self._h)
             self._h = None
         self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Group:
+    """Plans run together in one interleaved sweep (psim_group): different
+    circuits, lattices and depths; same-kernel FP32 site contractions of a
+    step are merged into one launch.  The plans must outlive the group."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(lib().psim_group(arr, len(self.plans), ctypes.byref(h)))
+        self._h = h
+
+    def stats(self) -> dict:
+        s = GroupStats()
+        _check(lib().psim_group_info(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in GroupStats._fields_}
+
+    def amplitudes(self, bits_list, stream=None):
+        """One bitstring array per plan (uint8, shape (n_p, lv*lh)); returns a
+        list of complex128 arrays."""
+        import torch
+        np_ = len(self.plans)
+        if len(bits_list) != np_:
+            raise ValueError(f"need {np_} bitstring arrays")
+        bs, outs = [], []
+        for p, b in zip(self.plans, bits_list):
+            b = np.ascontiguousarray(np.asarray(b, dtype=np.uint8))
+            if b.ndim == 1:
+                b = b[None, :]
+            if b.shape[1] != p.nq:
+                raise ValueError(f"bitstrings must have {p.nq} entries")
+            bs.append(b)
+            outs.append(np.zeros(max(2 * b.shape[0], 2), dtype=np.float64))
+        wss = [p.workspace() for p in self.plans]
+        PU8 = ctypes.POINTER(ctypes.c_uint8)
+        PD = ctypes.POINTER(ctypes.c_double)
+        c_bits = (PU8 * np_)(*[b.ctypes.data_as(PU8) for b in bs])
+        c_n = (ctypes.c_size_t * np_)(*[b.shape[0] for b in bs])
+        c_ws = (ctypes.c_void_p * np_)(*[w.data_ptr() for w in wss])
+        c_wsb = (ctypes.c_size_t * np_)(*[w.numel() for w in wss])
+        c_out = (PD * np_)(*[o.ctypes.data_as(PD) for o in outs])
+        dev = self.plans[0].device
+        st = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+        _check(lib().psim_group_amplitudes(self._h, c_bits, c_n, c_ws, c_wsb, ctypes.c_void_p(st), c_out))
+        return [o[0:2 * b.shape[0]:2] + 1j * o[1:2 * b.shape[0]:2] for o, b in zip(outs, bs)]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().psim_group_free(self._h)
+            self._h = None
 
     def __del__(self):
         try:

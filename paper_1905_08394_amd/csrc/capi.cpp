@@ -14,6 +14,10 @@ void free_plan(psim_plan_t* pl);
 void run_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, size_t ws_bytes, void* stream,
                     double* out);
 void tune_plan(psim_plan_t* pl, void* ws, size_t ws_bytes, void* stream, int reps, double* best_ms);
+psim_group_s* make_group(psim_plan_t* const* plans, int np);
+void free_group(psim_group_s* G);
+void run_group(psim_group_s* G, const uint8_t* const* bits, const size_t* n, void* const* ws, const size_t* ws_bytes,
+               void* stream, double* const* out);
 
 namespace psim {
 
@@ -203,6 +207,35 @@ psim_status psim_profile(psim_plan_t* pl, int32_t op, psim_kernel_stats* out) {
     }
   });
 }
+
+psim_status psim_group(psim_plan_t* const* plans, int32_t n_plans, psim_group_t** out) {
+  return guarded([&] {
+    if (!out) fail(PSIM_EINVAL, "out is NULL");
+    *out = make_group(plans, n_plans);
+  });
+}
+
+psim_status psim_group_info(const psim_group_t* g, psim_group_stats* out) {
+  return guarded([&] {
+    if (!g || !out) fail(PSIM_EINVAL, "group or out is NULL");
+    psim_group_stats o{};
+    o.n_plans = (int32_t)g->plans.size();
+    o.descriptor_bytes = g->desc_bytes;
+    o.grouped_launches = g->grouped_launches;
+    *out = o;
+  });
+}
+
+psim_status psim_group_amplitudes(psim_group_t* g, const uint8_t* const* bits, const size_t* n_bitstrings,
+                                  void* const* workspaces, const size_t* workspace_bytes, void* stream,
+                                  double* const* out) {
+  return guarded([&] {
+    if (!g) fail(PSIM_EINVAL, "group is NULL");
+    run_group(g, bits, n_bitstrings, workspaces, workspace_bytes, stream, out);
+  });
+}
+
+void psim_group_free(psim_group_t* g) { free_group(g); }
 
 const char* psim_last_error(void) { return g_last_error.c_str(); }
 

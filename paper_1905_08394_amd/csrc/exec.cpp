@@ -166,8 +166,9 @@ void tune_plan(psim_plan_t* pl, void* ws, size_t ws_bytes, void* stream, int rep
   (void)hipEventDestroy(b);
 }
 
-void run_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, size_t ws_bytes, void* stream,
-                    double* out) {
+namespace {
+
+void check_batch(const psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, size_t ws_bytes, double* out) {
   if (pl->host_only) fail(PSIM_EINVAL, "plan was made with PSIM_PLAN_HOST_ONLY");
   if (!bits || !out) fail(PSIM_EINVAL, "bits or out is NULL");
   if (n == 0) return;
@@ -175,130 +176,271 @@ void run_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, si
   if (ws_bytes < pl->ws_total)
     fail(PSIM_EINVAL, "workspace has " + std::to_string(ws_bytes) + " bytes, plan needs " +
                           std::to_string(pl->ws_total));
-  const int nq = pl->lv * pl->lh;
-  for (size_t x = 0; x < n * (size_t)nq; ++x)
+  const size_t nq = (size_t)pl->lv * pl->lh;
+  for (size_t x = 0; x < n * nq; ++x)
     if (bits[x] > 1) fail(PSIM_EINVAL, "bit " + std::to_string(x) + " is not 0 or 1");
-  // Split into sub-batches whose prefix trie fits the planned capacities:
-  // sort the bitstrings by their swept rows (row 0 first) so that neighbours
-  // share the longest prefixes, then cut greedily.
-  if (!pl->in_subbatch) {
-    std::vector<size_t> order(n);
-    for (size_t b = 0; b < n; ++b) order[b] = b;
-    auto rowkey = [&](size_t b, int i) {
-      uint64_t key = 0;
-      for (int j = 0; j < pl->L; ++j) key |= (uint64_t)bits[b * nq + pl->cs[(size_t)i * pl->L + j].qubit] << j;
-      return key;
-    };
-    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
-      for (int i = 0; i < pl->R; ++i) {
-        const uint64_t a = rowkey(x, i), b = rowkey(y, i);
-        if (a != b) return a < b;
-      }
-      return false;
-    });
-    std::vector<uint8_t> sb;
-    std::vector<double> so;
-    std::vector<int64_t> count(pl->R, 0);
-    size_t start = 0;
-    auto flush = [&](size_t end) {
-      const size_t m = end - start;
-      sb.resize(m * nq);
-      so.resize(2 * m);
-      for (size_t x = 0; x < m; ++x) std::memcpy(&sb[x * nq], bits + order[start + x] * nq, nq);
-      pl->in_subbatch = true;
-      try {
-        run_amplitudes(pl, sb.data(), m, ws, ws_bytes, stream, so.data());
-      } catch (...) {
-        pl->in_subbatch = false;
-        throw;
-      }
-      pl->in_subbatch = false;
-      for (size_t x = 0; x < m; ++x) {
-        out[2 * order[start + x]] = so[2 * x];
-        out[2 * order[start + x] + 1] = so[2 * x + 1];
-      }
-      start = end;
-    };
-    for (size_t x = 0; x < n; ++x) {
-      // first swept row where this bitstring leaves the previous one's path
-      int first = 0;
-      if (x > start) {
-        while (first < pl->R && rowkey(order[x], first) == rowkey(order[x - 1], first)) ++first;
-      }
-      bool fits = (int64_t)(x - start + 1) <= (int64_t)pl->opts.max_batch;
-      for (int i = (x > start ? first : 0); i < pl->R && fits; ++i) fits = count[i] + 1 <= pl->levels[i].cap;
-      if (!fits) {
-        flush(x);
-        std::fill(count.begin(), count.end(), 0);
-        first = 0;
-      }
-      for (int i = (x > start ? first : 0); i < pl->R; ++i) ++count[i];
+}
+
+// Sub-batches whose prefix trie fits the planned capacities: sort the
+// bitstrings by their swept rows (row 0 first) so that neighbours share the
+// longest prefixes, then cut greedily.  Returns lists of bitstring indices.
+std::vector<std::vector<size_t>> split_batches(const psim_plan_t* pl, const uint8_t* bits, size_t n) {
+  const int nq = pl->lv * pl->lh;
+  std::vector<size_t> order(n);
+  for (size_t b = 0; b < n; ++b) order[b] = b;
+  auto rowkey = [&](size_t b, int i) {
+    uint64_t key = 0;
+    for (int j = 0; j < pl->L; ++j) key |= (uint64_t)bits[b * nq + pl->cs[(size_t)i * pl->L + j].qubit] << j;
+    return key;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+    for (int i = 0; i < pl->R; ++i) {
+      const uint64_t a = rowkey(x, i), b = rowkey(y, i);
+      if (a != b) return a < b;
     }
-    flush(n);
-    return;
+    return false;
+  });
+  std::vector<std::vector<size_t>> out;
+  std::vector<int64_t> count(pl->R, 0);
+  size_t start = 0;
+  for (size_t x = 0; x < n; ++x) {
+    // first swept row where this bitstring leaves the previous one's path
+    int first = 0;
+    if (x > start) {
+      while (first < pl->R && rowkey(order[x], first) == rowkey(order[x - 1], first)) ++first;
+    }
+    bool fits = (int64_t)(x - start + 1) <= (int64_t)pl->opts.max_batch;
+    for (int i = (x > start ? first : 0); i < pl->R && fits; ++i) fits = count[i] + 1 <= pl->levels[i].cap;
+    if (!fits) {
+      out.emplace_back(order.begin() + start, order.begin() + x);
+      start = x;
+      std::fill(count.begin(), count.end(), 0);
+      first = 0;
+    }
+    for (int i = (x > start ? first : 0); i < pl->R; ++i) ++count[i];
   }
-  hip_check(hipSetDevice(pl->opts.device), "hipSetDevice");
-  hipStream_t st = (hipStream_t)stream;
-  const int R = pl->R, L = pl->L, prec = pl->opts.prec;
+  if (n > start) out.emplace_back(order.begin() + start, order.end());
+  return out;
+}
+
+// One device operation of the row sweep: a site contraction or a row rescale.
+struct Op {
+  bool rescale = false;
+  int cls = 0;  // 0 first site, 1 interior site, 2 last site, 3 rescale
+  double cmac = 0;
+  GemmLaunch g;
+  // rescale arguments
+  void* F = nullptr;
+  int64_t F_elems = 0, nodes = 0;
+  const int32_t* parent = nullptr;
+  const int32_t* e_in = nullptr;
+  int32_t* e_out = nullptr;
+  uint32_t* mx = nullptr;
+  int row = 0;
+};
+
+// One sub-batch of one plan, ready to run: its trie (uploaded to the
+// workspace) and the ordered operations that contract it.
+struct Prepared {
+  psim_plan_t* pl = nullptr;
+  std::vector<uint8_t> bits;  // the sub-batch's bitstrings, nq bytes each
+  size_t n = 0;
+  Trie t;
+  WsLayout W;
+  std::vector<Op> ops;
+  std::vector<char> vals;     // downloaded leaf boundaries (scalars)
+  std::vector<int32_t> ex;    // and their exponents
+};
+
+void prepare(psim_plan_t* pl, const uint8_t* bits, const std::vector<size_t>& idx, void* ws, hipStream_t st,
+             Prepared& P) {
+  const int R = pl->R, L = pl->L, prec = pl->opts.prec, nq = pl->lv * pl->lh;
   const uint64_t eb = pl->elem_bytes;
-  Trie t = build_trie(*pl, bits, n);
-
-  // ------------------------------------------------------------ workspace
-  WsLayout W = layout(*pl, ws);
-  std::vector<int32_t*>& d_parent = W.parent;
-  std::vector<uint8_t*>& d_tau = W.tau;
-  int32_t** d_exp = W.exp;
-  uint32_t* d_max = W.mx;
-  char** dF = W.F;
-  char** dG = W.G;
-
+  P.pl = pl;
+  P.n = idx.size();
+  P.bits.resize(P.n * nq);
+  for (size_t x = 0; x < P.n; ++x) std::memcpy(&P.bits[x * nq], bits + idx[x] * nq, nq);
+  P.t = build_trie(*pl, P.bits.data(), P.n);
+  P.W = layout(*pl, ws);
+  const Trie& t = P.t;
+  WsLayout& W = P.W;
   for (int i = 0; i < R; ++i) {
     if ((int64_t)t.parent[i].size() > pl->levels[i].cap) fail(PSIM_EINTERNAL, "trie larger than planned");
-    hip_check(hipMemcpyAsync(d_parent[i], t.parent[i].data(), t.parent[i].size() * 4, hipMemcpyHostToDevice, st),
+    hip_check(hipMemcpyAsync(W.parent[i], t.parent[i].data(), t.parent[i].size() * 4, hipMemcpyHostToDevice, st),
               "upload parents");
-    hip_check(hipMemcpyAsync(d_tau[i], t.tau[i].data(), t.tau[i].size(), hipMemcpyHostToDevice, st),
-              "upload bits");
+    hip_check(hipMemcpyAsync(W.tau[i], t.tau[i].data(), t.tau[i].size(), hipMemcpyHostToDevice, st), "upload bits");
   }
   // root exponent 0
-  const int32_t zero = 0;
-  hip_check(hipMemcpyAsync(d_exp[1], &zero, 4, hipMemcpyHostToDevice, st), "upload exponent");
+  static const int32_t zero = 0;
+  hip_check(hipMemcpyAsync(W.exp[1], &zero, 4, hipMemcpyHostToDevice, st), "upload exponent");
 
-  // ------------------------------------------------------------ event timing (optional)
+  P.ops.clear();
+  for (int i = 0; i < R; ++i) {
+    const Level& lev = pl->levels[i];
+    const int64_t nodes = (int64_t)t.parent[i].size();
+    const void* Fprev = i == 0 ? pl->d_ones : (const void*)W.F[(i - 1) % 2];
+    const int64_t Fprev_elems = i == 0 ? 1 : pl->levels[i - 1].F_elems;
+    char* Fcur = W.F[i % 2];
+    const int c = lev.vchunk;
+    for (int64_t g0 = 0; g0 < nodes; g0 += lev.group) {
+      const int64_t gn = std::min<int64_t>(lev.group, nodes - g0);
+      for (int v0 = 0; v0 < lev.Dv; v0 += c) {
+        for (int j = 0; j < L; ++j) {
+          const Step& s = pl->steps[(size_t)i * L + j];
+          const DevMatrix& w0 = pl->w[((size_t)i * L + j) * 2];
+          const DevMatrix& w1 = pl->w[((size_t)i * L + j) * 2 + 1];
+          Op op;
+          GemmLaunch& g = op.g;
+          g.prec = (prec == PSIM_FP32_3M && s.kind == 2) ? PSIM_FP32_4M : prec;  // see the packing
+          g.cfg = s.kind == 1 ? s.cfg : 0;
+          g.split = (pl->opts.flags & PSIM_PLAN_SPLIT_ACC) ? 1 : 0;
+          if (s.kind == 1 && w0.ptr_b) {
+            g.Wb0 = w0.ptr_b;
+            g.Wb1 = w1.ptr_b;
+            g.ldwb = w0.ld_b;
+            g.planeb = w0.plane_b;
+          }
+          g.W0 = w0.ptr;
+          g.W1 = w1.ptr;
+          g.ldw = w0.ld;
+          g.tau = W.tau[i] + g0 * L + j;
+          g.tau_stride = L;
+          g.nodes = gn;
+          g.N = s.N;
+          g.K2 = s.K2;
+          g.M = s.M;
+          if (s.kind == 2) {
+            g.trans_out = 1;
+            g.Bz = 1;
+            g.C = Fcur + (uint64_t)g0 * lev.F_elems * eb;
+            g.sC_node = lev.F_elems;
+            if (L == 1) {  // the only site: contracts the parent's boundary directly
+              g.A = Fprev;
+              g.a_index = W.parent[i] + g0;
+              g.sA_node = Fprev_elems;
+              g.K1 = lev.Dv;
+              g.beta = 0;
+            } else {
+              g.A = W.G[(L - 2) % 2];
+              g.sA_node = (int64_t)c * s.M * s.K2;
+              g.K1 = c;
+              g.w_koff = (int64_t)v0 * s.K2;
+              g.beta = v0 > 0;
+            }
+          } else {
+            g.Bz = c;
+            g.K1 = s.K1;
+            g.C = W.G[j % 2];
+            g.sC_v = s.g_out;
+            g.sC_node = (int64_t)c * s.g_out;
+            if (s.kind == 0) {
+              g.A = (const char*)Fprev + (uint64_t)v0 * s.K1 * s.M * eb;
+              g.a_index = W.parent[i] + g0;
+              g.sA_node = Fprev_elems;
+              g.sA_v = s.K1 * s.M;
+            } else {
+              g.A = W.G[(j - 1) % 2];
+              g.sA_v = s.K1 * s.M * s.K2;
+              g.sA_node = (int64_t)c * g.sA_v;
+            }
+          }
+          op.cls = s.kind;
+          op.cmac = (double)g.nodes * g.Bz * g.M * g.K1 * g.K2 * g.N;
+          op.row = i;
+          P.ops.push_back(op);
+        }
+        if (L == 1) break;  // the single site consumed every v at once
+      }
+    }
+    // exact power-of-two rescale of every node's boundary; exponents along the trie
+    Op op;
+    op.rescale = true;
+    op.cls = 3;
+    op.F = Fcur;
+    op.F_elems = lev.F_elems;
+    op.nodes = nodes;
+    op.parent = W.parent[i];
+    op.e_in = W.exp[(i + 1) % 2];
+    op.e_out = W.exp[i % 2];
+    op.mx = W.mx;
+    op.row = i;
+    P.ops.push_back(op);
+  }
+  if ((int64_t)P.ops.size() > pl->max_ops) fail(PSIM_EINTERNAL, "more operations than planned");
+}
+
+void run_op(const psim_plan_t* pl, const Op& op, hipStream_t st) {
+  if (op.rescale)
+    launch_rowscale(pl->opts.prec, op.F, op.F_elems, op.nodes, op.parent, const_cast<int32_t*>(op.e_in), op.e_out,
+                    op.mx, st);
+  else
+    launch_site_gemm(op.g, st);
+}
+
+void enqueue_download(Prepared& P, hipStream_t st) {
+  const psim_plan_t* pl = P.pl;
+  const int R = pl->R;
+  const int64_t leaves = (int64_t)P.t.parent[R - 1].size();
+  P.vals.resize((size_t)leaves * pl->elem_bytes);
+  P.ex.resize((size_t)leaves);
+  hip_check(hipMemcpyAsync(P.vals.data(), P.W.F[(R - 1) % 2], P.vals.size(), hipMemcpyDeviceToHost, st), "download");
+  hip_check(hipMemcpyAsync(P.ex.data(), P.W.exp[(R - 1) % 2], P.ex.size() * 4, hipMemcpyDeviceToHost, st),
+            "download");
+}
+
+// amplitude b = mantissa * 2^(row exponents + site-matrix exponents), in FP64
+void assemble(const Prepared& P, const std::vector<size_t>& idx, double* out) {
+  const psim_plan_t* pl = P.pl;
+  const int R = pl->R, L = pl->L, nq = pl->lv * pl->lh;
+  for (size_t b = 0; b < P.n; ++b) {
+    const int32_t leaf = P.t.leaf[b];
+    double re, im;
+    if (pl->elem_bytes == 16) {
+      const double* v = (const double*)P.vals.data();
+      re = v[2 * leaf];
+      im = v[2 * leaf + 1];
+    } else {
+      const float* v = (const float*)P.vals.data();
+      re = v[2 * leaf];
+      im = v[2 * leaf + 1];
+    }
+    int64_t e = P.ex[leaf];
+    for (int i = 0; i < R; ++i)
+      for (int j = 0; j < L; ++j) {
+        const int tau = P.bits[b * nq + pl->cs[(size_t)i * L + j].qubit];
+        e += pl->w[((size_t)i * L + j) * 2 + tau].exp2;
+      }
+    out[2 * idx[b]] = std::ldexp(re, (int)e);
+    out[2 * idx[b] + 1] = std::ldexp(im, (int)e);
+  }
+}
+
+// One sub-batch of one plan on its own: optional event timing, row progress
+// log, or graph capture / replay of the operation list.
+void run_one(psim_plan_t* pl, const uint8_t* bits, const std::vector<size_t>& idx, void* ws, hipStream_t st,
+             double* out) {
+  Prepared P;
+  prepare(pl, bits, idx, ws, st, P);
+
   struct Timed {
     hipEvent_t a, b;
     int cls;
     double cmac;
   };
   std::vector<Timed> timed;
-  auto tstart = [&](int cls, double cmac) {
-    if (!pl->profile) return;
-    Timed t{};
-    t.cls = cls;
-    t.cmac = cmac;
-    hip_check(hipEventCreate(&t.a), "hipEventCreate");
-    hip_check(hipEventCreate(&t.b), "hipEventCreate");
-    hip_check(hipEventRecord(t.a, st), "hipEventRecord");
-    timed.push_back(t);
-  };
-  auto tstop = [&]() {
-    if (!pl->profile) return;
-    hip_check(hipEventRecord(timed.back().b, st), "hipEventRecord");
-  };
-
   const char* env_log = std::getenv("PSIM_LOG");
   const bool log_rows = env_log && env_log[0] == '1';
   const auto t_begin = std::chrono::steady_clock::now();
 
-  // ------------------------------------------------------------ graph replay (optional)
-  // The launch sequence below depends only on the workspace address and the
-  // number of nodes per level; the tables it reads were uploaded above.
+  // The launch sequence depends only on the workspace address and the number
+  // of nodes per level; the tables it reads were uploaded by prepare().
   const bool use_graph = (pl->opts.flags & PSIM_PLAN_GRAPH) && !pl->profile && !log_rows;
   hipGraphExec_t gexec = nullptr;
   bool capturing = false;
   std::vector<int64_t> gkey;
   if (use_graph) {
     gkey.push_back((int64_t)(uintptr_t)ws);
-    for (int i = 0; i < R; ++i) gkey.push_back((int64_t)t.parent[i].size());
+    for (int i = 0; i < pl->R; ++i) gkey.push_back((int64_t)P.t.parent[i].size());
     auto it = pl->graphs.find(gkey);
     if (it != pl->graphs.end()) {
       gexec = (hipGraphExec_t)it->second;
@@ -313,143 +455,199 @@ void run_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, si
       capturing = true;
     }
   }
-  hipStream_t ust = st;  // stream the uploads and results use
-  if (capturing) st = (hipStream_t)pl->cap_stream;
-
-  // ------------------------------------------------------------ rows
-  for (int i = 0; i < R && !gexec; ++i) {
-    const Level& lev = pl->levels[i];
-    const int64_t nodes = (int64_t)t.parent[i].size();
-    const void* Fprev = i == 0 ? pl->d_ones : (const void*)dF[(i - 1) % 2];
-    const int64_t Fprev_elems = i == 0 ? 1 : pl->levels[i - 1].F_elems;
-    char* Fcur = dF[i % 2];
-    const int c = lev.vchunk;
-    for (int64_t g0 = 0; g0 < nodes; g0 += lev.group) {
-      const int64_t gn = std::min<int64_t>(lev.group, nodes - g0);
-      for (int v0 = 0; v0 < lev.Dv; v0 += c) {
-        for (int j = 0; j < L; ++j) {
-          const Step& s = pl->steps[(size_t)i * L + j];
-          const DevMatrix& w0 = pl->w[((size_t)i * L + j) * 2];
-          const DevMatrix& w1 = pl->w[((size_t)i * L + j) * 2 + 1];
-          GemmLaunch g;
-          g.prec = (prec == PSIM_FP32_3M && s.kind == 2) ? PSIM_FP32_4M : prec;  // see the packing
-          g.cfg = s.kind == 1 ? s.cfg : 0;
-          g.split = (pl->opts.flags & PSIM_PLAN_SPLIT_ACC) ? 1 : 0;
-          if (s.kind == 1 && w0.ptr_b) {
-            g.Wb0 = w0.ptr_b;
-            g.Wb1 = w1.ptr_b;
-            g.ldwb = w0.ld_b;
-            g.planeb = w0.plane_b;
-          }
-          g.W0 = w0.ptr;
-          g.W1 = w1.ptr;
-          g.ldw = w0.ld;
-          g.tau = d_tau[i] + g0 * L + j;
-          g.tau_stride = L;
-          g.nodes = gn;
-          g.N = s.N;
-          g.K2 = s.K2;
-          g.M = s.M;
-          if (s.kind == 2) {
-            g.trans_out = 1;
-            g.Bz = 1;
-            g.C = Fcur + (uint64_t)g0 * lev.F_elems * eb;
-            g.sC_node = lev.F_elems;
-            if (L == 1) {  // the only site: contracts the parent's boundary directly
-              g.A = Fprev;
-              g.a_index = d_parent[i] + g0;
-              g.sA_node = Fprev_elems;
-              g.K1 = lev.Dv;
-              g.beta = 0;
-            } else {
-              g.A = dG[(L - 2) % 2];
-              g.sA_node = (int64_t)c * s.M * s.K2;
-              g.K1 = c;
-              g.w_koff = (int64_t)v0 * s.K2;
-              g.beta = v0 > 0;
-            }
-          } else {
-            g.Bz = c;
-            g.K1 = s.K1;
-            g.C = dG[j % 2];
-            g.sC_v = s.g_out;
-            g.sC_node = (int64_t)c * s.g_out;
-            if (s.kind == 0) {
-              g.A = (const char*)Fprev + (uint64_t)v0 * s.K1 * s.M * eb;
-              g.a_index = d_parent[i] + g0;
-              g.sA_node = Fprev_elems;
-              g.sA_v = s.K1 * s.M;
-            } else {
-              g.A = dG[(j - 1) % 2];
-              g.sA_v = s.K1 * s.M * s.K2;
-              g.sA_node = (int64_t)c * g.sA_v;
-            }
-          }
-          tstart(s.kind, (double)g.nodes * g.Bz * g.M * g.K1 * g.K2 * g.N);
-          launch_site_gemm(g, st);
-          tstop();
+  hipStream_t lst = capturing ? (hipStream_t)pl->cap_stream : st;  // stream the sweep is recorded on
+  if (!gexec) {
+    try {
+      for (const Op& op : P.ops) {
+        if (pl->profile) {
+          Timed tm{};
+          tm.cls = op.cls;
+          tm.cmac = op.cmac;
+          hip_check(hipEventCreate(&tm.a), "hipEventCreate");
+          hip_check(hipEventCreate(&tm.b), "hipEventCreate");
+          hip_check(hipEventRecord(tm.a, lst), "hipEventRecord");
+          timed.push_back(tm);
         }
-        if (L == 1) break;  // the single site consumed every v at once
+        run_op(pl, op, lst);
+        if (pl->profile) hip_check(hipEventRecord(timed.back().b, lst), "hipEventRecord");
+        if (log_rows && op.rescale) {  // progress for long runs: wait for the row, then report it
+          hip_check(hipStreamSynchronize(lst), "hipStreamSynchronize");
+          std::fprintf(stderr, "psim: row %d/%d done (%lld nodes) at %.2f s\n", op.row + 1, pl->R,
+                       (long long)op.nodes,
+                       std::chrono::duration<double>(std::chrono::steady_clock::now() - t_begin).count());
+          std::fflush(stderr);
+        }
       }
-    }
-    // exact power-of-two rescale of every node's boundary; exponents along the trie
-    tstart(3, 0.0);
-    launch_rowscale(prec, Fcur, lev.F_elems, nodes, d_parent[i], d_exp[(i + 1) % 2], d_exp[i % 2], d_max, st);
-    tstop();
-    if (log_rows) {  // progress for long runs: wait for the row, then report it
-      hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
-      std::fprintf(stderr, "psim: row %d/%d done (%lld nodes) at %.2f s\n", i + 1, R, (long long)nodes,
-                   std::chrono::duration<double>(std::chrono::steady_clock::now() - t_begin).count());
-      std::fflush(stderr);
+    } catch (...) {
+      if (capturing) {
+        hipGraph_t graph = nullptr;
+        (void)hipStreamEndCapture(lst, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+      }
+      throw;
     }
   }
-
   if (capturing) {
     hipGraph_t graph = nullptr;
-    const hipError_t e1 = hipStreamEndCapture(st, &graph);
-    st = ust;
-    hip_check(e1, "hipStreamEndCapture");
-    hip_check(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    hip_check(hipStreamEndCapture(lst, &graph), "hipStreamEndCapture");
+    const hipError_t e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
+    hip_check(e, "hipGraphInstantiate");
     pl->graphs[gkey] = (void*)gexec;
   }
   if (gexec) hip_check(hipGraphLaunch(gexec, st), "hipGraphLaunch");
 
-  // ------------------------------------------------------------ results
-  const int64_t leaves = (int64_t)t.parent[R - 1].size();
-  std::vector<char> vals((size_t)leaves * eb);
-  std::vector<int32_t> ex((size_t)leaves);
-  hip_check(hipMemcpyAsync(vals.data(), dF[(R - 1) % 2], vals.size(), hipMemcpyDeviceToHost, st), "download");
-  hip_check(hipMemcpyAsync(ex.data(), d_exp[(R - 1) % 2], ex.size() * 4, hipMemcpyDeviceToHost, st), "download");
+  enqueue_download(P, st);
   hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
-  for (Timed& t : timed) {
+  for (Timed& tm : timed) {
     float ms = 0;
-    hip_check(hipEventElapsedTime(&ms, t.a, t.b), "hipEventElapsedTime");
-    pl->prof[t.cls].ms += ms;
-    pl->prof[t.cls].launches += 1;
-    pl->prof[t.cls].cmac += t.cmac;
-    (void)hipEventDestroy(t.a);
-    (void)hipEventDestroy(t.b);
+    hip_check(hipEventElapsedTime(&ms, tm.a, tm.b), "hipEventElapsedTime");
+    pl->prof[tm.cls].ms += ms;
+    pl->prof[tm.cls].launches += 1;
+    pl->prof[tm.cls].cmac += tm.cmac;
+    (void)hipEventDestroy(tm.a);
+    (void)hipEventDestroy(tm.b);
   }
-  for (size_t b = 0; b < n; ++b) {
-    const int32_t leaf = t.leaf[b];
-    double re, im;
-    if (eb == 16) {
-      const double* v = (const double*)vals.data();
-      re = v[2 * leaf];
-      im = v[2 * leaf + 1];
-    } else {
-      const float* v = (const float*)vals.data();
-      re = v[2 * leaf];
-      im = v[2 * leaf + 1];
+  assemble(P, idx, out);
+}
+
+}  // namespace
+
+void run_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, size_t ws_bytes, void* stream,
+                    double* out) {
+  check_batch(pl, bits, n, ws, ws_bytes, out);
+  if (n == 0) return;
+  hip_check(hipSetDevice(pl->opts.device), "hipSetDevice");
+  for (const auto& idx : split_batches(pl, bits, n)) run_one(pl, bits, idx, ws, (hipStream_t)stream, out);
+}
+
+// ------------------------------------------------------------------ groups
+// Several plans (different circuits, lattices, depths) advance together:
+// pass p runs sub-batch p of every plan, and step k of a pass issues
+// operation k of every plan's list.  Site contractions of one step that share
+// a kernel variant go into one grouped launch (one grid over all their
+// tiles); the others are launched one by one.  Every plan's operations stay
+// in their own order on the one stream, so each plan computes exactly what
+// psim_amplitudes computes for it.
+psim_group_s* make_group(psim_plan_t* const* plans, int np) {
+  if (!plans || np < 1) fail(PSIM_EINVAL, "plans is NULL or empty");
+  auto* G = new psim_group_s();
+  try {
+    uint64_t off = 0;
+    const uint64_t kb = (uint64_t)kargs_bytes();
+    for (int p = 0; p < np; ++p) {
+      psim_plan_t* pl = plans[p];
+      if (!pl) fail(PSIM_EINVAL, "plan " + std::to_string(p) + " is NULL");
+      if (pl->host_only) fail(PSIM_EINVAL, "plan " + std::to_string(p) + " was made with PSIM_PLAN_HOST_ONLY");
+      if (pl->opts.device != plans[0]->opts.device) fail(PSIM_EINVAL, "plans are on different devices");
+      G->plans.push_back(pl);
+      G->desc_off.push_back(off);
+      off += (uint64_t)pl->max_ops * kb;
     }
-    int64_t e = ex[leaf];
-    for (int i = 0; i < R; ++i)
-      for (int j = 0; j < L; ++j) {
-        const int tau = bits[b * nq + pl->cs[(size_t)i * L + j].qubit];
-        e += pl->w[((size_t)i * L + j) * 2 + tau].exp2;
+    G->device = plans[0]->opts.device;
+    G->desc_bytes = off;
+    hip_check(hipSetDevice(G->device), "hipSetDevice");
+    hip_check(hipMalloc(&G->d_desc, off), "hipMalloc(group descriptors)");
+  } catch (...) {
+    delete G;
+    throw;
+  }
+  return G;
+}
+
+void free_group(psim_group_s* G) {
+  if (!G) return;
+  if (G->d_desc) (void)hipFree(G->d_desc);
+  delete G;
+}
+
+void run_group(psim_group_s* G, const uint8_t* const* bits, const size_t* n, void* const* ws, const size_t* ws_bytes,
+               void* stream, double* const* out) {
+  const int np = (int)G->plans.size();
+  if (!bits || !n || !ws || !ws_bytes || !out) fail(PSIM_EINVAL, "an argument array is NULL");
+  for (int p = 0; p < np; ++p) {
+    try {
+      check_batch(G->plans[p], bits[p], n[p], ws[p], ws_bytes[p], out[p]);
+    } catch (const Error& e) {
+      fail(e.status, "plan " + std::to_string(p) + ": " + e.msg);
+    }
+  }
+  // workspaces must not overlap (each plan's sweep writes its own)
+  for (int p = 0; p < np; ++p)
+    for (int q = p + 1; q < np; ++q) {
+      if (!n[p] || !n[q]) continue;
+      const uintptr_t a0 = (uintptr_t)ws[p], a1 = a0 + G->plans[p]->ws_total;
+      const uintptr_t b0 = (uintptr_t)ws[q], b1 = b0 + G->plans[q]->ws_total;
+      if (a0 < b1 && b0 < a1) fail(PSIM_EINVAL, "workspaces of plans " + std::to_string(p) + " and " +
+                                                    std::to_string(q) + " overlap");
+    }
+  hip_check(hipSetDevice(G->device), "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<std::vector<std::vector<size_t>>> subs(np);
+  size_t passes = 0;
+  for (int p = 0; p < np; ++p) {
+    if (n[p]) subs[p] = split_batches(G->plans[p], bits[p], n[p]);
+    passes = std::max(passes, subs[p].size());
+  }
+  const int kb = kargs_bytes();
+  const int maxg = max_group();
+  for (size_t pass = 0; pass < passes; ++pass) {
+    std::vector<Prepared> P;
+    std::vector<int> who;
+    for (int p = 0; p < np; ++p)
+      if (pass < subs[p].size()) {
+        P.emplace_back();
+        who.push_back(p);
+        prepare(G->plans[p], bits[p], subs[p][pass], ws[p], st, P.back());
       }
-    out[2 * b] = std::ldexp(re, (int)e);
-    out[2 * b + 1] = std::ldexp(im, (int)e);
+    // descriptors of every groupable contraction, one upload per plan
+    const size_t m = P.size();
+    std::vector<std::vector<char>> desc(m);
+    std::vector<std::vector<int>> variant(m);
+    std::vector<std::vector<long long>> tiles(m);
+    size_t steps = 0;
+    for (size_t q = 0; q < m; ++q) {
+      const auto& ops = P[q].ops;
+      steps = std::max(steps, ops.size());
+      desc[q].resize(ops.size() * kb);
+      variant[q].assign(ops.size(), -1);
+      tiles[q].assign(ops.size(), 0);
+      for (size_t k = 0; k < ops.size(); ++k)
+        if (!ops[k].rescale) variant[q][k] = group_variant(ops[k].g, &desc[q][k * kb], &tiles[q][k]);
+      char* d = (char*)G->d_desc + G->desc_off[who[q]];
+      hip_check(hipMemcpyAsync(d, desc[q].data(), desc[q].size(), hipMemcpyHostToDevice, st), "upload descriptors");
+    }
+    for (size_t k = 0; k < steps; ++k) {
+      std::map<int, std::vector<std::pair<size_t, size_t>>> byvar;  // variant -> (plan slot, op)
+      for (size_t q = 0; q < m; ++q) {
+        if (k >= P[q].ops.size()) continue;
+        if (variant[q][k] < 0)
+          run_op(P[q].pl, P[q].ops[k], st);
+        else
+          byvar[variant[q][k]].emplace_back(q, k);
+      }
+      for (auto& kv : byvar) {
+        const auto& lst = kv.second;
+        if (lst.size() == 1) {  // nothing to merge with
+          run_op(P[lst[0].first].pl, P[lst[0].first].ops[lst[0].second], st);
+          continue;
+        }
+        for (size_t a = 0; a < lst.size(); a += maxg) {
+          const int cnt = (int)std::min<size_t>(maxg, lst.size() - a);
+          std::vector<const void*> probs(cnt);
+          std::vector<long long> start(cnt + 1, 0);
+          for (int x = 0; x < cnt; ++x) {
+            const size_t q = lst[a + x].first, kk = lst[a + x].second;
+            probs[x] = (const char*)G->d_desc + G->desc_off[who[q]] + kk * kb;
+            start[x + 1] = start[x] + tiles[q][kk];
+          }
+          launch_group(kv.first, probs.data(), start.data(), cnt, st);
+          G->grouped_launches += 1;
+        }
+      }
+    }
+    for (size_t q = 0; q < m; ++q) enqueue_download(P[q], st);
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    for (size_t q = 0; q < m; ++q) assemble(P[q], subs[who[q]][pass], out[who[q]]);
   }
 }

@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
 
 #include "psim_internal.hpp"
 
@@ -119,7 +120,7 @@ struct V16<double> { typedef f64x2 t; static constexpr int n = 2; };
 // rounding of the K-loop sum grows like sqrt(BK) + sqrt(K/BK) instead of
 // sqrt(K) (about 3x smaller at K = 2048).
 template <typename T, int BM, int BN, int BK, int AMODE, bool TRANS, int SCH, bool SPLIT>
-__device__ __forceinline__ void site_gemm_body(const KArgs& p) {
+__device__ __forceinline__ void site_gemm_body(const KArgs& p, const long long t) {
   typedef Mfma<T> MF;
   typedef typename V16<T>::t vec_t;
   static_assert(SCH == 4 || (SCH == 3 && sizeof(T) == 4), "3M is FP32 only");
@@ -145,10 +146,6 @@ __device__ __forceinline__ void site_gemm_body(const KArgs& p) {
   __shared__ __attribute__((aligned(16))) T sA[2][BM * LDS_LD];
   __shared__ __attribute__((aligned(16))) T sB[2][BROWS * LDS_LD];
 
-  const long long per_xcd = (p.T + 7) / 8;
-  const long long bid = blockIdx.x;
-  const long long t = (bid % 8) * per_xcd + bid / 8;
-  if (t >= p.T) return;
   const long long nt = t % p.NT;
   const long long rest = t / p.NT;
   const long long mt = rest % p.MT;
@@ -480,15 +477,63 @@ __device__ __forceinline__ void site_gemm_body(const KArgs& p) {
   }
 }
 
+// XCD-aware tile order: workgroup b runs on XCD b mod 8; tile
+// (b mod 8) * ceil(T/8) + b / 8 gives each XCD a contiguous range of tiles.
+__device__ __forceinline__ long long xcd_tile(long long T) {
+  const long long per_xcd = (T + 7) / 8;
+  const long long bid = blockIdx.x;
+  return (bid % 8) * per_xcd + bid / 8;
+}
+
 template <typename T, int BM, int BN, int BK, int AMODE, bool TRANS, int SCH>
 __global__ __launch_bounds__(256) void site_gemm(KArgs p) {
-  site_gemm_body<T, BM, BN, BK, AMODE, TRANS, SCH, false>(p);
+  const long long t = xcd_tile(p.T);
+  if (t >= p.T) return;
+  site_gemm_body<T, BM, BN, BK, AMODE, TRANS, SCH, false>(p, t);
 }
 
 // split-accumulation variant, held to two waves per SIMD
 template <typename T, int BM, int BN, int BK, int AMODE, bool TRANS>
 __global__ __launch_bounds__(256, 2) void site_gemm_split(KArgs p) {
-  site_gemm_body<T, BM, BN, BK, AMODE, TRANS, 4, true>(p);
+  const long long t = xcd_tile(p.T);
+  if (t >= p.T) return;
+  site_gemm_body<T, BM, BN, BK, AMODE, TRANS, 4, true>(p, t);
+}
+
+// Grouped launch: one grid over the tiles of several independent problems
+// (site contractions of different circuits).  Problem i owns global tiles
+// [start[i], start[i+1]); the descriptors live in device memory, their
+// addresses and the tile offsets travel in the kernel arguments.  Every
+// workgroup finds its problem by a binary search over uniform values and
+// reads the descriptor into scalar registers.
+constexpr int kMaxGroup = 32;
+struct GroupArgs {
+  const KArgs* probs[kMaxGroup];
+  long long start[kMaxGroup + 1];  // start[nprob] = total tiles
+  int nprob;
+};
+
+__device__ __forceinline__ int find_problem(const GroupArgs& ga, long long g) {
+  int lo = 0, hi = ga.nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ga.start[mid] <= g) lo = mid; else hi = mid - 1;
+  }
+  return __builtin_amdgcn_readfirstlane(lo);
+}
+
+template <typename T, int BM, int BN, int BK, int AMODE, bool TRANS, int SCH>
+__global__ __launch_bounds__(256) void site_gemm_group(GroupArgs ga) {
+  const long long total = ga.start[ga.nprob];
+  const long long g = xcd_tile(total);
+  if (g >= total) return;
+  const int i = find_problem(ga, g);
+  KArgs p;
+  const int* src = (const int*)ga.probs[i];
+  int* dst = (int*)&p;
+#pragma unroll
+  for (int w = 0; w < (int)(sizeof(KArgs) / 4); ++w) dst[w] = __builtin_amdgcn_readfirstlane(src[w]);
+  site_gemm_body<T, BM, BN, BK, AMODE, TRANS, SCH, false>(p, g - ga.start[i]);
 }
 
 // ---------------------------------------------------------------- BF16x3
@@ -742,8 +787,7 @@ static void launch(const KArgs& a, long long blocks, hipStream_t st) {
     hipLaunchKernelGGL((site_gemm<T, BM, BN, BK, AMODE, TRANS, SCH>), dim3((unsigned)blocks), dim3(256), 0, st, a);
 }
 
-void launch_site_gemm(const GemmLaunch& g, void* stream) {
-  hipStream_t st = (hipStream_t)stream;
+static KArgs make_kargs(const GemmLaunch& g) {
   if (g.M < 1 || g.K1 < 1 || g.K2 < 1 || g.N < 1 || g.nodes < 1 || g.Bz < 1)
     fail(PSIM_EINVAL, "site gemm: non-positive size");
   if (g.M >= (1LL << 31) || g.K1 * g.K2 >= (1LL << 30))
@@ -772,6 +816,94 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
   a.Bz = g.Bz;
   a.trans_out = g.trans_out;
   a.beta = g.beta;
+  return a;
+}
+
+// 16-byte vector loads need every batch entry's A to start 16-byte aligned
+static int fp32_mode(const GemmLaunch& g) {
+  const bool even_base = ((uintptr_t)g.A % 16 == 0) && (g.sA_node % 2 == 0) && (g.sA_v % 2 == 0);
+  return (g.K2 % 2 == 0 && even_base) ? ROWMAJOR
+         : (g.K2 == 1 && g.M % 2 == 0 && g.K1 > 1 && even_base) ? KMAJOR : GENERIC;
+}
+
+// Grouped-launch variants (FP32 only), the kernels launch_site_gemm picks for
+// default tiles: id = 8 * (3M ? 1 : 0) + 2 * mode + trans with 128 x 128 x 32
+// tiles (mode: ROWMAJOR, KMAJOR, GENERIC, ROWFAST); 16 / 17 = 4M transposed
+// small-N tiles (256 x 64 x 16, ROWMAJOR / KMAJOR).  -1: not groupable.
+int group_variant(const GemmLaunch& g, void* out, long long* tiles) {
+  if ((g.prec != PSIM_FP32_4M && g.prec != PSIM_FP32_3M) || g.split || g.cfg > 0) return -1;
+  int mode = fp32_mode(g);
+  KArgs a = make_kargs(g);
+  const long long Z = g.nodes * g.Bz;
+  int id, bm, bn;
+  if (g.prec == PSIM_FP32_4M && g.trans_out && g.N <= 32 && mode != GENERIC) {
+    id = mode == ROWMAJOR ? 16 : 17;
+    bm = 256;
+    bn = 64;
+  } else {
+    if (mode == ROWMAJOR && g.M % 128 == 0 && (2 * g.K1 * g.K2) % 32 == 0 && (2 * g.K2) % 32 == 0) mode = ROWFAST;
+    id = 8 * (g.prec == PSIM_FP32_3M ? 1 : 0) + 2 * mode + (g.trans_out ? 1 : 0);
+    bm = 128;
+    bn = 128;
+  }
+  a.MT = (a.M + bm - 1) / bm;
+  a.NT = (a.Nr + bn - 1) / bn;
+  a.T = a.MT * a.NT * Z;
+  std::memcpy(out, &a, sizeof(KArgs));
+  *tiles = a.T;
+  return id;
+}
+
+template <int SCH, int AMODE, bool TRANS>
+static void glaunch(const GroupArgs& ga, long long blocks, hipStream_t st) {
+  hipLaunchKernelGGL((site_gemm_group<float, 128, 128, 32, AMODE, TRANS, SCH>), dim3((unsigned)blocks), dim3(256), 0,
+                     st, ga);
+}
+
+template <int SCH>
+static void glaunch_mode(int mode, bool trans, const GroupArgs& ga, long long blocks, hipStream_t st) {
+  switch (mode) {
+    case ROWMAJOR: trans ? glaunch<SCH, ROWMAJOR, true>(ga, blocks, st) : glaunch<SCH, ROWMAJOR, false>(ga, blocks, st); break;
+    case KMAJOR: trans ? glaunch<SCH, KMAJOR, true>(ga, blocks, st) : glaunch<SCH, KMAJOR, false>(ga, blocks, st); break;
+    case GENERIC: trans ? glaunch<SCH, GENERIC, true>(ga, blocks, st) : glaunch<SCH, GENERIC, false>(ga, blocks, st); break;
+    default: trans ? glaunch<SCH, ROWFAST, true>(ga, blocks, st) : glaunch<SCH, ROWFAST, false>(ga, blocks, st); break;
+  }
+}
+
+void launch_group(int variant, const void* const* d_probs, const long long* start, int nprob, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (nprob < 1 || nprob > kMaxGroup) fail(PSIM_EINTERNAL, "group size out of range");
+  if (variant < 0 || variant > 17) fail(PSIM_EINTERNAL, "unknown group variant");
+  GroupArgs ga{};
+  for (int i = 0; i < nprob; ++i) {
+    ga.probs[i] = (const KArgs*)d_probs[i];
+    ga.start[i] = start[i];
+  }
+  ga.start[nprob] = start[nprob];
+  ga.nprob = nprob;
+  const long long total = start[nprob];
+  if (total < 1) return;
+  const long long blocks = (total + 7) / 8 * 8;
+  if (blocks > 0x7fffffffLL) fail(PSIM_EUNSUPPORTED, "grid too large");
+  if (variant == 16)
+    hipLaunchKernelGGL((site_gemm_group<float, 256, 64, 16, ROWMAJOR, true, 4>), dim3((unsigned)blocks), dim3(256), 0,
+                       st, ga);
+  else if (variant == 17)
+    hipLaunchKernelGGL((site_gemm_group<float, 256, 64, 16, KMAJOR, true, 4>), dim3((unsigned)blocks), dim3(256), 0,
+                       st, ga);
+  else if (variant < 8)
+    glaunch_mode<4>((variant >> 1) & 3, variant & 1, ga, blocks, st);
+  else
+    glaunch_mode<3>((variant >> 1) & 3, variant & 1, ga, blocks, st);
+  hip_check(hipGetLastError(), "grouped site_gemm launch");
+}
+
+int kargs_bytes() { return (int)sizeof(KArgs); }
+int max_group() { return kMaxGroup; }
+
+void launch_site_gemm(const GemmLaunch& g, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  KArgs a = make_kargs(g);
   // batch entries = nodes * Bz; the kernel splits z = node * Bz + v
   const long long Z = g.nodes * g.Bz;
   if (g.prec == PSIM_FP64) {
@@ -797,10 +929,7 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
     b.T = b.MT * b.NT * Z;
     const long long blocks = (b.T + 7) / 8 * 8;
     if (blocks > 0x7fffffffLL) fail(PSIM_EUNSUPPORTED, "grid too large");
-    // 16-byte vector loads need every batch entry's A to start 16-byte aligned
-    const bool even_base = ((uintptr_t)g.A % 16 == 0) && (g.sA_node % 2 == 0) && (g.sA_v % 2 == 0);
-    const int mode = (g.K2 % 2 == 0 && even_base) ? ROWMAJOR
-                     : (g.K2 == 1 && g.M % 2 == 0 && g.K1 > 1 && even_base) ? KMAJOR : GENERIC;
+    const int mode = fp32_mode(g);
     // interior-only tiles of bm rows and bk reals per stage
     auto fast = [&](int bm, int bk) {
       return mode == ROWMAJOR && g.M % bm == 0 && (2 * g.K1 * g.K2) % bk == 0 && (2 * g.K2) % bk == 0;

@@ -331,6 +331,15 @@ psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o) {
       lev.group = (int)std::min<int64_t>(lev.group, lev.cap);
       lev.F_off = (i % 2) ? Fb[0] : 0;
     }
+    // device operations per sub-batch: per level, every node group runs L
+    // site contractions per v chunk, then one rescale
+    pl->max_ops = 0;
+    for (int i = 0; i < R; ++i) {
+      const Level& lev = pl->levels[i];
+      const int64_t groups = (lev.cap + lev.group - 1) / lev.group;
+      const int64_t chunks = L == 1 ? 1 : (lev.Dv + lev.vchunk - 1) / lev.vchunk;
+      pl->max_ops += groups * chunks * L + 1;
+    }
     pl->ws_F = Fb[0] + Fb[1];
     pl->ws_G = G;
     pl->ws_total = pl->ws_tab + pl->ws_F + pl->ws_G + 256;

@@ -104,13 +104,24 @@ struct psim_plan_s {
   bool host_only = false;
   int elem_bytes = 8;
   void* d_ones = nullptr;                // device scalar 1 (the empty boundary before row 0)
-  bool in_subbatch = false;              // scheduler re-entry guard
   bool profile = false;                  // time launches with events
   psim_kernel_stats prof[4] = {};
   // PSIM_PLAN_GRAPH: instantiated graphs of the row sweep, keyed by workspace
   // address and node count per level, and the stream they are captured on
   std::map<std::vector<int64_t>, void*> graphs;
   void* cap_stream = nullptr;
+  int64_t max_ops = 0;                   // most device operations one sub-batch can need
+};
+
+// Plans run together (psim_group): the plans are borrowed; the group owns the
+// device array of launch descriptors (max_ops slots per plan).
+struct psim_group_s {
+  std::vector<psim_plan_s*> plans;
+  std::vector<uint64_t> desc_off;        // byte offset of each plan's slots
+  void* d_desc = nullptr;
+  uint64_t desc_bytes = 0;
+  int device = 0;
+  int64_t grouped_launches = 0;
 };
 
 namespace psim {
@@ -149,6 +160,14 @@ struct GemmLaunch {
 int fp32_config_count();
 int fp32_3m_config_count();
 void launch_site_gemm(const GemmLaunch& g, void* stream);
+// Grouped launches (several problems, one grid): returns the variant id and
+// writes the problem descriptor (kargs_bytes() bytes) to out and its tile
+// count to *tiles, or returns -1 when the launch is not groupable.
+int group_variant(const GemmLaunch& g, void* out, long long* tiles);
+int kargs_bytes();
+int max_group();
+// d_probs[i]: device address of problem i's descriptor; start[0..nprob]: tile offsets
+void launch_group(int variant, const void* const* d_probs, const long long* start, int nprob, void* stream);
 void launch_rowscale(int prec, void* F, int64_t elems_per_node, int64_t nodes, const int32_t* parent,
                      const int32_t* exp_prev, int32_t* exp_cur, uint32_t* scratch_max, void* stream);
 void launch_fill_ones(int prec, void* p, void* stream);

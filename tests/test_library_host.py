@@ -124,3 +124,16 @@ def test_tile_cfg_validation(ps):
         with pytest.raises(ps.PsimError) as e:
             ps.Plan(P, prec=prec, host_only=True, tile_cfg=bad)
         assert e.value.status == ps.PSIM_EINVAL
+
+
+def test_group_rejects_host_only_and_empty(ps):
+    P = ps.Peps(rqcgen.generate(3, 3, 8, 0))
+    pl = ps.Plan(P, prec="fp32", host_only=True)
+    with pytest.raises(ps.PsimError) as e:
+        ps.Group([pl])
+    assert e.value.status == ps.PSIM_EINVAL and "HOST_ONLY" in str(e.value)
+    L = ps.lib()
+    h = ctypes.c_void_p()
+    assert L.psim_group(None, 0, ctypes.byref(h)) == ps.PSIM_EINVAL
+    arr = (ctypes.c_void_p * 1)(None)
+    assert L.psim_group(arr, 1, ctypes.byref(h)) == ps.PSIM_EINVAL
