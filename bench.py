@@ -206,68 +206,80 @@ def fig2_program(args):
                                         for m, h in zip(mids, hist)]}), flush=True)
 
 
-# Mixed batch: (lv, lh, depth) of circuits with uneven lattices and depths,
-# seed = position in the list, MIXED_BITS random bitstrings each
-MIXED = [(3, 3, 8), (3, 4, 13), (2, 6, 16), (4, 4, 16), (4, 4, 24), (4, 5, 24),
-         (5, 5, 16), (5, 5, 24), (3, 6, 24), (6, 6, 16), (5, 6, 24), (6, 6, 24)]
-MIXED_BITS = 64
+# Mixed batches: (lv, lh, depth) of circuits with uneven lattices and depths,
+# seed = position in the list, a fixed number of random bitstrings each.
+# "large": 3x3 .. 6x6 up to depth (1+24+1), 64 bitstrings each (the 6x6 d24
+# circuit carries most of the work); "small": 48 circuits of at most 20
+# qubits, 16 bitstrings each (launch-bound when run one by one).
+MIXED = {
+    "large": ([(3, 3, 8), (3, 4, 13), (2, 6, 16), (4, 4, 16), (4, 4, 24), (4, 5, 24),
+               (5, 5, 16), (5, 5, 24), (3, 6, 24), (6, 6, 16), (5, 6, 24), (6, 6, 24)], 64),
+    "small": ([(lv, lh, d) for d in (8, 12, 16, 20, 24, 13, 17, 21)
+               for lv, lh in ((3, 3), (3, 4), (4, 4), (4, 5), (2, 6), (3, 5))], 16),
+}
 
 
 def mixed_program(args):
-    """Mixed batch of 3x3 .. 6x6 circuits of uneven depth: every circuit's
+    """Mixed batches of circuits of uneven size and depth: every circuit's
     bitstrings contracted (a) plan by plan, one psim_amplitudes call each, and
     (b) all plans together in one psim_group_amplitudes call, whose merged
-    launches cover the tiles of several circuits at once."""
+    launches cover the tiles of several circuits at once; each both eagerly
+    and with HIP-graph replay."""
     import numpy as np
     import torch
     import paper_1905_08394_amd as ps
     import rqcgen
-    circuits, bits = [], []
-    for k, (lv, lh, d) in enumerate(MIXED):
-        circuits.append(rqcgen.generate(lv, lh, d, k))
-        bits.append(rqcgen.bitstrings(lv, lh, k, MIXED_BITS))
-    plans = []
-    for c, b in zip(circuits, bits):
-        P = ps.Peps(c)
-        plans.append(ps.Plan(P, prec=args.prec, max_batch=len(b)))
-        P.close()
-    for p in plans:
-        p.workspace()
-    group = ps.Group(plans)
-    cmac = sum(p.stats()["cmac_per_amplitude"] * len(b) for p, b in zip(plans, bits))
-    n_amp = sum(len(b) for b in bits)
-
-    def seq():
-        return [p.amplitudes(b) for p, b in zip(plans, bits)]
-
-    def grp():
-        return group.amplitudes(bits)
-
-    ref = seq()
-    out = grp()
-    same = all(np.array_equal(a, r) for a, r in zip(out, ref))
-    launches0 = group.stats()["grouped_launches"]
-    times = {}
-    for name, fn in (("per_plan", seq), ("grouped", grp)):
-        ts = []
-        for r in range(max(args.steps, 5)):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            fn()
-            torch.cuda.synchronize()
-            ts.append(time.perf_counter() - t0)
-        times[name] = float(np.median(ts))
-        log(f"mixed {name}: median {times[name] * 1e3:.2f} ms over {len(ts)} runs")
-    merged = (group.stats()["grouped_launches"] - launches0) // max(args.steps, 5)
-    print(json.dumps({
-        "workload": "mixed batch: " + ", ".join(f"{lv}x{lh} (1+{d}+1)" for lv, lh, d in MIXED) +
-                    f"; {MIXED_BITS} random bitstrings each, seeds 0..{len(MIXED) - 1}",
-        "prec": args.prec, "amplitudes": n_amp, "cmac": cmac,
-        "per_plan_s": times["per_plan"], "grouped_s": times["grouped"],
-        "speedup": times["per_plan"] / times["grouped"],
-        "grouped_amplitudes_per_s": n_amp / times["grouped"],
-        "grouped_tflops": 8 * cmac / times["grouped"] / 1e12,
-        "merged_launches_per_call": merged, "bitwise_equal_to_per_plan": same}), flush=True)
+    for name, (spec, nbits) in MIXED.items():
+        circuits, bits = [], []
+        for k, (lv, lh, d) in enumerate(spec):
+            circuits.append(rqcgen.generate(lv, lh, d, k))
+            bits.append(rqcgen.bitstrings(lv, lh, k, nbits))
+        res = {}
+        times = {}
+        merged = {}
+        for graph in (False, True):
+            plans = []
+            for c, b in zip(circuits, bits):
+                P = ps.Peps(c)
+                plans.append(ps.Plan(P, prec=args.prec, max_batch=len(b), graph=graph))
+                P.close()
+            for p in plans:
+                p.workspace()
+            group = ps.Group(plans)
+            cmac = sum(p.stats()["cmac_per_amplitude"] * len(b) for p, b in zip(plans, bits))
+            tag = "_graph" if graph else ""
+            fns = {"per_plan" + tag: lambda: [p.amplitudes(b) for p, b in zip(plans, bits)],
+                   "grouped" + tag: lambda: group.amplitudes(bits)}
+            for fname, fn in fns.items():
+                res[fname] = fn()                       # warm (captures graphs)
+                reps = max(args.steps, 7)
+                l0 = group.stats()["grouped_launches"]
+                ts = []
+                for r in range(reps):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    fn()
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t0)
+                times[fname] = float(np.median(ts))
+                merged[fname] = (group.stats()["grouped_launches"] - l0) // reps
+                log(f"mixed {name} {fname}: median {times[fname] * 1e3:.2f} ms over {reps} runs")
+            group.close()
+            for p in plans:
+                p.close()
+        ref = res["per_plan"]
+        same = all(all(np.array_equal(a, r) for a, r in zip(res[k], ref)) for k in res)
+        n_amp = sum(len(b) for b in bits)
+        best = min(times, key=times.get)
+        print(json.dumps({
+            "workload": f"mixed batch '{name}': " + ", ".join(f"{lv}x{lh} (1+{d}+1)" for lv, lh, d in spec) +
+                        f"; {nbits} random bitstrings each, seeds 0..{len(spec) - 1}",
+            "prec": args.prec, "circuits": len(spec), "amplitudes": n_amp, "cmac": cmac,
+            "seconds": times, "speedup_grouped_vs_per_plan": times["per_plan"] / times["grouped"],
+            "speedup_grouped_graph_vs_per_plan": times["per_plan"] / times["grouped_graph"],
+            "best": best, "best_amplitudes_per_s": n_amp / times[best],
+            "best_contraction_tflops": 8 * cmac / times[best] / 1e12,
+            "merged_launches_per_call": merged["grouped"], "all_bitwise_equal_to_per_plan": same}), flush=True)
 
 
 def main():
@@ -288,7 +300,7 @@ def main():
     ap.add_argument("--counters", action="store_true", help="short program for rocprofv3 --pmc passes")
     ap.add_argument("--fig2", action="store_true", help="8x8 (1+25+1) Porter-Thomas experiment")
     ap.add_argument("--fig2-count", type=int, default=2048)
-    ap.add_argument("--mixed", action="store_true", help="mixed batch of 3x3..6x6 circuits, grouped vs per plan")
+    ap.add_argument("--mixed", action="store_true", help="mixed batches of 3x3..6x6 circuits, grouped vs per plan")
     args = ap.parse_args()
     if args.mixed:
         mixed_program(args)

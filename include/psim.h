@@ -213,7 +213,10 @@ psim_status psim_group_info(const psim_group_t *group, psim_group_stats *out);
  * device operation of every plan; FP32 (4M / 3M, default tiles, no split
  * accumulation) site contractions of one step that use the same kernel are
  * merged into one launch over all their tiles, everything else is launched
- * per plan.  Each plan's results equal psim_amplitudes' bit for bit.
+ * per plan.  Each plan's results equal psim_amplitudes' bit for bit.  When
+ * every plan was made with PSIM_PLAN_GRAPH, each pass of the sweep is
+ * captured into a HIP graph the first time its shape (plans taking part,
+ * workspaces, prefix-trie sizes) is seen, and replayed afterwards.
  * Enqueues on hip_stream and synchronises it.
  * Errors: as psim_amplitudes, for the first failing plan (its index in the
  * message); EINVAL for overlapping workspaces. */

@@ -64,9 +64,13 @@ Trie build_trie(const psim_plan_t& pl, const uint8_t* bits, size_t n) {
   return t;
 }
 
-// Workspace layout: per-level trie tables, exponents, row maxima, the two
-// boundary buffers (even / odd rows) and the two intermediate buffers.
+// Workspace layout: per-level trie tables, exponents, row maxima (the table
+// region, pl.ws_tab bytes at the start), the two boundary buffers (even / odd
+// rows) and the two intermediate buffers.  A grouped run may place the table
+// region elsewhere (tab != NULL); the boundary and intermediate buffers stay
+// where they are.
 struct WsLayout {
+  char* tab;
   std::vector<int32_t*> parent;
   std::vector<uint8_t*> tau;
   int32_t* exp[2];
@@ -75,10 +79,12 @@ struct WsLayout {
   char* G[2];
 };
 
-WsLayout layout(const psim_plan_t& pl, void* ws) {
+WsLayout layout(const psim_plan_t& pl, void* ws, char* tab = nullptr) {
   auto al = [](uint64_t x) { return (x + 255) / 256 * 256; };
-  char* p = (char*)(((uintptr_t)ws + 255) / 256 * 256);
+  char* base = (char*)(((uintptr_t)ws + 255) / 256 * 256);
+  char* p = tab ? tab : base;
   WsLayout w;
+  w.tab = p;
   const int R = pl.R, L = pl.L;
   w.parent.resize(R);
   w.tau.resize(R);
@@ -94,6 +100,7 @@ WsLayout layout(const psim_plan_t& pl, void* ws) {
   w.exp[0] = (int32_t*)p; p += al((uint64_t)nmax_all * 4);
   w.exp[1] = (int32_t*)p; p += al((uint64_t)nmax_all * 4);
   w.mx = (uint32_t*)p; p += al((uint64_t)nmax_all * 4);
+  p = base + pl.ws_tab;
   w.F[0] = p + pl.levels[0].F_off;
   w.F[1] = p + (R > 1 ? pl.levels[1].F_off : 0);
   p += pl.ws_F;
@@ -252,8 +259,12 @@ struct Prepared {
   std::vector<int32_t> ex;    // and their exponents
 };
 
-void prepare(psim_plan_t* pl, const uint8_t* bits, const std::vector<size_t>& idx, void* ws, hipStream_t st,
-             Prepared& P) {
+// Builds the trie and the operation list of one sub-batch.  The trie tables
+// and the root exponent are written to tab_img, the host image of the table
+// region (pl->ws_tab bytes, zero-filled by the caller); the caller uploads it
+// to P.W.tab before the operations run.
+void prepare(psim_plan_t* pl, const uint8_t* bits, const std::vector<size_t>& idx, void* ws, char* tab_dev,
+             char* tab_img, Prepared& P) {
   const int R = pl->R, L = pl->L, prec = pl->opts.prec, nq = pl->lv * pl->lh;
   const uint64_t eb = pl->elem_bytes;
   P.pl = pl;
@@ -261,18 +272,16 @@ void prepare(psim_plan_t* pl, const uint8_t* bits, const std::vector<size_t>& id
   P.bits.resize(P.n * nq);
   for (size_t x = 0; x < P.n; ++x) std::memcpy(&P.bits[x * nq], bits + idx[x] * nq, nq);
   P.t = build_trie(*pl, P.bits.data(), P.n);
-  P.W = layout(*pl, ws);
+  P.W = layout(*pl, ws, tab_dev);
   const Trie& t = P.t;
   WsLayout& W = P.W;
   for (int i = 0; i < R; ++i) {
     if ((int64_t)t.parent[i].size() > pl->levels[i].cap) fail(PSIM_EINTERNAL, "trie larger than planned");
-    hip_check(hipMemcpyAsync(W.parent[i], t.parent[i].data(), t.parent[i].size() * 4, hipMemcpyHostToDevice, st),
-              "upload parents");
-    hip_check(hipMemcpyAsync(W.tau[i], t.tau[i].data(), t.tau[i].size(), hipMemcpyHostToDevice, st), "upload bits");
+    std::memcpy(tab_img + ((char*)W.parent[i] - W.tab), t.parent[i].data(), t.parent[i].size() * 4);
+    std::memcpy(tab_img + ((char*)W.tau[i] - W.tab), t.tau[i].data(), t.tau[i].size());
   }
   // root exponent 0
-  static const int32_t zero = 0;
-  hip_check(hipMemcpyAsync(W.exp[1], &zero, 4, hipMemcpyHostToDevice, st), "upload exponent");
+  std::memset(tab_img + ((char*)W.exp[1] - W.tab), 0, 4);
 
   P.ops.clear();
   for (int i = 0; i < R; ++i) {
@@ -420,7 +429,9 @@ void assemble(const Prepared& P, const std::vector<size_t>& idx, double* out) {
 void run_one(psim_plan_t* pl, const uint8_t* bits, const std::vector<size_t>& idx, void* ws, hipStream_t st,
              double* out) {
   Prepared P;
-  prepare(pl, bits, idx, ws, st, P);
+  std::vector<char> img(pl->ws_tab, 0);
+  prepare(pl, bits, idx, ws, nullptr, img.data(), P);
+  hip_check(hipMemcpyAsync(P.W.tab, img.data(), img.size(), hipMemcpyHostToDevice, st), "upload tables");
 
   struct Timed {
     hipEvent_t a, b;
@@ -529,10 +540,13 @@ void run_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, si
 // tiles); the others are launched one by one.  Every plan's operations stay
 // in their own order on the one stream, so each plan computes exactly what
 // psim_amplitudes computes for it.
+void free_group(psim_group_s* G);
+
 psim_group_s* make_group(psim_plan_t* const* plans, int np) {
   if (!plans || np < 1) fail(PSIM_EINVAL, "plans is NULL or empty");
   auto* G = new psim_group_s();
   try {
+    auto al = [](uint64_t x) { return (x + 255) / 256 * 256; };
     uint64_t off = 0;
     const uint64_t kb = (uint64_t)kargs_bytes();
     for (int p = 0; p < np; ++p) {
@@ -542,14 +556,29 @@ psim_group_s* make_group(psim_plan_t* const* plans, int np) {
       if (pl->opts.device != plans[0]->opts.device) fail(PSIM_EINVAL, "plans are on different devices");
       G->plans.push_back(pl);
       G->desc_off.push_back(off);
-      off += (uint64_t)pl->max_ops * kb;
+      off += al((uint64_t)pl->max_ops * kb);
+      G->tab_off.push_back(off);
+      off += al(pl->ws_tab);
     }
+    G->seg_off = off;
+    off += al((uint64_t)np * 2 * sizeof(CopySeg));
+    G->res_begin = off;
+    for (int p = 0; p < np; ++p) {
+      const psim_plan_t* pl = plans[p];
+      const uint64_t leaves = (uint64_t)pl->levels[pl->R - 1].cap;
+      G->res_off.push_back(off);
+      off += al(leaves * pl->elem_bytes);
+      G->res_exp_off.push_back(off);
+      off += al(leaves * 4);
+    }
+    G->bytes = off;
     G->device = plans[0]->opts.device;
     G->desc_bytes = off;
     hip_check(hipSetDevice(G->device), "hipSetDevice");
-    hip_check(hipMalloc(&G->d_desc, off), "hipMalloc(group descriptors)");
+    hip_check(hipMalloc(&G->d_buf, off), "hipMalloc(group buffer)");
+    hip_check(hipHostMalloc((void**)&G->h_buf, off, hipHostMallocDefault), "hipHostMalloc(group staging)");
   } catch (...) {
-    delete G;
+    free_group(G);
     throw;
   }
   return G;
@@ -557,7 +586,10 @@ psim_group_s* make_group(psim_plan_t* const* plans, int np) {
 
 void free_group(psim_group_s* G) {
   if (!G) return;
-  if (G->d_desc) (void)hipFree(G->d_desc);
+  for (auto& kv : G->graphs) (void)hipGraphExecDestroy((hipGraphExec_t)kv.second.first);
+  if (G->cap_stream) (void)hipStreamDestroy((hipStream_t)G->cap_stream);
+  if (G->d_buf) (void)hipFree(G->d_buf);
+  if (G->h_buf) (void)hipHostFree(G->h_buf);
   delete G;
 }
 
@@ -591,63 +623,142 @@ void run_group(psim_group_s* G, const uint8_t* const* bits, const size_t* n, voi
   }
   const int kb = kargs_bytes();
   const int maxg = max_group();
+  const int maxs = max_scale_group();
+  char* dbuf = (char*)G->d_buf;
+  char* hbuf = G->h_buf;
+  CopySeg* hseg = (CopySeg*)(hbuf + G->seg_off);
   for (size_t pass = 0; pass < passes; ++pass) {
+    // host image of everything the pass reads: trie tables (relocated into
+    // the group buffer), launch descriptors, the result-gather segments
     std::vector<Prepared> P;
     std::vector<int> who;
     for (int p = 0; p < np; ++p)
       if (pass < subs[p].size()) {
         P.emplace_back();
         who.push_back(p);
-        prepare(G->plans[p], bits[p], subs[p][pass], ws[p], st, P.back());
+        std::memset(hbuf + G->tab_off[p], 0, G->plans[p]->ws_tab);
+        prepare(G->plans[p], bits[p], subs[p][pass], ws[p], dbuf + G->tab_off[p], hbuf + G->tab_off[p], P.back());
       }
-    // descriptors of every groupable contraction, one upload per plan
     const size_t m = P.size();
-    std::vector<std::vector<char>> desc(m);
     std::vector<std::vector<int>> variant(m);
     std::vector<std::vector<long long>> tiles(m);
     size_t steps = 0;
+    int64_t max_seg = 0;
     for (size_t q = 0; q < m; ++q) {
+      const int p = who[q];
       const auto& ops = P[q].ops;
       steps = std::max(steps, ops.size());
-      desc[q].resize(ops.size() * kb);
       variant[q].assign(ops.size(), -1);
       tiles[q].assign(ops.size(), 0);
       for (size_t k = 0; k < ops.size(); ++k)
-        if (!ops[k].rescale) variant[q][k] = group_variant(ops[k].g, &desc[q][k * kb], &tiles[q][k]);
-      char* d = (char*)G->d_desc + G->desc_off[who[q]];
-      hip_check(hipMemcpyAsync(d, desc[q].data(), desc[q].size(), hipMemcpyHostToDevice, st), "upload descriptors");
+        if (!ops[k].rescale) variant[q][k] = group_variant(ops[k].g, hbuf + G->desc_off[p] + k * kb, &tiles[q][k]);
+      const psim_plan_t* pl = P[q].pl;
+      const int64_t leaves = (int64_t)P[q].t.parent[pl->R - 1].size();
+      hseg[2 * q] = CopySeg{P[q].W.F[(pl->R - 1) % 2], dbuf + G->res_off[p], leaves * pl->elem_bytes};
+      hseg[2 * q + 1] = CopySeg{P[q].W.exp[(pl->R - 1) % 2], dbuf + G->res_exp_off[p], leaves * 4};
+      max_seg = std::max(max_seg, leaves * (int64_t)pl->elem_bytes);
     }
-    for (size_t k = 0; k < steps; ++k) {
-      std::map<int, std::vector<std::pair<size_t, size_t>>> byvar;  // variant -> (plan slot, op)
-      for (size_t q = 0; q < m; ++q) {
-        if (k >= P[q].ops.size()) continue;
-        if (variant[q][k] < 0)
-          run_op(P[q].pl, P[q].ops[k], st);
-        else
-          byvar[variant[q][k]].emplace_back(q, k);
-      }
-      for (auto& kv : byvar) {
-        const auto& lst = kv.second;
-        if (lst.size() == 1) {  // nothing to merge with
-          run_op(P[lst[0].first].pl, P[lst[0].first].ops[lst[0].second], st);
-          continue;
+    hip_check(hipMemcpyAsync(dbuf, hbuf, G->res_begin, hipMemcpyHostToDevice, st), "upload group tables");
+    // the interleaved sweep; returns the number of merged launches issued
+    auto issue = [&](hipStream_t ls) {
+      int64_t merged = 0;
+      for (size_t k = 0; k < steps; ++k) {
+        std::map<int, std::vector<std::pair<size_t, size_t>>> byvar;  // variant -> (plan slot, op)
+        std::map<int, std::vector<RescaleJob>> scale;  // storage (FP64 or FP32) -> fused rescales
+        for (size_t q = 0; q < m; ++q) {
+          if (k >= P[q].ops.size()) continue;
+          const Op& op = P[q].ops[k];
+          if (op.rescale && rescale_fusable(op.F_elems))
+            scale[P[q].pl->elem_bytes == 16 ? PSIM_FP64 : PSIM_FP32_4M].push_back(
+                RescaleJob{op.F, op.F_elems, op.nodes, op.parent, op.e_in, op.e_out});
+          else if (variant[q][k] < 0)
+            run_op(P[q].pl, op, ls);
+          else
+            byvar[variant[q][k]].emplace_back(q, k);
         }
-        for (size_t a = 0; a < lst.size(); a += maxg) {
-          const int cnt = (int)std::min<size_t>(maxg, lst.size() - a);
-          std::vector<const void*> probs(cnt);
-          std::vector<long long> start(cnt + 1, 0);
-          for (int x = 0; x < cnt; ++x) {
-            const size_t q = lst[a + x].first, kk = lst[a + x].second;
-            probs[x] = (const char*)G->d_desc + G->desc_off[who[q]] + kk * kb;
-            start[x + 1] = start[x] + tiles[q][kk];
+        for (auto& kv : scale)
+          for (size_t a = 0; a < kv.second.size(); a += maxs) {
+            const int cnt = (int)std::min<size_t>(maxs, kv.second.size() - a);
+            launch_rescale_group(kv.first, kv.second.data() + a, cnt, ls);
           }
-          launch_group(kv.first, probs.data(), start.data(), cnt, st);
-          G->grouped_launches += 1;
+        for (auto& kv : byvar) {
+          const auto& lst = kv.second;
+          if (lst.size() == 1) {  // nothing to merge with
+            run_op(P[lst[0].first].pl, P[lst[0].first].ops[lst[0].second], ls);
+            continue;
+          }
+          for (size_t a = 0; a < lst.size(); a += maxg) {
+            const int cnt = (int)std::min<size_t>(maxg, lst.size() - a);
+            std::vector<const void*> probs(cnt);
+            std::vector<long long> start(cnt + 1, 0);
+            for (int x = 0; x < cnt; ++x) {
+              const size_t q = lst[a + x].first, kk = lst[a + x].second;
+              probs[x] = dbuf + G->desc_off[who[q]] + kk * kb;
+              start[x + 1] = start[x] + tiles[q][kk];
+            }
+            launch_group(kv.first, probs.data(), start.data(), cnt, ls);
+            merged += 1;
+          }
         }
       }
+      // every plan's leaf values and exponents into the group buffer
+      launch_copy_segments((const CopySeg*)(dbuf + G->seg_off), (int)(2 * m), max_seg, ls);
+      return merged;
+    };
+    // Graph replay when every plan asks for it: the launch sequence depends
+    // only on which plans take part, their workspaces and their trie shapes
+    // (the descriptors and tables it reads were uploaded above).
+    bool use_graph = true;
+    for (size_t q = 0; q < m; ++q) use_graph = use_graph && (P[q].pl->opts.flags & PSIM_PLAN_GRAPH);
+    if (!use_graph) {
+      G->grouped_launches += issue(st);
+    } else {
+      std::vector<int64_t> key;
+      for (size_t q = 0; q < m; ++q) {
+        key.push_back(who[q]);
+        key.push_back((int64_t)(uintptr_t)ws[who[q]]);
+        for (const auto& lev : P[q].t.parent) key.push_back((int64_t)lev.size());
+      }
+      auto it = G->graphs.find(key);
+      if (it == G->graphs.end()) {
+        if (!G->cap_stream) {
+          hipStream_t cs;
+          hip_check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
+          G->cap_stream = cs;
+        }
+        hipStream_t cs = (hipStream_t)G->cap_stream;
+        hip_check(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+        int64_t merged = 0;
+        try {
+          merged = issue(cs);
+        } catch (...) {
+          hipGraph_t graph = nullptr;
+          (void)hipStreamEndCapture(cs, &graph);
+          if (graph) (void)hipGraphDestroy(graph);
+          throw;
+        }
+        hipGraph_t graph = nullptr;
+        hip_check(hipStreamEndCapture(cs, &graph), "hipStreamEndCapture");
+        hipGraphExec_t gexec = nullptr;
+        const hipError_t e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        hip_check(e, "hipGraphInstantiate");
+        it = G->graphs.emplace(key, std::make_pair((void*)gexec, merged)).first;
+      }
+      hip_check(hipGraphLaunch((hipGraphExec_t)it->second.first, st), "hipGraphLaunch");
+      G->grouped_launches += it->second.second;
     }
-    for (size_t q = 0; q < m; ++q) enqueue_download(P[q], st);
+    hip_check(hipMemcpyAsync(hbuf + G->res_begin, dbuf + G->res_begin, G->bytes - G->res_begin,
+                             hipMemcpyDeviceToHost, st), "download group results");
     hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
-    for (size_t q = 0; q < m; ++q) assemble(P[q], subs[who[q]][pass], out[who[q]]);
+    for (size_t q = 0; q < m; ++q) {
+      const int p = who[q];
+      const psim_plan_t* pl = P[q].pl;
+      const size_t leaves = P[q].t.parent[pl->R - 1].size();
+      P[q].vals.assign(hbuf + G->res_off[p], hbuf + G->res_off[p] + leaves * pl->elem_bytes);
+      P[q].ex.resize(leaves);
+      std::memcpy(P[q].ex.data(), hbuf + G->res_exp_off[p], leaves * 4);
+      assemble(P[q], subs[who[q]][pass], out[who[q]]);
+    }
   }
 }

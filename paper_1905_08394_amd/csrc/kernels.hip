@@ -28,6 +28,7 @@
 // site of a row) and transposes into LDS, GENERIC reads one complex at a time.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstring>
 
@@ -749,6 +750,59 @@ __global__ void row_apply(T* __restrict__ F, long long per_node, const uint32_t*
     f[x] = ldexp(f[x], -e);
 }
 
+// Fused rescale for small boundaries, several problems per launch: one
+// workgroup per node finds the node's largest component, its exponent e,
+// the node's running exponent (parent's plus e) and scales the node by 2^-e.
+// Same results as row_absmax + row_exponent + row_apply.
+constexpr int kMaxScale = 32;
+struct ScaleProb {
+  void* F;
+  long long per_node;  // complex elements per node
+  const int32_t* parent;
+  const int32_t* exp_prev;
+  int32_t* exp_cur;
+};
+struct ScaleArgs {
+  ScaleProb p[kMaxScale];
+  long long start[kMaxScale + 1];  // first global node of each problem; start[n] = total
+  int n;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void row_rescale_fused(ScaleArgs a) {
+  const long long g = blockIdx.x;
+  int lo = 0, hi = a.n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.start[mid] <= g) lo = mid; else hi = mid - 1;
+  }
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  const long long node = g - a.start[lo];
+  const long long len = 2 * a.p[lo].per_node;
+  T* f = (T*)a.p[lo].F + node * len;
+  T m = 0;
+  for (long long x = threadIdx.x; x < len; x += blockDim.x) m = fmax(m, fabs(f[x]));
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  __shared__ T red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  int e = 0;
+  if (m > 0) frexp(m, &e);
+  if (threadIdx.x == 0) a.p[lo].exp_cur[node] = a.p[lo].exp_prev[a.p[lo].parent[node]] + e;
+  if (e == 0) return;
+  for (long long x = threadIdx.x; x < len; x += blockDim.x) f[x] = ldexp(f[x], -e);
+}
+
+__global__ void copy_segments(const CopySeg* __restrict__ segs) {
+  const CopySeg sg = segs[blockIdx.y];
+  const unsigned char* a = (const unsigned char*)sg.src;
+  unsigned char* b = (unsigned char*)sg.dst;
+  for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < sg.bytes;
+       x += (long long)gridDim.x * blockDim.x)
+    b[x] = a[x];
+}
+
 __global__ void zero_u32(uint32_t* p, long long n) {
   const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (x < n) p[x] = 0;
@@ -1046,9 +1100,47 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
   hip_check(hipGetLastError(), "site_gemm launch");
 }
 
+void launch_copy_segments(const CopySeg* d_segs, int n, int64_t max_bytes, void* stream) {
+  if (n < 1) return;
+  if (n > 65535) fail(PSIM_EUNSUPPORTED, "too many segments for one gather");
+  const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_bytes + 255) / 256, 64));
+  hipLaunchKernelGGL(copy_segments, dim3(gx, (unsigned)n), dim3(256), 0, (hipStream_t)stream, d_segs);
+  hip_check(hipGetLastError(), "gather launch");
+}
+
+bool rescale_fusable(int64_t per_node) { return 2 * per_node <= kFusedScaleReals; }
+int max_scale_group() { return kMaxScale; }
+
+void launch_rescale_group(int prec, const RescaleJob* jobs, int n, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (n < 1 || n > kMaxScale) fail(PSIM_EINTERNAL, "rescale group size out of range");
+  ScaleArgs a{};
+  long long total = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!rescale_fusable(jobs[i].per_node)) fail(PSIM_EINTERNAL, "boundary too large for the fused rescale");
+    a.p[i] = ScaleProb{jobs[i].F, jobs[i].per_node, jobs[i].parent, jobs[i].exp_prev, jobs[i].exp_cur};
+    a.start[i] = total;
+    total += jobs[i].nodes;
+  }
+  a.start[n] = total;
+  a.n = n;
+  if (total < 1) return;
+  if (total > 0x7fffffffLL) fail(PSIM_EUNSUPPORTED, "grid too large");
+  if (prec == PSIM_FP64)
+    hipLaunchKernelGGL(row_rescale_fused<double>, dim3((unsigned)total), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(row_rescale_fused<float>, dim3((unsigned)total), dim3(256), 0, st, a);
+  hip_check(hipGetLastError(), "fused rescale launch");
+}
+
 void launch_rowscale(int prec, void* F, int64_t per_node, int64_t nodes, const int32_t* parent,
                      const int32_t* exp_prev, int32_t* exp_cur, uint32_t* mx, void* stream) {
   hipStream_t st = (hipStream_t)stream;
+  if (rescale_fusable(per_node)) {  // small boundaries: one launch
+    RescaleJob j{F, per_node, nodes, parent, exp_prev, exp_cur};
+    launch_rescale_group(prec, &j, 1, stream);
+    return;
+  }
   const unsigned nb = (unsigned)((nodes + 255) / 256);
   hipLaunchKernelGGL(zero_u32, dim3(nb), dim3(256), 0, st, mx, nodes);
   long long per_block = 256 * 16;

@@ -117,11 +117,23 @@ struct psim_plan_s {
 // device array of launch descriptors (max_ops slots per plan).
 struct psim_group_s {
   std::vector<psim_plan_s*> plans;
-  std::vector<uint64_t> desc_off;        // byte offset of each plan's slots
-  void* d_desc = nullptr;
+  // One device buffer and a pinned host mirror at the same offsets: per plan
+  // the launch descriptors (max_ops slots) and the trie-table region, the
+  // result-gather segment table, then per plan the gathered leaf values and
+  // exponents.  [0, res_off) is uploaded once per pass, [res_off, bytes)
+  // downloaded once per pass.
+  std::vector<uint64_t> desc_off, tab_off, res_off, res_exp_off;
+  uint64_t seg_off = 0, res_begin = 0, bytes = 0;
+  void* d_buf = nullptr;
+  char* h_buf = nullptr;
   uint64_t desc_bytes = 0;
   int device = 0;
   int64_t grouped_launches = 0;
+  // all plans with PSIM_PLAN_GRAPH: instantiated graphs of a pass, keyed by
+  // (plan slot, workspace address, nodes per level) of every plan in it, with
+  // the number of merged launches each holds; the stream they are captured on
+  std::map<std::vector<int64_t>, std::pair<void*, int64_t>> graphs;
+  void* cap_stream = nullptr;
 };
 
 namespace psim {
@@ -171,6 +183,26 @@ void launch_group(int variant, const void* const* d_probs, const long long* star
 void launch_rowscale(int prec, void* F, int64_t elems_per_node, int64_t nodes, const int32_t* parent,
                      const int32_t* exp_prev, int32_t* exp_cur, uint32_t* scratch_max, void* stream);
 void launch_fill_ones(int prec, void* p, void* stream);
+// Rescale of small boundaries (at most kFusedScaleReals reals per node) in one
+// fused launch, for up to max_scale_group() boundaries of one precision.
+constexpr int64_t kFusedScaleReals = 1 << 18;
+struct RescaleJob {
+  void* F;
+  int64_t per_node, nodes;
+  const int32_t* parent;
+  const int32_t* exp_prev;
+  int32_t* exp_cur;
+};
+// Device-side gather of small segments (one workgroup row per segment).
+struct CopySeg {
+  const void* src;
+  void* dst;
+  int64_t bytes;
+};
+void launch_copy_segments(const CopySeg* d_segs, int n, int64_t max_bytes, void* stream);
+bool rescale_fusable(int64_t per_node);
+int max_scale_group();
+void launch_rescale_group(int prec, const RescaleJob* jobs, int n, void* stream);
 
 void hip_check(int err, const char* what);
 

@@ -152,3 +152,26 @@ def test_group_errors(ps):
     assert st == ps.PSIM_EINVAL and "plan 1" in L.psim_last_error().decode()
     assert not outs[0].any() and not outs[1].any()
     g.close()
+
+
+def test_group_graph_replay(ps):
+    """Graph-captured grouped sweeps: first call captures, repeats replay;
+    every replay (with eager work and synchronisation in between) equals the
+    eager single-plan result bit for bit."""
+    import torch
+    mix = _mix()[:5]
+    eager = [ps.Plan(ps.Peps(c), prec="fp32_3m", max_batch=len(b)) for c, b in mix]
+    graphed = [ps.Plan(ps.Peps(c), prec="fp32_3m", max_batch=len(b), graph=True) for c, b in mix]
+    g = ps.Group(graphed)
+    sets = [[b for c, b in mix],
+            [rqcgen.bitstrings(c.lv, c.lh, 100 + k, len(b)) for k, (c, b) in enumerate(mix)]]
+    for r, which in enumerate([0, 1, 0, 0, 1]):
+        bits = sets[which]
+        got = g.amplitudes(bits)
+        x = torch.ones(1 << 20, device="cuda:0")       # eager work between replays
+        assert float(x.sum()) == float(1 << 20)
+        torch.cuda.synchronize()
+        for k, (p, b, a) in enumerate(zip(eager, bits, got)):
+            assert np.array_equal(a, p.amplitudes(b)), (r, k)
+    say(f"group graph replays ok, merged launches {g.stats()['grouped_launches']}")
+    g.close()
