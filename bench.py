@@ -333,13 +333,16 @@ def main():
     hot_tflops = issued * hot["cmac"] / (hot["ms"] / 1e3) / 1e12 if hot["ms"] > 0 else None
     peak = PEAK_TFLOPS[args.prec]
     traffic = None
+    tr = None
     tfile = TRAFFIC_FILE.format(prec=args.prec)
     if os.path.exists(tfile) and args.lattice == 6:
         with open(tfile) as f:
             tr = json.load(f)
-        if tr.get("kernel_source_sha256") == kernel_source_hash():
-            traffic = tr.get("bytes_per_launch")
     per_launch_cmac = hot["cmac"] / max(hot["launches"], 1)
+    if tr is not None and tr.get("kernel_source_sha256") == kernel_source_hash() and "issued_flops_per_launch" in tr:
+        # counters were taken on the largest interior launch; scale to this
+        # run's average launch by issued flops (same K and N, M differs)
+        traffic = tr["bytes_per_launch"] * issued * per_launch_cmac / tr["issued_flops_per_launch"]
     out = {
         "metric": METRIC,
         "value": elapsed / n_amp,

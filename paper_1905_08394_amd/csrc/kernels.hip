@@ -170,16 +170,22 @@ __device__ __forceinline__ void site_gemm_body(const KArgs& p, const long long t
   T rc[AMODE == GENERIC ? A_CPLX * 2 : 1];
   vec_t rb[B_VECS];
 
+  // ROWFAST: (k1, k2) of the next stage, advanced one stage per load (stages
+  // are loaded in order and never straddle a k1 block), so no division
+  long long fk1 = 0, fk2 = 0;
   auto load_a = [&](long long kr0) {
     if constexpr (AMODE == ROWFAST) {
-      const long long k = kr0 >> 1;
-      const long long k1 = k / p.K2, k2 = k - k1 * p.K2;
-      const T* base = A + 2 * (k1 * sK1 + m0 * p.K2 + k2);
+      const T* base = A + 2 * (fk1 * sK1 + m0 * p.K2 + fk2);
 #pragma unroll
       for (int it = 0; it < A_VECS; ++it) {
         const int lin = it * 256 + tid;
         const int row = lin / (BK / VN), kq = lin % (BK / VN);
         ra[it] = *(const vec_t*)(base + 2 * (long long)row * p.K2 + kq * VN);
+      }
+      fk2 += BK / 2;
+      if (fk2 == p.K2) {
+        fk2 = 0;
+        ++fk1;
       }
     } else if constexpr (AMODE == ROWMAJOR) {
 #pragma unroll
@@ -592,16 +598,20 @@ __global__ __launch_bounds__(256) void site_gemm_bf16x3(KArgs p) {
   f32x4 ra[A_VECS];
   f32x4 rbh[B_VECS], rbl[B_VECS];  // 16 bytes = 8 bf16 each
 
+  long long fk1 = 0, fk2 = 0;  // FAST: next stage's (k1, k2), as in ROWFAST
   auto load = [&](long long kr0) {
     if constexpr (FAST) {  // interior tile, stage inside one k1 (see ROWFAST)
-      const long long k = kr0 >> 1;
-      const long long k1 = k / p.K2, k2 = k - k1 * p.K2;
-      const float* base = A + 2 * (k1 * sK1 + m0 * p.K2 + k2);
+      const float* base = A + 2 * (fk1 * sK1 + m0 * p.K2 + fk2);
 #pragma unroll
       for (int it = 0; it < A_VECS; ++it) {
         const int lin = it * 256 + tid;
         const int row = lin / (BK / 4), kq = lin % (BK / 4);
         ra[it] = *(const f32x4*)(base + 2 * (long long)row * p.K2 + kq * 4);
+      }
+      fk2 += BK / 2;
+      if (fk2 == p.K2) {
+        fk2 = 0;
+        ++fk1;
       }
     } else {
 #pragma unroll
