@@ -372,6 +372,10 @@ def main():
         "pct_mfma_peak": tflops / peak * issued / 8,
         "s_per_single_amplitude": elapsed / args.steps,
         "kernel_ms": {k: round(v["ms"], 3) for k, v in prof.items()},
+        # memory-bound classes: algorithmic bytes / their time, against 8 TB/s
+        "hbm_kernels": {k: {"gb_per_s": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1),
+                            "frac_of_8tbs": round(v["bytes"] / (v["ms"] / 1e3) / 8e12, 3)}
+                        for k, v in prof.items() if k != "interior_site" and v["ms"] > 0},
         "roofline": {
             "bound": "mfma", "achieved": hot_tflops, "peak": peak, "unit": "TFLOP/s",
             "frac": (hot_tflops / peak) if hot_tflops else None,

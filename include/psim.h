@@ -175,11 +175,15 @@ psim_status psim_tune(psim_plan_t *plan, void *d_workspace, size_t workspace_byt
  * row (v summed, transposed store), 3 = per-row rescale.  op = 1 resets and
  * enables, op = 2 reads the accumulated totals into out[4] (nullable for
  * op 1/0), op = 0 disables.  cmac is the algorithmic complex multiply-add
- * count of the timed launches. */
+ * count of the timed launches, bytes their algorithmic memory traffic (for
+ * the memory-bound classes 0, 2 and 3). */
 typedef struct {
   double ms;          /* summed kernel time */
   int64_t launches;
   double cmac;
+  double bytes;       /* algorithmic device-memory bytes of the timed launches: operands read
+                         once, results written once (read too when accumulated), one site
+                         matrix per launch; rescale: boundary read twice, written once */
 } psim_kernel_stats;
 
 psim_status psim_profile(psim_plan_t *plan, int32_t op, psim_kernel_stats *out);

@@ -58,7 +58,8 @@ class PlanStats(ctypes.Structure):
 
 
 class KernelStats(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double), ("launches", ctypes.c_int64), ("cmac", ctypes.c_double)]
+    _fields_ = [("ms", ctypes.c_double), ("launches", ctypes.c_int64), ("cmac", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
 
 
 class GroupStats(ctypes.Structure):
@@ -226,7 +227,7 @@ class Plan:
     def profile_read(self) -> dict:
         out = (KernelStats * 4)()
         _check(lib().psim_profile(self._h, 2, out))
-        return {name: {"ms": out[i].ms, "launches": out[i].launches, "cmac": out[i].cmac}
+        return {name: {"ms": out[i].ms, "launches": out[i].launches, "cmac": out[i].cmac, "bytes": out[i].bytes}
                 for i, name in enumerate(KERNEL_CLASSES)}
 
     def profile_stop(self):

@@ -235,6 +235,7 @@ struct Op {
   bool rescale = false;
   int cls = 0;  // 0 first site, 1 interior site, 2 last site, 3 rescale
   double cmac = 0;
+  double bytes = 0;  // algorithmic device-memory traffic
   GemmLaunch g;
   // rescale arguments
   void* F = nullptr;
@@ -355,6 +356,9 @@ void prepare(psim_plan_t* pl, const uint8_t* bits, const std::vector<size_t>& id
           }
           op.cls = s.kind;
           op.cmac = (double)g.nodes * g.Bz * g.M * g.K1 * g.K2 * g.N;
+          op.bytes = (double)eb * ((double)g.nodes * g.Bz * g.K1 * g.M * g.K2 +
+                                   (double)g.nodes * g.Bz * g.M * g.N * (g.beta ? 2 : 1) +
+                                   (double)g.K1 * g.K2 * g.N);
           op.row = i;
           P.ops.push_back(op);
         }
@@ -365,6 +369,7 @@ void prepare(psim_plan_t* pl, const uint8_t* bits, const std::vector<size_t>& id
     Op op;
     op.rescale = true;
     op.cls = 3;
+    op.bytes = 3.0 * eb * (double)nodes * lev.F_elems;
     op.F = Fcur;
     op.F_elems = lev.F_elems;
     op.nodes = nodes;
@@ -436,7 +441,7 @@ void run_one(psim_plan_t* pl, const uint8_t* bits, const std::vector<size_t>& id
   struct Timed {
     hipEvent_t a, b;
     int cls;
-    double cmac;
+    double cmac, bytes;
   };
   std::vector<Timed> timed;
   const char* env_log = std::getenv("PSIM_LOG");
@@ -474,6 +479,7 @@ void run_one(psim_plan_t* pl, const uint8_t* bits, const std::vector<size_t>& id
           Timed tm{};
           tm.cls = op.cls;
           tm.cmac = op.cmac;
+          tm.bytes = op.bytes;
           hip_check(hipEventCreate(&tm.a), "hipEventCreate");
           hip_check(hipEventCreate(&tm.b), "hipEventCreate");
           hip_check(hipEventRecord(tm.a, lst), "hipEventRecord");
@@ -516,6 +522,7 @@ void run_one(psim_plan_t* pl, const uint8_t* bits, const std::vector<size_t>& id
     pl->prof[tm.cls].ms += ms;
     pl->prof[tm.cls].launches += 1;
     pl->prof[tm.cls].cmac += tm.cmac;
+    pl->prof[tm.cls].bytes += tm.bytes;
     (void)hipEventDestroy(tm.a);
     (void)hipEventDestroy(tm.b);
   }
