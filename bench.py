@@ -282,6 +282,54 @@ def mixed_program(args):
             "merged_launches_per_call": merged["grouped"], "all_bitwise_equal_to_per_plan": same}), flush=True)
 
 
+def small_configs_program(args):
+    """The smaller lattices of the parity suite timed through the library:
+    3x3 (1+8+1) all 512 amplitudes, 4x5 (1+24+1) 64 random bitstrings for each
+    of seeds 0-7 (eight plans, one grouped call), 5x5 (1+32+1) 256 random
+    bitstrings in one call; median over repeats, graph replay on."""
+    import numpy as np
+    import torch
+    import paper_1905_08394_amd as ps
+    import rqcgen
+    rows = []
+
+    def timeit(fn, reps):
+        fn()
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    c = rqcgen.generate(3, 3, 8, 0)
+    bits = rqcgen.all_bitstrings(9)
+    pl = ps.Plan(ps.Peps(c), prec=args.prec, max_batch=len(bits), graph=True)
+    t = timeit(lambda: pl.amplitudes(bits), 20)
+    rows.append(("3x3 (1+8+1), all 512 amplitudes", len(bits), pl.stats()["cmac_per_amplitude"] * len(bits), t))
+    plans, bl = [], []
+    for seed in range(8):
+        c = rqcgen.generate(4, 5, 24, seed)
+        bl.append(rqcgen.bitstrings(4, 5, seed, 64))
+        plans.append(ps.Plan(ps.Peps(c), prec=args.prec, max_batch=64, graph=True))
+    g = ps.Group(plans)
+    t = timeit(lambda: g.amplitudes(bl), 20)
+    rows.append(("4x5 (1+24+1), seeds 0-7 x 64 random bitstrings (one grouped call)", 512,
+                 sum(p.stats()["cmac_per_amplitude"] * 64 for p in plans), t))
+    c = rqcgen.generate(5, 5, 32, 0)
+    bits = rqcgen.bitstrings(5, 5, 0, 256)
+    pl = ps.Plan(ps.Peps(c), prec=args.prec, max_batch=256, graph=True)
+    t = timeit(lambda: pl.amplitudes(bits), 5)
+    rows.append(("5x5 (1+32+1), 256 random bitstrings in one call", 256, pl.stats()["cmac_per_amplitude"] * 256, t))
+    for name, n, cmac, t in rows:
+        print(json.dumps({"workload": name, "prec": args.prec, "amplitudes": n, "seconds": t,
+                          "amplitudes_per_s": n / t, "cmac": cmac,
+                          "contraction_tflops": 8 * cmac / t / 1e12}), flush=True)
+        log(f"{name}: {t * 1e3:.2f} ms")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -301,7 +349,11 @@ def main():
     ap.add_argument("--fig2", action="store_true", help="8x8 (1+25+1) Porter-Thomas experiment")
     ap.add_argument("--fig2-count", type=int, default=2048)
     ap.add_argument("--mixed", action="store_true", help="mixed batches of 3x3..6x6 circuits, grouped vs per plan")
+    ap.add_argument("--small-configs", action="store_true", help="3x3, 4x5 and 5x5 parity workloads, timed")
     args = ap.parse_args()
+    if args.small_configs:
+        small_configs_program(args)
+        return
     if args.mixed:
         mixed_program(args)
         return
