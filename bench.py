@@ -140,6 +140,40 @@ def cpu_baseline(circuit, bits, target_seconds):
                       f"multiply-add counts to the 16-bitstring batch ({batch_cmac:.3e} CMAC)"}
 
 
+def plain_fp64_gpu_baseline(stats, batch_cmac, nbits, reps=3):
+    """The plain FP64 GPU contraction the target is compared with: the hot
+    step (eq. S4) written the ordinary way, torch.tensordot on complex128
+    (permute A to (m, u, l), then one complex GEMM in the vendor BLAS), at
+    the 6x6 interior-row shape of one v slice (M = 32^4, K = N = 32^2).
+    Timed with CUDA events on torch's stream; the batch total is extrapolated
+    by the exact multiply-add count of the batch the library ran (the hot
+    step carries 98 % of it)."""
+    import torch
+    torch.cuda.empty_cache()
+    D = stats["chi"]
+    L = stats["L"]
+    M = D ** (L - 2)
+    A = torch.randn(D, M, D, dtype=torch.complex128, device="cuda")   # [u][m][l]
+    W = torch.randn(D, D, D * D, dtype=torch.complex128, device="cuda")  # [(u, l)][(d, r)]
+    C = torch.tensordot(A, W, dims=([0, 2], [0, 1]))                    # warm
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        C = torch.tensordot(A, W, dims=([0, 2], [0, 1]))
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    step_cmac = M * D * D * D * D
+    del A, W, C
+    torch.cuda.empty_cache()
+    return {"value": ms / 1e3 * batch_cmac / step_cmac / nbits, "unit": "s/amplitude",
+            "kind": "torch complex128 tensordot (permute + vendor complex GEMM)",
+            "step_ms": ms, "step_tflops": 8 * step_cmac / (ms / 1e3) / 1e12,
+            "sample": f"{reps} interior-site steps of M = {M}, K = N = {D * D} complex128, extrapolated by "
+                      f"exact multiply-add counts to the {nbits}-bitstring batch ({batch_cmac:.3e} CMAC)"}
+
+
 def counters_program(prec="fp32_3m", reps=3):
     """Short program for rocprofv3 --pmc passes: a plain 4 GiB device copy (to
     calibrate FETCH_SIZE / WRITE_SIZE) and the interior-site contraction at the
@@ -457,6 +491,10 @@ def main():
         d = np.abs(amps - amps64)
         out["vs_fp64_gpu"] = {"max_rel": float(np.max(d / np.abs(amps64))),
                                    "median_rel": float(np.median(d / np.abs(amps64)))}
+    if args.compare_fp64 and args.prec != "fp64" and args.lattice == 6:
+        log("plain FP64 GPU baseline (torch complex128) ...")
+        out["plain_fp64_gpu"] = plain_fp64_gpu_baseline(stats, cmac, len(bits))
+        out["vs_plain_fp64_gpu"] = out["plain_fp64_gpu"]["value"] / out["value"]
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(circuit, bits, args.cpu_seconds)
