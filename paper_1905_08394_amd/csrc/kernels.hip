@@ -978,7 +978,18 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
     const long long blocks = (b.T + 7) / 8 * 8;
     if (blocks > 0x7fffffffLL) fail(PSIM_EUNSUPPORTED, "grid too large");
     const bool kmajor = g.K2 == 1 && g.K1 > 1;
-    if (kmajor && g.trans_out)
+    // interior-only row-major launches (every stage inside one k1 block):
+    // 128 x 64 tiles with the division-free loader
+    const bool fastd = !g.trans_out && g.K2 % 8 == 0 && g.M % 128 == 0;
+    if (fastd) {
+      KArgs f = a;
+      f.MT = f.M / 128;
+      f.NT = (f.Nr + 64 - 1) / 64;
+      f.T = f.MT * f.NT * Z;
+      const long long fb = (f.T + 7) / 8 * 8;
+      if (fb > 0x7fffffffLL) fail(PSIM_EUNSUPPORTED, "grid too large");
+      launch<double, 128, 64, 16, ROWFAST, false>(f, fb, st);
+    } else if (kmajor && g.trans_out)
       launch<double, 64, 64, 16, KMAJOR, true>(b, blocks, st);
     else if (kmajor)
       launch<double, 64, 64, 16, KMAJOR, false>(b, blocks, st);
