@@ -543,6 +543,171 @@ __global__ __launch_bounds__(256) void site_gemm_group(GroupArgs ga) {
   site_gemm_body<T, BM, BN, BK, AMODE, TRANS, SCH, false>(p, g - ga.start[i]);
 }
 
+// ---------------------------------------------------------------- 3M, direct-to-LDS
+// The 3M interior-site contraction for launches where every tile is interior
+// and every stage lies inside one k1 block (the ROWFAST conditions), with
+// operands copied global -> LDS by the load unit itself
+// (global_load_lds_dwordx4): no register staging and no LDS store
+// instructions.  Each wave-wide copy writes 64 x 16 bytes contiguously, so the
+// LDS tiles are unpadded rows of BK floats (8 chunks of 16 bytes) and the lane
+// that fills physical chunk p of row r fetches logical chunk p ^ swz(r); the
+// fragment reads apply the same permutation, which spreads 16 consecutive
+// rows over distinct banks.  The two LDS buffers are separate arrays and the
+// K loop is unrolled by two, so each copy and each read names its buffer.
+#define PSIM_LDS(p) ((__attribute__((address_space(3))) void*)(p))
+
+__device__ __forceinline__ int dtl_swz(int r) { return (r ^ (r >> 3)) & 7; }
+
+template <int BM, int BN>
+__global__ __launch_bounds__(256, 3) void site_gemm_3m_dtl(KArgs p) {
+  constexpr int BK = 32;                 // floats per stage row = 8 chunks
+  constexpr int MB = 32;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int MBLK = WM / MB;
+  constexpr int NBLK3 = WN / 2 / MB;
+  constexpr int BROWS = BN / 2;          // packed-W rows (complex columns) per tile
+  constexpr int A_INS = BM * BK / 4 / 64 / 4;     // wave-wide 1 KB copies per wave
+  constexpr int B_INS = BROWS * BK / 4 / 64 / 4;
+  static_assert(A_INS >= 1 && B_INS >= 1 && NBLK3 >= 1, "tile");
+  __shared__ __attribute__((aligned(1024))) float sA0[BM * BK];
+  __shared__ __attribute__((aligned(1024))) float sA1[BM * BK];
+  __shared__ __attribute__((aligned(1024))) float sB0[BROWS * BK];
+  __shared__ __attribute__((aligned(1024))) float sB1[BROWS * BK];
+
+  const long long t = xcd_tile(p.T);
+  if (t >= p.T) return;
+  const long long nt = t % p.NT;
+  const long long rest = t / p.NT;
+  const long long mt = rest % p.MT;
+  const long long z = rest / p.MT;
+  const long long node = z / p.Bz, vb = z % p.Bz;
+  const long long ablk = p.a_index ? (long long)p.a_index[node] : node;
+  const float* __restrict__ A = (const float*)p.A + 2 * (ablk * p.sA_node + vb * p.sA_v);
+  const int tauv = p.tau ? (int)p.tau[node * p.tau_stride] : 0;
+  const float* __restrict__ W = (const float*)(tauv ? p.W1 : p.W0) + p.w_koff_r;
+  float* __restrict__ C = (float*)p.C + 2 * (node * p.sC_node + vb * p.sC_v);
+  const long long m0 = mt * BM;
+  const long long brow0 = nt * BROWS;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  const long long sK1 = p.M * p.K2;
+
+  // Copy `it` of this wave fills tile rows (it * 4 + wid) * 8 + lane / 8,
+  // physical chunk lane % 8; the lane fetches logical chunk p ^ swz(row).
+  // Byte offsets from the uniform stage base stay below 2^31.
+  const unsigned a_rs = (unsigned)(2 * p.K2 * 4);  // bytes between rows of A
+  const unsigned b_rs = (unsigned)(p.ldw * 4);     // bytes between rows of packed W
+  auto src_off = [&](int it, unsigned row_stride) {
+    const int row = (it * 4 + wid) * 8 + (lane >> 3);
+    const int chk = (lane & 7) ^ dtl_swz(row);
+    return (unsigned)row * row_stride + (unsigned)chk * 16u;
+  };
+  long long fk1 = 0, fk2 = 0, kr = 0;  // next stage: (k1, k2) of A, real k of W
+  auto issue = [&](float* sa, float* sb) {
+    const char* abase = (const char*)(A + 2 * (fk1 * sK1 + m0 * p.K2 + fk2));
+    const char* bbase = (const char*)(W + brow0 * p.ldw + kr);
+#pragma unroll
+    for (int it = 0; it < A_INS; ++it)
+      __builtin_amdgcn_global_load_lds((const void*)(abase + src_off(it, a_rs)), PSIM_LDS(sa + (it * 4 + wid) * 256),
+                                       16, 0, 0);
+#pragma unroll
+    for (int it = 0; it < B_INS; ++it)
+      __builtin_amdgcn_global_load_lds((const void*)(bbase + src_off(it, b_rs)), PSIM_LDS(sb + (it * 4 + wid) * 256),
+                                       16, 0, 0);
+    fk2 += BK / 2;
+    if (fk2 == p.K2) {
+      fk2 = 0;
+      ++fk1;
+    }
+    kr += BK;
+  };
+
+  f32x16 acc3[MBLK][NBLK3][3];
+#pragma unroll
+  for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < NBLK3; ++bj)
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc3[bi][bj][q][r] = 0;
+
+  const int frow = lane % MB;
+  const int fh = (lane / MB) * 2;  // first logical chunk of this lane half within a group of 4
+  auto compute = [&](const float* a_s, const float* b_s) {
+#pragma unroll
+    for (int g = 0; g < BK / 16; ++g) {
+      f32x4 ar[MBLK], ai[MBLK], as[MBLK], br[NBLK3], bim[NBLK3], bs[NBLK3];
+#pragma unroll
+      for (int bi = 0; bi < MBLK; ++bi) {
+        const int r = wr * WM + bi * MB + frow;
+        const int c0 = g * 4 + fh, sw = dtl_swz(r);
+        const f32x4 x0 = *(const f32x4*)(a_s + r * BK + ((c0 ^ sw) << 2));
+        const f32x4 x1 = *(const f32x4*)(a_s + r * BK + (((c0 + 1) ^ sw) << 2));
+        ar[bi] = f32x4{x0[0], x0[2], x1[0], x1[2]};
+        ai[bi] = f32x4{x0[1], x0[3], x1[1], x1[3]};
+        as[bi] = ar[bi] + ai[bi];
+      }
+#pragma unroll
+      for (int bj = 0; bj < NBLK3; ++bj) {
+        const int r = wc * (WN / 2) + bj * MB + frow;
+        const int c0 = g * 4 + fh, sw = dtl_swz(r);
+        const f32x4 x0 = *(const f32x4*)(b_s + r * BK + ((c0 ^ sw) << 2));
+        const f32x4 x1 = *(const f32x4*)(b_s + r * BK + (((c0 + 1) ^ sw) << 2));
+        br[bj] = f32x4{x0[0], x0[2], x1[0], x1[2]};
+        bim[bj] = f32x4{x0[1], x0[3], x1[1], x1[3]};
+        bs[bj] = br[bj] + bim[bj];
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < NBLK3; ++bj) {
+            acc3[bi][bj][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[bi][s], br[bj][s], acc3[bi][bj][0], 0, 0, 0);
+            acc3[bi][bj][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[bi][s], bim[bj][s], acc3[bi][bj][1], 0, 0, 0);
+            acc3[bi][bj][2] = __builtin_amdgcn_mfma_f32_32x32x2f32(as[bi][s], bs[bj][s], acc3[bi][bj][2], 0, 0, 0);
+          }
+    }
+  };
+  // vmcnt(0), other counters unconstrained: the copies into LDS have landed
+  constexpr unsigned kWaitVm0 = 0x3f70;
+
+  // the launcher guarantees an even number of stages
+  const int npair = (int)(p.Kr / (2 * BK));
+  issue(sA0, sB0);
+  __builtin_amdgcn_s_waitcnt(kWaitVm0);
+  __syncthreads();
+  for (int kp = 0; kp < npair; ++kp) {
+    issue(sA1, sB1);
+    compute(sA0, sB0);
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    __syncthreads();
+    if (kp + 1 < npair) issue(sA0, sB0);
+    compute(sA1, sB1);
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    __syncthreads();
+  }
+
+  const long long c0 = nt * (BN / 2);  // first complex column of the tile
+#pragma unroll
+  for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < NBLK3; ++bj)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const long long row = m0 + wr * WM + bi * MB + Mfma<float>::out_row(lane, r);
+        const long long col = c0 + wc * (WN / 2) + bj * MB + Mfma<float>::out_col(lane);
+        if (col < p.N) {
+          const float t1 = acc3[bi][bj][0][r], t2 = acc3[bi][bj][1][r], t3 = acc3[bi][bj][2][r];
+          f32x2 v = {t1 - t2, t3 - t1 - t2};
+          *(f32x2*)(C + 2 * (row * p.N + col)) = v;
+        }
+      }
+}
+
 // ---------------------------------------------------------------- BF16x3
 // Split-precision variant of the 4M kernel for row-major A and a plain store:
 // every FP32 operand x is split as x = hi + lo with hi = bf16(x) and
@@ -1059,7 +1224,13 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
                   : launch<float, 128, 256, 32, ROWMAJOR, false, 3>(b, bl, st); break;
         default: fail(PSIM_EINVAL, "unknown kernel config");
       }
-    } else if (g.prec == PSIM_FP32_3M) {
+    } else if (g.prec == PSIM_FP32_3M && !g.trans_out && fast(128, 32) && (2 * g.K1 * g.K2) % 64 == 0 &&
+               g.K2 < (1 << 20) && g.ldw < (1 << 22)) {
+      // interior tiles, an even number of K stages, 32-bit copy offsets:
+      // the direct-to-LDS kernel (same products in the same order as the
+      // ROWFAST 3M kernel, so the same results bit for bit)
+      hipLaunchKernelGGL((site_gemm_3m_dtl<128, 128>), dim3((unsigned)blocks), dim3(256), 0, st, b);
+  } else if (g.prec == PSIM_FP32_3M) {
       if (fast(128, 32))
         g.trans_out ? launch<float, 128, 128, 32, ROWFAST, true, 3>(b, blocks, st)
                     : launch<float, 128, 128, 32, ROWFAST, false, 3>(b, blocks, st);

@@ -5,6 +5,7 @@ Each plan's grouped result must equal its own psim_amplitudes result bit for
 bit (the merged launches run the same kernel body on the same tiles), and the
 oracle within the precision's bar (eps_rms, as in the single-plan tests)."""
 import ctypes
+import json
 import os
 import sys
 
@@ -174,4 +175,28 @@ def test_group_graph_replay(ps):
         for k, (p, b, a) in enumerate(zip(eager, bits, got)):
             assert np.array_equal(a, p.amplitudes(b)), (r, k)
     say(f"group graph replays ok, merged launches {g.stats()['grouped_launches']}")
+    g.close()
+
+
+def test_group_bitwise_with_direct_lds_kernel(ps):
+    """5x5 (1+32+1) interior steps (M = 4096, K = N = 256) run the 3M
+    direct-to-LDS kernel on their own and the grouped row-major 3M kernel in a
+    group: the products are the same and in the same order, so the results
+    must agree bit for bit; both against the state-vector golden values."""
+    with open(os.path.join(HERE, "golden", "rqc_5x5_d32_s0.json")) as f:
+        gold = json.load(f)
+    bits5 = np.array(gold["bits"][:32], dtype=np.uint8)
+    ref5 = (np.array(gold["amps_re"]) + 1j * np.array(gold["amps_im"]))[:32]
+    c5 = rqcgen.generate(5, 5, 32, 0)
+    assert c5.sha256() == gold["sha256"]
+    mix = [(c5, bits5)] + _mix()[:3]
+    plans = [ps.Plan(ps.Peps(c), prec="fp32_3m", max_batch=len(b)) for c, b in mix]
+    single = [p.amplitudes(b) for p, (c, b) in zip(plans, mix)]
+    g = ps.Group(plans)
+    grouped = g.amplitudes([b for c, b in mix])
+    for k, (a, s) in enumerate(zip(grouped, single)):
+        assert np.array_equal(a, s), k
+    e_rms = np.abs(single[0] - ref5) * 2.0 ** 12.5
+    say(f"5x5 d32 3M (direct-to-LDS) max eps_rms {e_rms.max():.2e}")
+    assert e_rms.max() <= AMP_BAR["fp32_3m"]
     g.close()
