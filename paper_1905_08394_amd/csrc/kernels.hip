@@ -559,7 +559,7 @@ __global__ __launch_bounds__(256) void site_gemm_group(GroupArgs ga) {
 __device__ __forceinline__ int dtl_swz(int r) { return (r ^ (r >> 3)) & 7; }
 
 template <int BM, int BN>
-__global__ __launch_bounds__(256, 3) void site_gemm_3m_dtl(KArgs p) {
+__device__ __forceinline__ void dtl3m_body(const KArgs& p, const long long t) {
   constexpr int BK = 32;                 // floats per stage row = 8 chunks
   constexpr int MB = 32;
   constexpr int WM = BM / 2, WN = BN / 2;
@@ -574,8 +574,6 @@ __global__ __launch_bounds__(256, 3) void site_gemm_3m_dtl(KArgs p) {
   __shared__ __attribute__((aligned(1024))) float sB0[BROWS * BK];
   __shared__ __attribute__((aligned(1024))) float sB1[BROWS * BK];
 
-  const long long t = xcd_tile(p.T);
-  if (t >= p.T) return;
   const long long nt = t % p.NT;
   const long long rest = t / p.NT;
   const long long mt = rest % p.MT;
@@ -706,6 +704,28 @@ __global__ __launch_bounds__(256, 3) void site_gemm_3m_dtl(KArgs p) {
           *(f32x2*)(C + 2 * (row * p.N + col)) = v;
         }
       }
+}
+
+template <int BM, int BN>
+__global__ __launch_bounds__(256, 3) void site_gemm_3m_dtl(KArgs p) {
+  const long long t = xcd_tile(p.T);
+  if (t >= p.T) return;
+  dtl3m_body<BM, BN>(p, t);
+}
+
+// grouped form (see site_gemm_group)
+template <int BM, int BN>
+__global__ __launch_bounds__(256, 3) void site_gemm_3m_dtl_group(GroupArgs ga) {
+  const long long total = ga.start[ga.nprob];
+  const long long g = xcd_tile(total);
+  if (g >= total) return;
+  const int i = find_problem(ga, g);
+  KArgs p;
+  const int* src = (const int*)ga.probs[i];
+  int* dst = (int*)&p;
+#pragma unroll
+  for (int w = 0; w < (int)(sizeof(KArgs) / 4); ++w) dst[w] = __builtin_amdgcn_readfirstlane(src[w]);
+  dtl3m_body<BM, BN>(p, g - ga.start[i]);
 }
 
 // ---------------------------------------------------------------- BF16x3
@@ -1055,10 +1075,18 @@ static int fp32_mode(const GemmLaunch& g) {
          : (g.K2 == 1 && g.M % 2 == 0 && g.K1 > 1 && even_base) ? KMAJOR : GENERIC;
 }
 
+// The direct-to-LDS 3M kernel applies: interior tiles only, every K stage
+// inside one k1 block, an even number of stages, 32-bit copy offsets.
+static bool dtl3m_ok(const GemmLaunch& g, int mode) {
+  return g.prec == PSIM_FP32_3M && !g.trans_out && !g.split && mode == ROWMAJOR && g.M % 128 == 0 &&
+         (2 * g.K2) % 32 == 0 && (2 * g.K1 * g.K2) % 64 == 0 && g.K2 < (1 << 20) && g.ldw < (1 << 22);
+}
+
 // Grouped-launch variants (FP32 only), the kernels launch_site_gemm picks for
 // default tiles: id = 8 * (3M ? 1 : 0) + 2 * mode + trans with 128 x 128 x 32
 // tiles (mode: ROWMAJOR, KMAJOR, GENERIC, ROWFAST); 16 / 17 = 4M transposed
-// small-N tiles (256 x 64 x 16, ROWMAJOR / KMAJOR).  -1: not groupable.
+// small-N tiles (256 x 64 x 16, ROWMAJOR / KMAJOR); 18 = 3M direct-to-LDS.
+// -1: not groupable.
 int group_variant(const GemmLaunch& g, void* out, long long* tiles) {
   if ((g.prec != PSIM_FP32_4M && g.prec != PSIM_FP32_3M) || g.split || g.cfg > 0) return -1;
   int mode = fp32_mode(g);
@@ -1069,6 +1097,10 @@ int group_variant(const GemmLaunch& g, void* out, long long* tiles) {
     id = mode == ROWMAJOR ? 16 : 17;
     bm = 256;
     bn = 64;
+  } else if (dtl3m_ok(g, mode)) {
+    id = 18;
+    bm = 128;
+    bn = 128;
   } else {
     if (mode == ROWMAJOR && g.M % 128 == 0 && (2 * g.K1 * g.K2) % 32 == 0 && (2 * g.K2) % 32 == 0) mode = ROWFAST;
     id = 8 * (g.prec == PSIM_FP32_3M ? 1 : 0) + 2 * mode + (g.trans_out ? 1 : 0);
@@ -1102,7 +1134,7 @@ static void glaunch_mode(int mode, bool trans, const GroupArgs& ga, long long bl
 void launch_group(int variant, const void* const* d_probs, const long long* start, int nprob, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   if (nprob < 1 || nprob > kMaxGroup) fail(PSIM_EINTERNAL, "group size out of range");
-  if (variant < 0 || variant > 17) fail(PSIM_EINTERNAL, "unknown group variant");
+  if (variant < 0 || variant > 18) fail(PSIM_EINTERNAL, "unknown group variant");
   GroupArgs ga{};
   for (int i = 0; i < nprob; ++i) {
     ga.probs[i] = (const KArgs*)d_probs[i];
@@ -1114,7 +1146,9 @@ void launch_group(int variant, const void* const* d_probs, const long long* star
   if (total < 1) return;
   const long long blocks = (total + 7) / 8 * 8;
   if (blocks > 0x7fffffffLL) fail(PSIM_EUNSUPPORTED, "grid too large");
-  if (variant == 16)
+  if (variant == 18)
+    hipLaunchKernelGGL((site_gemm_3m_dtl_group<128, 128>), dim3((unsigned)blocks), dim3(256), 0, st, ga);
+  else if (variant == 16)
     hipLaunchKernelGGL((site_gemm_group<float, 256, 64, 16, ROWMAJOR, true, 4>), dim3((unsigned)blocks), dim3(256), 0,
                        st, ga);
   else if (variant == 17)
@@ -1224,8 +1258,7 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
                   : launch<float, 128, 256, 32, ROWMAJOR, false, 3>(b, bl, st); break;
         default: fail(PSIM_EINVAL, "unknown kernel config");
       }
-    } else if (g.prec == PSIM_FP32_3M && !g.trans_out && fast(128, 32) && (2 * g.K1 * g.K2) % 64 == 0 &&
-               g.K2 < (1 << 20) && g.ldw < (1 << 22)) {
+    } else if (dtl3m_ok(g, mode)) {
       // interior tiles, an even number of K stages, 32-bit copy offsets:
       // the direct-to-LDS kernel (same products in the same order as the
       // ROWFAST 3M kernel, so the same results bit for bit)

@@ -180,9 +180,9 @@ def test_group_graph_replay(ps):
 
 def test_group_bitwise_with_direct_lds_kernel(ps):
     """5x5 (1+32+1) interior steps (M = 4096, K = N = 256) run the 3M
-    direct-to-LDS kernel on their own and the grouped row-major 3M kernel in a
-    group: the products are the same and in the same order, so the results
-    must agree bit for bit; both against the state-vector golden values."""
+    direct-to-LDS kernel, on their own and merged with other circuits' steps
+    in a grouped launch: the results must agree bit for bit, and with the
+    state-vector golden values."""
     with open(os.path.join(HERE, "golden", "rqc_5x5_d32_s0.json")) as f:
         gold = json.load(f)
     bits5 = np.array(gold["bits"][:32], dtype=np.uint8)
