@@ -36,9 +36,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
-    with open(os.path.join(ROOT, "paper_1905_08394_amd", "csrc", "kernels.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+# Section of kernels.hip that holds each precision's hot kernel (between two
+# "// ----...---- <name>" marker lines); traffic counters are tied to its hash.
+KERNEL_SECTIONS = {"fp32_3m": ("3M, direct-to-LDS", "BF16x3"), "fp32": ("kernel", "3M, direct-to-LDS")}
+
+
+def kernel_source_hash(prec):
+    with open(os.path.join(ROOT, "paper_1905_08394_amd", "csrc", "kernels.hip")) as f:
+        lines = f.read().split("\n")
+    first, last = KERNEL_SECTIONS[prec]
+    marker = "// " + "-" * 64 + " "
+    a = lines.index(marker + first)
+    b = lines.index(marker + last)
+    return hashlib.sha256("\n".join(lines[a:b]).encode()).hexdigest()
 
 
 def workload(lattice, depth, seed=0):
@@ -425,7 +435,8 @@ def main():
         with open(tfile) as f:
             tr = json.load(f)
     per_launch_cmac = hot["cmac"] / max(hot["launches"], 1)
-    if tr is not None and tr.get("kernel_source_sha256") == kernel_source_hash() and "issued_flops_per_launch" in tr:
+    if tr is not None and args.prec in KERNEL_SECTIONS and tr.get("kernel_source_sha256") == kernel_source_hash(args.prec) \
+            and "issued_flops_per_launch" in tr:
         # counters were taken on the largest interior launch; scale to this
         # run's average launch by issued flops (same K and N, M differs)
         traffic = tr["bytes_per_launch"] * issued * per_launch_cmac / tr["issued_flops_per_launch"]
