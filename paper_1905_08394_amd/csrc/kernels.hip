@@ -728,6 +728,130 @@ __global__ __launch_bounds__(256, 3) void site_gemm_3m_dtl_group(GroupArgs ga) {
   dtl3m_body<BM, BN>(p, g - ga.start[i]);
 }
 
+// FP64 form of the direct-to-LDS interior kernel: 4M real expansion on
+// v_mfma_f64_16x16x4f64, stage rows of 16 doubles (the same 128-byte rows,
+// chunks and swizzle as above), 128 x 64 real outputs per workgroup.  The
+// products and their order are those of the row-major FP64 kernel.
+template <int BM, int BN>
+__global__ __launch_bounds__(256, 3) void site_gemm_f64_dtl(KArgs p) {
+  typedef Mfma<double> MF;
+  constexpr int BK = 16;                 // doubles per stage row = 8 chunks
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int MBLK = WM / MF::MB, NBLK = WN / MF::MB;
+  constexpr int A_INS = BM * 128 / 1024 / 4;
+  constexpr int B_INS = BN * 128 / 1024 / 4;
+  static_assert(A_INS >= 1 && B_INS >= 1 && MBLK >= 1 && NBLK >= 1, "tile");
+  __shared__ __attribute__((aligned(1024))) double sA0[BM * BK];
+  __shared__ __attribute__((aligned(1024))) double sA1[BM * BK];
+  __shared__ __attribute__((aligned(1024))) double sB0[BN * BK];
+  __shared__ __attribute__((aligned(1024))) double sB1[BN * BK];
+
+  const long long t = xcd_tile(p.T);
+  if (t >= p.T) return;
+  const long long nt = t % p.NT;
+  const long long rest = t / p.NT;
+  const long long mt = rest % p.MT;
+  const long long z = rest / p.MT;
+  const long long node = z / p.Bz, vb = z % p.Bz;
+  const long long ablk = p.a_index ? (long long)p.a_index[node] : node;
+  const double* __restrict__ A = (const double*)p.A + 2 * (ablk * p.sA_node + vb * p.sA_v);
+  const int tauv = p.tau ? (int)p.tau[node * p.tau_stride] : 0;
+  const double* __restrict__ W = (const double*)(tauv ? p.W1 : p.W0) + p.w_koff_r;
+  double* __restrict__ C = (double*)p.C + 2 * (node * p.sC_node + vb * p.sC_v);
+  const long long m0 = mt * BM, n0 = nt * BN;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  const long long sK1 = p.M * p.K2;
+  const unsigned a_rs = (unsigned)(2 * p.K2 * 8);
+  const unsigned b_rs = (unsigned)(p.ldw * 8);
+  auto src_off = [&](int it, unsigned row_stride) {
+    const int row = (it * 4 + wid) * 8 + (lane >> 3);
+    const int chk = (lane & 7) ^ dtl_swz(row);
+    return (unsigned)row * row_stride + (unsigned)chk * 16u;
+  };
+  long long fk1 = 0, fk2 = 0, kr = 0;
+  auto issue = [&](double* sa, double* sb) {
+    const char* abase = (const char*)(A + 2 * (fk1 * sK1 + m0 * p.K2 + fk2));
+    const char* bbase = (const char*)(W + n0 * p.ldw + kr);
+#pragma unroll
+    for (int it = 0; it < A_INS; ++it)
+      __builtin_amdgcn_global_load_lds((const void*)(abase + src_off(it, a_rs)), PSIM_LDS(sa + (it * 4 + wid) * 128),
+                                       16, 0, 0);
+#pragma unroll
+    for (int it = 0; it < B_INS; ++it)
+      __builtin_amdgcn_global_load_lds((const void*)(bbase + src_off(it, b_rs)), PSIM_LDS(sb + (it * 4 + wid) * 128),
+                                       16, 0, 0);
+    fk2 += BK / 2;
+    if (fk2 == p.K2) {
+      fk2 = 0;
+      ++fk1;
+    }
+    kr += BK;
+  };
+
+  typename MF::acc_t acc[MBLK][NBLK];
+#pragma unroll
+  for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < NBLK; ++bj)
+#pragma unroll
+      for (int r = 0; r < MF::NACC; ++r) acc[bi][bj][r] = 0;
+
+  const int frow = lane % MF::MB;
+  const int fq = lane / MF::MB;  // which pair of k inside a group of 8
+  auto compute = [&](const double* a_s, const double* b_s) {
+#pragma unroll
+    for (int g = 0; g < BK / 8; ++g) {
+      typename MF::frag_t af[MBLK], bf[NBLK];
+#pragma unroll
+      for (int bi = 0; bi < MBLK; ++bi) {
+        const int r = wr * WM + bi * MF::MB + frow;
+        af[bi] = *(const typename MF::frag_t*)(a_s + r * BK + (((g * 4 + fq) ^ dtl_swz(r)) << 1));
+      }
+#pragma unroll
+      for (int bj = 0; bj < NBLK; ++bj) {
+        const int r = wc * WN + bj * MF::MB + frow;
+        bf[bj] = *(const typename MF::frag_t*)(b_s + r * BK + (((g * 4 + fq) ^ dtl_swz(r)) << 1));
+      }
+#pragma unroll
+      for (int s = 0; s < MF::KV; ++s)
+#pragma unroll
+        for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < NBLK; ++bj) MF::mma(af[bi], bf[bj], acc[bi][bj], s);
+    }
+  };
+  constexpr unsigned kWaitVm0 = 0x3f70;
+
+  const int npair = (int)(p.Kr / (2 * BK));
+  issue(sA0, sB0);
+  __builtin_amdgcn_s_waitcnt(kWaitVm0);
+  __syncthreads();
+  for (int kp = 0; kp < npair; ++kp) {
+    issue(sA1, sB1);
+    compute(sA0, sB0);
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    __syncthreads();
+    if (kp + 1 < npair) issue(sA0, sB0);
+    compute(sA1, sB1);
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < NBLK; ++bj)
+#pragma unroll
+      for (int r = 0; r < MF::NACC; ++r) {
+        const long long row = m0 + wr * WM + bi * MF::MB + MF::out_row(lane, r);
+        const long long col = n0 + wc * WN + bj * MF::MB + MF::out_col(lane);
+        if (col < p.Nr) C[row * p.Nr + col] = acc[bi][bj][r];
+      }
+}
+
 // ---------------------------------------------------------------- BF16x3
 // Split-precision variant of the 4M kernel for row-major A and a plain store:
 // every FP32 operand x is split as x = hi + lo with hi = bf16(x) and
@@ -1180,7 +1304,16 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
     // interior-only row-major launches (every stage inside one k1 block):
     // 128 x 64 tiles with the division-free loader
     const bool fastd = !g.trans_out && g.K2 % 8 == 0 && g.M % 128 == 0;
-    if (fastd) {
+    if (fastd && (g.K1 * g.K2) % 16 == 0 && g.K2 < (1 << 20) && g.ldw < (1 << 22)) {
+      // an even number of 16-double stages, 32-bit copy offsets: direct-to-LDS
+      KArgs f = a;
+      f.MT = f.M / 128;
+      f.NT = (f.Nr + 64 - 1) / 64;
+      f.T = f.MT * f.NT * Z;
+      const long long fb = (f.T + 7) / 8 * 8;
+      if (fb > 0x7fffffffLL) fail(PSIM_EUNSUPPORTED, "grid too large");
+      hipLaunchKernelGGL((site_gemm_f64_dtl<128, 64>), dim3((unsigned)fb), dim3(256), 0, st, f);
+    } else if (fastd) {
       KArgs f = a;
       f.MT = f.M / 128;
       f.NT = (f.Nr + 64 - 1) / 64;
