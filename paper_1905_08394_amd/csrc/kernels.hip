@@ -728,23 +728,27 @@ __global__ __launch_bounds__(256, 3) void site_gemm_3m_dtl_group(GroupArgs ga) {
   dtl3m_body<BM, BN>(p, g - ga.start[i]);
 }
 
-// FP64 form of the direct-to-LDS interior kernel: 4M real expansion on
-// v_mfma_f64_16x16x4f64, stage rows of 16 doubles (the same 128-byte rows,
-// chunks and swizzle as above), 128 x 64 real outputs per workgroup.  The
-// products and their order are those of the row-major FP64 kernel.
-template <int BM, int BN>
-__global__ __launch_bounds__(256, 3) void site_gemm_f64_dtl(KArgs p) {
-  typedef Mfma<double> MF;
-  constexpr int BK = 16;                 // doubles per stage row = 8 chunks
+// 4M form of the direct-to-LDS interior kernel (FP32 on v_mfma_f32_32x32x2f32,
+// FP64 on v_mfma_f64_16x16x4f64): the real expansion of the complex product,
+// stage rows of 128 bytes (32 floats or 16 doubles: the same chunks and
+// swizzle as above), BM x BN real outputs per workgroup.  A lane's fragment
+// (KV consecutive k) is one 16-byte chunk.  The products and their order are
+// those of the row-major kernel with the same tile.
+template <typename T, int BM, int BN, int OCC>
+__global__ __launch_bounds__(256, OCC) void site_gemm_4m_dtl(KArgs p) {
+  typedef Mfma<T> MF;
+  constexpr int BK = 128 / (int)sizeof(T);  // elements per stage row = 8 chunks
+  constexpr int KV = MF::KV;                 // elements per chunk
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int MBLK = WM / MF::MB, NBLK = WN / MF::MB;
   constexpr int A_INS = BM * 128 / 1024 / 4;
   constexpr int B_INS = BN * 128 / 1024 / 4;
   static_assert(A_INS >= 1 && B_INS >= 1 && MBLK >= 1 && NBLK >= 1, "tile");
-  __shared__ __attribute__((aligned(1024))) double sA0[BM * BK];
-  __shared__ __attribute__((aligned(1024))) double sA1[BM * BK];
-  __shared__ __attribute__((aligned(1024))) double sB0[BN * BK];
-  __shared__ __attribute__((aligned(1024))) double sB1[BN * BK];
+  static_assert(KV * (int)sizeof(T) == 16, "one chunk per fragment");
+  __shared__ __attribute__((aligned(1024))) T sA0[BM * BK];
+  __shared__ __attribute__((aligned(1024))) T sA1[BM * BK];
+  __shared__ __attribute__((aligned(1024))) T sB0[BN * BK];
+  __shared__ __attribute__((aligned(1024))) T sB1[BN * BK];
 
   const long long t = xcd_tile(p.T);
   if (t >= p.T) return;
@@ -754,34 +758,34 @@ __global__ __launch_bounds__(256, 3) void site_gemm_f64_dtl(KArgs p) {
   const long long z = rest / p.MT;
   const long long node = z / p.Bz, vb = z % p.Bz;
   const long long ablk = p.a_index ? (long long)p.a_index[node] : node;
-  const double* __restrict__ A = (const double*)p.A + 2 * (ablk * p.sA_node + vb * p.sA_v);
+  const T* __restrict__ A = (const T*)p.A + 2 * (ablk * p.sA_node + vb * p.sA_v);
   const int tauv = p.tau ? (int)p.tau[node * p.tau_stride] : 0;
-  const double* __restrict__ W = (const double*)(tauv ? p.W1 : p.W0) + p.w_koff_r;
-  double* __restrict__ C = (double*)p.C + 2 * (node * p.sC_node + vb * p.sC_v);
+  const T* __restrict__ W = (const T*)(tauv ? p.W1 : p.W0) + p.w_koff_r;
+  T* __restrict__ C = (T*)p.C + 2 * (node * p.sC_node + vb * p.sC_v);
   const long long m0 = mt * BM, n0 = nt * BN;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
   const int wr = wid >> 1, wc = wid & 1;
   const long long sK1 = p.M * p.K2;
-  const unsigned a_rs = (unsigned)(2 * p.K2 * 8);
-  const unsigned b_rs = (unsigned)(p.ldw * 8);
+  const unsigned a_rs = (unsigned)(2 * p.K2 * (long long)sizeof(T));
+  const unsigned b_rs = (unsigned)(p.ldw * (long long)sizeof(T));
   auto src_off = [&](int it, unsigned row_stride) {
     const int row = (it * 4 + wid) * 8 + (lane >> 3);
     const int chk = (lane & 7) ^ dtl_swz(row);
     return (unsigned)row * row_stride + (unsigned)chk * 16u;
   };
   long long fk1 = 0, fk2 = 0, kr = 0;
-  auto issue = [&](double* sa, double* sb) {
+  auto issue = [&](T* sa, T* sb) {
     const char* abase = (const char*)(A + 2 * (fk1 * sK1 + m0 * p.K2 + fk2));
     const char* bbase = (const char*)(W + n0 * p.ldw + kr);
 #pragma unroll
     for (int it = 0; it < A_INS; ++it)
-      __builtin_amdgcn_global_load_lds((const void*)(abase + src_off(it, a_rs)), PSIM_LDS(sa + (it * 4 + wid) * 128),
+      __builtin_amdgcn_global_load_lds((const void*)(abase + src_off(it, a_rs)), PSIM_LDS(sa + (it * 4 + wid) * (1024 / (int)sizeof(T))),
                                        16, 0, 0);
 #pragma unroll
     for (int it = 0; it < B_INS; ++it)
-      __builtin_amdgcn_global_load_lds((const void*)(bbase + src_off(it, b_rs)), PSIM_LDS(sb + (it * 4 + wid) * 128),
+      __builtin_amdgcn_global_load_lds((const void*)(bbase + src_off(it, b_rs)), PSIM_LDS(sb + (it * 4 + wid) * (1024 / (int)sizeof(T))),
                                        16, 0, 0);
     fk2 += BK / 2;
     if (fk2 == p.K2) {
@@ -800,20 +804,20 @@ __global__ __launch_bounds__(256, 3) void site_gemm_f64_dtl(KArgs p) {
       for (int r = 0; r < MF::NACC; ++r) acc[bi][bj][r] = 0;
 
   const int frow = lane % MF::MB;
-  const int fq = lane / MF::MB;  // which pair of k inside a group of 8
-  auto compute = [&](const double* a_s, const double* b_s) {
+  const int fq = lane / MF::MB;  // which chunk of a group of 8 k this lane reads
+  auto compute = [&](const T* a_s, const T* b_s) {
 #pragma unroll
     for (int g = 0; g < BK / 8; ++g) {
       typename MF::frag_t af[MBLK], bf[NBLK];
 #pragma unroll
       for (int bi = 0; bi < MBLK; ++bi) {
         const int r = wr * WM + bi * MF::MB + frow;
-        af[bi] = *(const typename MF::frag_t*)(a_s + r * BK + (((g * 4 + fq) ^ dtl_swz(r)) << 1));
+        af[bi] = *(const typename MF::frag_t*)(a_s + r * BK + (((g * (8 / KV) + fq) ^ dtl_swz(r)) * KV));
       }
 #pragma unroll
       for (int bj = 0; bj < NBLK; ++bj) {
         const int r = wc * WN + bj * MF::MB + frow;
-        bf[bj] = *(const typename MF::frag_t*)(b_s + r * BK + (((g * 4 + fq) ^ dtl_swz(r)) << 1));
+        bf[bj] = *(const typename MF::frag_t*)(b_s + r * BK + (((g * (8 / KV) + fq) ^ dtl_swz(r)) * KV));
       }
 #pragma unroll
       for (int s = 0; s < MF::KV; ++s)
@@ -1312,7 +1316,7 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
       f.T = f.MT * f.NT * Z;
       const long long fb = (f.T + 7) / 8 * 8;
       if (fb > 0x7fffffffLL) fail(PSIM_EUNSUPPORTED, "grid too large");
-      hipLaunchKernelGGL((site_gemm_f64_dtl<128, 64>), dim3((unsigned)fb), dim3(256), 0, st, f);
+      hipLaunchKernelGGL((site_gemm_4m_dtl<double, 128, 64, 3>), dim3((unsigned)fb), dim3(256), 0, st, f);
     } else if (fastd) {
       KArgs f = a;
       f.MT = f.M / 128;
@@ -1442,6 +1446,10 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
         launch<float, 256, 64, 16, ROWMAJOR, true>(b, bl, st);
       else
         launch<float, 256, 64, 16, KMAJOR, true>(b, bl, st);
+    } else if (!g.trans_out && fast(128, 32) && (2 * g.K1 * g.K2) % 64 == 0 && g.K2 < (1 << 20) &&
+               g.ldw < (1 << 22)) {
+      // interior tiles, an even number of K stages: direct-to-LDS 4M kernel
+      hipLaunchKernelGGL((site_gemm_4m_dtl<float, 128, 128, 2>), dim3((unsigned)blocks), dim3(256), 0, st, b);
     } else if (fast(128, 32))
       g.trans_out ? launch<float, 128, 128, 32, ROWFAST, true>(b, blocks, st)
                   : launch<float, 128, 128, 32, ROWFAST, false>(b, blocks, st);
