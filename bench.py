@@ -38,7 +38,7 @@ def log(*a):
 
 # Section of kernels.hip that holds each precision's hot kernel (between two
 # "// ----...---- <name>" marker lines); traffic counters are tied to its hash.
-KERNEL_SECTIONS = {"fp32_3m": ("3M, direct-to-LDS", "BF16x3"), "fp32": ("kernel", "3M, direct-to-LDS")}
+KERNEL_SECTIONS = {"fp32_3m": ("3M, direct-to-LDS", "4M, direct-to-LDS"), "fp32": ("4M, direct-to-LDS", "BF16x3")}
 
 
 def kernel_source_hash(prec):

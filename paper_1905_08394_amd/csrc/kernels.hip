@@ -728,6 +728,7 @@ __global__ __launch_bounds__(256, 3) void site_gemm_3m_dtl_group(GroupArgs ga) {
   dtl3m_body<BM, BN>(p, g - ga.start[i]);
 }
 
+// ---------------------------------------------------------------- 4M, direct-to-LDS
 // 4M form of the direct-to-LDS interior kernel (FP32 on v_mfma_f32_32x32x2f32,
 // FP64 on v_mfma_f64_16x16x4f64): the real expansion of the complex product,
 // stage rows of 128 bytes (32 floats or 16 doubles: the same chunks and

@@ -137,3 +137,11 @@ def test_group_rejects_host_only_and_empty(ps):
     assert L.psim_group(None, 0, ctypes.byref(h)) == ps.PSIM_EINVAL
     arr = (ctypes.c_void_p * 1)(None)
     assert L.psim_group(arr, 1, ctypes.byref(h)) == ps.PSIM_EINVAL
+
+
+def test_bench_kernel_sections_exist():
+    """bench.py ties traffic counters to the hash of the hot kernel's source
+    section; the section markers must stay in kernels.hip."""
+    import bench
+    hs = {p: bench.kernel_source_hash(p) for p in bench.KERNEL_SECTIONS}
+    assert len(set(hs.values())) == len(hs) and all(len(h) == 64 for h in hs.values())
