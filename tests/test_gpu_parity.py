@@ -87,6 +87,7 @@ def _oracle_step(A, W, M, K1, K2, N):
     (99, 3, 3, 5, 1, True),        # generic loader, transposed store
     (1000, 2, 32, 32, 1, True),    # last site of a 6x6 row: v chunk 2, N = 32
     (256, 4, 16, 48, 2, False),    # interior tiles only: the bounds-check-free loader
+    (384, 2, 32, 100, 3, False),   # direct-to-LDS kernels: 3 row tiles, 3 batch entries, ragged N
 ])
 def test_site_contraction_parity(ps, prec, M, K1, K2, N, batch, trans):
     import torch
@@ -311,3 +312,7 @@ def test_tile_candidates(ps, prec, cfg):
     a = pl.amplitudes(bits)
     _, erms = _errors(a, ref, 25)
     assert np.max(erms) <= AMP_BAR[prec]
+    # every tile runs the same products in the same k order for each output
+    # element, so all candidates agree with the default bit for bit
+    a0 = ps.Plan(P, prec=prec, max_batch=256, mem_budget=48 << 30).amplitudes(bits)
+    assert np.array_equal(a, a0)
