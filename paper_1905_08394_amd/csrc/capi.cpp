@@ -98,7 +98,7 @@ psim_status psim_plan_info(const psim_plan_t* pl, psim_plan_stats* s) {
     o.weights_bytes = pl->weights_bytes;
     o.peak_tensor_elems = (uint64_t)pl->peak_elems;
     o.cmac_per_amplitude = pl->cmac;
-    o.n_gemm_steps = (int64_t)pl->steps.size();
+    o.n_gemm_steps = pl->sq ? pl->sq_steps : (int64_t)pl->steps.size();
     o.L = pl->L;
     o.R = pl->R;
     o.chi = pl->chi;

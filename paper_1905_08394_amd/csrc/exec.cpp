@@ -116,7 +116,8 @@ void tune_plan(psim_plan_t* pl, void* ws, size_t ws_bytes, void* stream, int rep
   if (!ws || ws_bytes < pl->ws_total) fail(PSIM_EINVAL, "workspace is NULL or smaller than the plan needs");
   if (reps < 1) fail(PSIM_EINVAL, "reps must be at least 1");
   if (best_ms) *best_ms = 0;
-  if ((pl->opts.prec != PSIM_FP32_4M && pl->opts.prec != PSIM_FP32_3M) || (pl->opts.flags & PSIM_PLAN_SPLIT_ACC))
+  if ((pl->opts.prec != PSIM_FP32_4M && pl->opts.prec != PSIM_FP32_3M) || (pl->opts.flags & PSIM_PLAN_SPLIT_ACC) ||
+      pl->sq)
     return;
   const int ncfg = pl->opts.prec == PSIM_FP32_3M ? fp32_3m_config_count() : fp32_config_count();
   hip_check(hipSetDevice(pl->opts.device), "hipSetDevice");
@@ -535,6 +536,10 @@ void run_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, si
                     double* out) {
   check_batch(pl, bits, n, ws, ws_bytes, out);
   if (n == 0) return;
+  if (pl->sq) {
+    run_square(pl, bits, n, ws, stream, out);
+    return;
+  }
   hip_check(hipSetDevice(pl->opts.device), "hipSetDevice");
   for (const auto& idx : split_batches(pl, bits, n)) run_one(pl, bits, idx, ws, (hipStream_t)stream, out);
 }
@@ -561,6 +566,7 @@ psim_group_s* make_group(psim_plan_t* const* plans, int np) {
       if (!pl) fail(PSIM_EINVAL, "plan " + std::to_string(p) + " is NULL");
       if (pl->host_only) fail(PSIM_EINVAL, "plan " + std::to_string(p) + " was made with PSIM_PLAN_HOST_ONLY");
       if (pl->opts.device != plans[0]->opts.device) fail(PSIM_EINVAL, "plans are on different devices");
+      if (pl->sq) fail(PSIM_EUNSUPPORTED, "plan " + std::to_string(p) + " uses the square partition (not groupable)");
       G->plans.push_back(pl);
       G->desc_off.push_back(off);
       off += al((uint64_t)pl->max_ops * kb);

@@ -1127,6 +1127,83 @@ __global__ void copy_segments(const CopySeg* __restrict__ segs) {
     b[x] = a[x];
 }
 
+// ---------------------------------------------------------------- square partition helpers
+// Three-index permutes of a complex tensor in[X][Y][Z] (E = float2 or
+// double2, one complex element): mode 0 writes out[Y][X][Z], mode 1
+// out[X][Z][Y].  One thread per output element.
+template <typename E>
+__global__ void permute3(const E* __restrict__ in, E* __restrict__ out, long long X, long long Y, long long Z,
+                         int mode) {
+  const long long total = X * Y * Z;
+  for (long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x; o < total;
+       o += (long long)gridDim.x * blockDim.x) {
+    long long x, y, z;
+    if (mode == 0) {  // o = (y X + x) Z + z
+      z = o % Z;
+      const long long q = o / Z;
+      x = q % X;
+      y = q / X;
+    } else {          // o = (x Z + z) Y + y
+      y = o % Y;
+      const long long q = o / Y;
+      z = q % Z;
+      x = q / Z;
+    }
+    out[o] = in[(x * Y + y) * Z + z];
+  }
+}
+
+// A device complex matrix Q[n][k] (row-major, N x K) as the packed W operand
+// of the site kernels for W[k][n] = Q[n][k], zero padded to rows x ld:
+// 3M: P[n][2k + c] = component c of Q[n][k]; 4M (float or double): the real
+// expansion P[2n + a][2k + b] = [[Re, -Im], [Im, Re]][a][b] of Q[n][k].
+template <typename T>
+__global__ void pack_w(const T* __restrict__ Q, T* __restrict__ P, long long N, long long K, long long rows,
+                       long long ld, int three_m) {
+  const long long total = rows * ld;
+  for (long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x; o < total;
+       o += (long long)gridDim.x * blockDim.x) {
+    const long long row = o / ld, c = o - row * ld;
+    T v = 0;
+    if (three_m) {
+      if (row < N && c < 2 * K) v = Q[2 * (row * K + (c >> 1)) + (c & 1)];
+    } else if (row < 2 * N && c < 2 * K) {
+      const long long n = row >> 1, k = c >> 1;
+      const int a = (int)(row & 1), b = (int)(c & 1);
+      const T re = Q[2 * (n * K + k)], im = Q[2 * (n * K + k) + 1];
+      v = (a == b) ? re : (a ? im : -im);
+    }
+    P[o] = v;
+  }
+}
+
+// Partial sums of sum_i a[i] b[i] (complex, no conjugation) in FP64: one
+// (re, im) pair per workgroup in part[2 * blockIdx.x].
+template <typename T>
+__global__ __launch_bounds__(256) void cdot_partial(const T* __restrict__ a, const T* __restrict__ b, long long n,
+                                                    double* __restrict__ part) {
+  double re = 0, im = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const double ar = a[2 * i], ai = a[2 * i + 1], br = b[2 * i], bi = b[2 * i + 1];
+    re += ar * br - ai * bi;
+    im += ar * bi + ai * br;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    re += __shfl_xor(re, off);
+    im += __shfl_xor(im, off);
+  }
+  __shared__ double red[2][4];
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = re;
+    red[1][threadIdx.x >> 6] = im;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    part[2 * blockIdx.x + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
+}
+
 __global__ void zero_u32(uint32_t* p, long long n) {
   const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (x < n) p[x] = 0;
@@ -1465,6 +1542,48 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
                   : launch<float, 128, 128, 32, GENERIC, false>(b, blocks, st);
   }
   hip_check(hipGetLastError(), "site_gemm launch");
+}
+
+static unsigned grid_for(long long total) {
+  return (unsigned)std::max<long long>(1, std::min<long long>((total + 255) / 256, 1 << 20));
+}
+
+void launch_permute3(int prec, const void* in, void* out, int64_t X, int64_t Y, int64_t Z, int mode, void* stream) {
+  if (X < 1 || Y < 1 || Z < 1 || (mode != 0 && mode != 1)) fail(PSIM_EINTERNAL, "permute3: bad arguments");
+  hipStream_t st = (hipStream_t)stream;
+  const long long total = X * Y * Z;
+  if (prec == PSIM_FP64)
+    hipLaunchKernelGGL(permute3<double2>, dim3(grid_for(total)), dim3(256), 0, st, (const double2*)in, (double2*)out,
+                       (long long)X, (long long)Y, (long long)Z, mode);
+  else
+    hipLaunchKernelGGL(permute3<float2>, dim3(grid_for(total)), dim3(256), 0, st, (const float2*)in, (float2*)out,
+                       (long long)X, (long long)Y, (long long)Z, mode);
+  hip_check(hipGetLastError(), "permute3 launch");
+}
+
+void launch_pack_w(int prec, const void* Q, void* P, int64_t N, int64_t K, int64_t rows, int64_t ld, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const long long total = rows * ld;
+  if (prec == PSIM_FP64)
+    hipLaunchKernelGGL(pack_w<double>, dim3(grid_for(total)), dim3(256), 0, st, (const double*)Q, (double*)P,
+                       (long long)N, (long long)K, (long long)rows, (long long)ld, 0);
+  else
+    hipLaunchKernelGGL(pack_w<float>, dim3(grid_for(total)), dim3(256), 0, st, (const float*)Q, (float*)P,
+                       (long long)N, (long long)K, (long long)rows, (long long)ld, prec == PSIM_FP32_3M ? 1 : 0);
+  hip_check(hipGetLastError(), "pack_w launch");
+}
+
+int cdot_blocks() { return 1024; }
+
+void launch_cdot(int prec, const void* a, const void* b, int64_t n, double* part, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == PSIM_FP64)
+    hipLaunchKernelGGL(cdot_partial<double>, dim3(cdot_blocks()), dim3(256), 0, st, (const double*)a, (const double*)b,
+                       (long long)n, part);
+  else
+    hipLaunchKernelGGL(cdot_partial<float>, dim3(cdot_blocks()), dim3(256), 0, st, (const float*)a, (const float*)b,
+                       (long long)n, part);
+  hip_check(hipGetLastError(), "cdot launch");
 }
 
 void launch_copy_segments(const CopySeg* d_segs, int n, int64_t max_bytes, void* stream) {

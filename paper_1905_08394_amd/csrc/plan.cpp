@@ -189,7 +189,33 @@ psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o) {
     fail(PSIM_EINVAL, "tile_cfg " + std::to_string(opts.tile_cfg) + " is not a candidate of this precision");
   int sweep = opts.sweep;
   if (sweep == 0) sweep = (P->lh <= P->lv) ? 1 : 2;
-  if (sweep != 1 && sweep != 2) fail(PSIM_EINVAL, "sweep must be 0, 1 or 2");
+  if (sweep < 1 || sweep > 3) fail(PSIM_EINVAL, "sweep must be 0, 1, 2 or 3");
+  if (sweep == 3) {  // square partition (square.cpp)
+    auto* pl = new psim_plan_t();
+    try {
+      pl->opts = opts;
+      pl->lv = P->lv;
+      pl->lh = P->lh;
+      pl->sweep = 3;
+      pl->R = pl->L = P->lv;
+      pl->host_only = (opts.flags & PSIM_PLAN_HOST_ONLY) != 0;
+      pl->elem_bytes = opts.prec == PSIM_FP64 ? 16 : 8;
+      pl->chi = 1;
+      for (const Site& s : P->sites) pl->chi = std::max({pl->chi, s.dl, s.dr, s.du, s.dd});
+      if (!pl->host_only) hip_check(hipSetDevice(opts.device), "hipSetDevice");
+      make_square_plan(pl, *P);
+      if (!pl->host_only) {
+        hip_check(hipMalloc(&pl->d_ones, 16), "hipMalloc(ones)");
+        launch_fill_ones(opts.prec, pl->d_ones, nullptr);
+        hip_check(hipDeviceSynchronize(), "fill ones");
+      }
+    } catch (...) {
+      if (pl->d_ones) (void)hipFree(pl->d_ones);
+      delete pl;
+      throw;
+    }
+    return pl;
+  }
 
   auto* pl = new psim_plan_t();
   try {

@@ -4,6 +4,7 @@
 #include <complex>
 #include <cstdint>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -87,6 +88,10 @@ struct DevMatrix {
 
 }  // namespace psim
 
+namespace psim {
+struct SquarePlan;
+}
+
 struct psim_plan_s {
   psim_plan_opts opts{};
   int lv = 0, lh = 0;
@@ -111,6 +116,9 @@ struct psim_plan_s {
   std::map<std::vector<int64_t>, void*> graphs;
   void* cap_stream = nullptr;
   int64_t max_ops = 0;                   // most device operations one sub-batch can need
+  // square partition (sweep 3): quadrant frames, packed site matrices, workspace plan
+  std::shared_ptr<psim::SquarePlan> sq;
+  int64_t sq_steps = 0;
 };
 
 // Plans run together (psim_group): the plans are borrowed; the group owns the
@@ -200,6 +208,16 @@ struct CopySeg {
   int64_t bytes;
 };
 void launch_copy_segments(const CopySeg* d_segs, int n, int64_t max_bytes, void* stream);
+// square partition: complex in[X][Y][Z] -> out[Y][X][Z] (mode 0) or out[X][Z][Y] (mode 1)
+void launch_permute3(int prec, const void* in, void* out, int64_t X, int64_t Y, int64_t Z, int mode, void* stream);
+// device Q[n][k] (N x K complex) -> packed W operand for W[k][n] = Q[n][k] (rows x ld, zero padded)
+void launch_pack_w(int prec, const void* Q, void* P, int64_t N, int64_t K, int64_t rows, int64_t ld, void* stream);
+// sum_i a[i] b[i] over n complex elements: cdot_blocks() (re, im) partial sums in FP64
+int cdot_blocks();
+// square.cpp
+void make_square_plan(psim_plan_t* pl, const psim_peps_t& P);
+void run_square(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, void* stream, double* out);
+void launch_cdot(int prec, const void* a, const void* b, int64_t n, double* part, void* stream);
 bool rescale_fusable(int64_t per_node);
 int max_scale_group();
 void launch_rescale_group(int prec, const RescaleJob* jobs, int n, void* stream);

@@ -1,0 +1,402 @@
+// Square partition of an L x L lattice, L even (supplement S-II, Fig. S2(b),
+// eqs. S9-S10).
+//
+// The lattice is cut into four h x h quadrants (h = L/2).  Each quadrant is
+// contracted on its own from its lattice corner inward; what is left open
+// are the bonds it shares with the two neighbouring quadrants: h horizontal
+// bonds of the middle vertical cut and h vertical bonds of the middle
+// horizontal cut.  The four quadrant tensors are then joined, each join
+// being one complex GEMM of size D^h x D^h x D^h (the leading term of eq.
+// S10):
+//   T[vUR][vUL] = sum_hU   Q_UR[vUR][hU]  Q_UL[vUL][hU]
+//   Y[vUR][hL]  = sum_vUL  T[vUR][vUL]    Q_LL[hL][vUL]
+//   <tau|psi>   = sum      Y[vUR][hL]     Q_LR[vUR][hL].
+// Bitstrings that agree on the upper half share T, those that also agree on
+// the lower-left quadrant share Y (the reuse of the fast-sampling remark).
+//
+// Quadrant frames.  Quadrant q is walked in a frame (i, j), i, j < h, that
+// starts at its lattice corner: rows are mirrored for the lower quadrants
+// (bottom-up) and columns for the right ones (right to left), with the legs
+// l/r and u/d swapped accordingly.  Frame row 0 lies on the lattice edge and
+// frame column 0 too, so their u and l legs have size 1; the frame-r legs of
+// column h-1 (o_i) and the frame-d legs of row h-1 stay open.
+//
+// Leg order inside a quadrant.  Before frame row i the running tensor is
+//   [u_0 .. u_{h-1}][o_0 .. o_{i-1}]   (u_j = frame-d leg of site (i-1, j)),
+// and site j of the row is one GEMM of the row scheme's rotating layout,
+//   C[m][(d_j, r_j)] = sum_{u_j, r_{j-1}} A[u_j][m][r_{j-1}] W[(u_j, l_j)][(d_j, r_j)],
+// with m = [u_{j+1} .. u_{h-1}][o_0 .. o_{i-1}][d_0 .. d_{j-1}] untouched.
+// After the row the tensor is [o_0 .. o_{i-1}][d_0 .. d_{h-1}][o_i]; one
+// permute brings it to [d ...][o_0 .. o_i] for the next row.  The finished
+// quadrant is stored as [d ...][o ...] (UL, UR, LR) or [o ...][d ...] (LL),
+// the layouts the joins read (a quadrant tensor Q[n][k] is the packed W
+// operand of W[k][n] = Q[n][k]).
+//
+// Every tensor is rescaled by an exact power of two after each row and each
+// join; the exponents are summed on the host in FP64 with the site-matrix
+// exponents.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+
+#include <hip/hip_runtime_api.h>
+
+#include "psim_internal.hpp"
+
+namespace psim {
+
+struct SqSite {
+  int qubit = 0;
+  int dl = 1, dr = 1, du = 1, dd = 1;  // frame leg sizes
+  DevMatrix w[2];                       // packed W[(u, l)][(d, r)] for tau = 0, 1
+};
+
+struct SqQuad {
+  int mr = 0, mc = 0;          // mirrored rows / columns
+  std::vector<SqSite> s;       // frame (i, j) at i * h + j
+  int64_t dv = 1, dh = 1;      // sizes of the open vertical-cut / horizontal-cut legs
+  double cmac = 0;
+};
+
+struct SquarePlan {
+  int L = 0, h = 0;
+  SqQuad q[4];                 // UL, UR, LL, LR
+  int64_t tmax = 1;            // largest running tensor (complex elements)
+  int64_t qmax = 1;            // largest quadrant / joined tensor
+  int64_t prow[2] = {0, 0}, pld[2] = {0, 0};  // packed operands of the two joins
+  uint64_t off_w1 = 0, off_w2 = 0, off_a = 0, off_b = 0, off_c = 0, off_p = 0, off_small = 0;
+  double cmac_quads = 0, cmac_joins = 0;
+  int64_t n_steps = 0;
+  ~SquarePlan() {
+    for (auto& qd : q)
+      for (auto& st : qd.s)
+        for (auto& w : st.w)
+          if (w.ptr) (void)hipFree(w.ptr);
+  }
+};
+
+namespace {
+
+int exponent_of_max_sq(const std::vector<cd>& W) {
+  double mx = 0;
+  for (const cd& w : W) mx = std::max(mx, std::max(std::abs(w.real()), std::abs(w.imag())));
+  if (mx == 0) return 0;
+  int e;
+  std::frexp(mx, &e);
+  return e;
+}
+
+// Running-tensor shapes of frame site (i, j): M, K1, K2, N as in the header.
+struct Shape {
+  int64_t M, K1, K2, N;
+};
+
+Shape site_shape(const SqQuad& Q, int h, int i, int j) {
+  auto at = [&](int a, int b) -> const SqSite& { return Q.s[(size_t)a * h + b]; };
+  Shape sh;
+  sh.K1 = at(i, j).du;
+  sh.K2 = at(i, j).dl;
+  sh.N = (int64_t)at(i, j).dd * at(i, j).dr;
+  int64_t M = 1;
+  for (int jj = j + 1; jj < h; ++jj) M *= at(i, jj).du;
+  for (int k = 0; k < i; ++k) M *= at(k, h - 1).dr;
+  for (int jj = 0; jj < j; ++jj) M *= at(i, jj).dd;
+  sh.M = M;
+  return sh;
+}
+
+}  // namespace
+
+void make_square_plan(psim_plan_t* pl, const psim_peps_t& P) {
+  const int L = P.lv;
+  if (P.lv != P.lh || L < 2 || L % 2) fail(PSIM_EUNSUPPORTED, "the square partition needs an L x L lattice with L even");
+  const int prec = pl->opts.prec;
+  if (prec == PSIM_BF16X3) fail(PSIM_EUNSUPPORTED, "the square partition runs in FP64, FP32 4M or FP32 3M");
+  auto sq = std::make_shared<SquarePlan>();
+  const int h = L / 2;
+  sq->L = L;
+  sq->h = h;
+  const int mirror[4][2] = {{0, 0}, {0, 1}, {1, 0}, {1, 1}};
+  for (int qi = 0; qi < 4; ++qi) {
+    SqQuad& Q = sq->q[qi];
+    Q.mr = mirror[qi][0];
+    Q.mc = mirror[qi][1];
+    Q.s.resize((size_t)h * h);
+    for (int i = 0; i < h; ++i)
+      for (int j = 0; j < h; ++j) {
+        const int r = Q.mr ? L - 1 - i : i, c = Q.mc ? L - 1 - j : j;
+        SqSite& st = Q.s[(size_t)i * h + j];
+        st.qubit = r * L + c;
+        const Site& s = P.sites[st.qubit];
+        st.dl = Q.mc ? s.dr : s.dl;
+        st.dr = Q.mc ? s.dl : s.dr;
+        st.du = Q.mr ? s.dd : s.du;
+        st.dd = Q.mr ? s.du : s.dd;
+      }
+    for (int j = 0; j < h; ++j) Q.dv *= Q.s[(size_t)(h - 1) * h + j].dd;
+    for (int i = 0; i < h; ++i) Q.dh *= Q.s[(size_t)i * h + h - 1].dr;
+    for (int i = 0; i < h; ++i)
+      for (int j = 0; j < h; ++j) {
+        const Shape sh = site_shape(Q, h, i, j);
+        Q.cmac += (double)sh.M * sh.K1 * sh.K2 * sh.N;
+        sq->tmax = std::max({sq->tmax, sh.M * sh.K1 * sh.K2, sh.M * sh.N});
+        ++sq->n_steps;
+      }
+    sq->qmax = std::max(sq->qmax, Q.dv * Q.dh);
+    sq->cmac_quads += Q.cmac;
+  }
+  const int64_t vUL = sq->q[0].dv, vUR = sq->q[1].dv, hU = sq->q[0].dh, hL = sq->q[2].dh;
+  if (sq->q[1].dh != hU || sq->q[2].dv != vUL || sq->q[3].dv != vUR || sq->q[3].dh != hL)
+    fail(PSIM_EINTERNAL, "quadrant cut legs do not match");
+  sq->qmax = std::max({sq->qmax, vUR * vUL, vUR * hL});
+  sq->cmac_joins = (double)vUR * hU * vUL + (double)vUR * vUL * hL + (double)vUR * hL;
+  sq->n_steps += 2;
+  // packed W operands: join 1 reads Q_UL as (N = vUL) x (K = hU), join 2 reads Q_LL as (N = hL) x (K = vUL)
+  sq->prow[0] = packed_rows(prec, vUL);
+  sq->pld[0] = packed_ld(prec, hU);
+  sq->prow[1] = packed_rows(prec, hL);
+  sq->pld[1] = packed_ld(prec, vUL);
+
+  // ---------------------------------------------------------- workspace
+  const uint64_t eb = pl->elem_bytes;  // bytes per complex element
+  const uint64_t rb = eb / 2;          // bytes per real
+  auto al = [](uint64_t x) { return (x + 255) / 256 * 256; };
+  uint64_t off = 0;
+  sq->off_w1 = off; off += al((uint64_t)sq->tmax * eb);
+  sq->off_w2 = off; off += al((uint64_t)sq->tmax * eb);
+  sq->off_a = off; off += al((uint64_t)sq->qmax * eb);
+  sq->off_b = off; off += al((uint64_t)sq->qmax * eb);
+  sq->off_c = off; off += al((uint64_t)sq->qmax * eb);
+  sq->off_p = off;
+  off += al((uint64_t)std::max(sq->prow[0] * sq->pld[0], sq->prow[1] * sq->pld[1]) * rb);
+  sq->off_small = off;
+  off += al(16 + (uint64_t)cdot_blocks() * 16);
+  pl->ws_total = off + 256;
+  if (pl->ws_total > pl->opts.mem_budget_bytes)
+    fail(PSIM_ENOMEM, "square partition needs " + std::to_string(pl->ws_total) + " bytes; budget is " +
+                          std::to_string(pl->opts.mem_budget_bytes));
+  pl->peak_elems = std::max(sq->tmax, sq->qmax);
+  pl->cmac = sq->cmac_quads + sq->cmac_joins;
+
+  // ---------------------------------------------------------- site matrices
+  std::vector<cd> W;
+  std::vector<char> buf;
+  for (auto& Q : sq->q)
+    for (auto& st : Q.s) {
+      const Site& s = P.sites[st.qubit];
+      const int64_t K = (int64_t)st.du * st.dl, N = (int64_t)st.dd * st.dr;
+      for (int tau = 0; tau < 2; ++tau) {
+        W.assign((size_t)(K * N), cd(0.0));
+        for (int u = 0; u < st.du; ++u)
+          for (int l = 0; l < st.dl; ++l)
+            for (int d = 0; d < st.dd; ++d)
+              for (int r = 0; r < st.dr; ++r) {
+                const int ol = Q.mc ? r : l, orr = Q.mc ? l : r;
+                const int ou = Q.mr ? d : u, od = Q.mr ? u : d;
+                W[(size_t)((u * st.dl + l) * N + d * st.dr + r)] = s.t[s.at(tau, ol, orr, ou, od)];
+              }
+        DevMatrix& dm = st.w[tau];
+        dm.exp2 = exponent_of_max_sq(W);
+        const double sc = std::ldexp(1.0, -dm.exp2);
+        for (cd& x : W) x *= sc;
+        pack_site_matrix(prec, W.data(), K, N, buf, dm.ld);
+        pl->weights_bytes += buf.size();
+        if (!pl->host_only) {
+          hip_check(hipMalloc(&dm.ptr, buf.size()), "hipMalloc(site matrix)");
+          hip_check(hipMemcpy(dm.ptr, buf.data(), buf.size(), hipMemcpyHostToDevice), "hipMemcpy(site matrix)");
+        }
+      }
+    }
+  pl->sq = sq;
+  pl->sq_steps = sq->n_steps;
+}
+
+namespace {
+
+struct SqRun {
+  const psim_plan_t* pl;
+  const SquarePlan* sq;
+  hipStream_t st;
+  char* base;
+  int prec;
+  uint64_t eb;
+  int32_t* d_zero;
+  int32_t* d_e;
+  uint32_t* d_mx;
+  double* d_part;
+
+  char* buf(uint64_t off) const { return base + off; }
+
+  // exact power-of-two rescale of one tensor; returns the exponent taken out
+  int64_t rescale(void* T, int64_t elems) {
+    launch_rowscale(prec, T, elems, 1, d_zero, d_zero, d_e, d_mx, st);
+    int32_t e = 0;
+    hip_check(hipMemcpyAsync(&e, d_e, 4, hipMemcpyDeviceToHost, st), "download exponent");
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    return e;
+  }
+
+  // Contract quadrant qi for bits into dst; returns its exponent.
+  int64_t quad(int qi, const uint8_t* bits, char* dst) {
+    const SqQuad& Q = sq->q[qi];
+    const int h = sq->h;
+    char* cur = buf(sq->off_w1);
+    char* nxt = buf(sq->off_w2);
+    int64_t e = 0;
+    int64_t cur_elems = 1;
+    for (int i = 0; i < h; ++i) {
+      for (int j = 0; j < h; ++j) {
+        const SqSite& st_ = Q.s[(size_t)i * h + j];
+        const int tau = bits[st_.qubit];
+        const DevMatrix& w = st_.w[tau];
+        const Shape sh = site_shape(Q, h, i, j);
+        GemmLaunch g;
+        g.prec = prec;
+        g.A = (i == 0 && j == 0) ? pl->d_ones : (const void*)cur;
+        g.C = nxt;
+        g.W0 = g.W1 = w.ptr;
+        g.ldw = w.ld;
+        g.M = sh.M;
+        g.K1 = sh.K1;
+        g.K2 = sh.K2;
+        g.N = sh.N;
+        g.nodes = 1;
+        g.Bz = 1;
+        g.sA_node = sh.K1 * sh.M * sh.K2;
+        g.sC_node = sh.M * sh.N;
+        launch_site_gemm(g, st);
+        e += w.exp2;
+        std::swap(cur, nxt);
+        cur_elems = sh.M * sh.N;
+      }
+      e += rescale(cur, cur_elems);
+      // [o_0 .. o_{i-1}][d_0 .. d_{h-1}][o_i] -> next layout
+      int64_t X = 1, Y = 1;
+      for (int k = 0; k < i; ++k) X *= Q.s[(size_t)k * h + h - 1].dr;
+      for (int j = 0; j < h; ++j) Y *= Q.s[(size_t)i * h + j].dd;
+      const int64_t Z = Q.s[(size_t)i * h + h - 1].dr;
+      if (i + 1 < h) {
+        if (X > 1) {
+          launch_permute3(prec, cur, nxt, X, Y, Z, 0, st);
+          std::swap(cur, nxt);
+        }
+      } else {
+        launch_permute3(prec, cur, dst, X, Y, Z, qi == 2 ? 1 : 0, st);
+      }
+    }
+    return e;
+  }
+
+  void gemm(const void* A, int64_t M, int64_t K, const void* P, int64_t ld, int64_t N, void* C) {
+    GemmLaunch g;
+    g.prec = prec;
+    g.A = A;
+    g.C = C;
+    g.W0 = g.W1 = P;
+    g.ldw = ld;
+    g.M = M;
+    g.K1 = 1;
+    g.K2 = K;
+    g.N = N;
+    g.nodes = 1;
+    g.Bz = 1;
+    g.sA_node = M * K;
+    g.sC_node = M * N;
+    launch_site_gemm(g, st);
+  }
+};
+
+}  // namespace
+
+void run_square(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, void* stream, double* out) {
+  const SquarePlan* sq = pl->sq.get();
+  const int L = sq->L, h = sq->h, nq = L * L;
+  hip_check(hipSetDevice(pl->opts.device), "hipSetDevice");
+  SqRun R;
+  R.pl = pl;
+  R.sq = sq;
+  R.st = (hipStream_t)stream;
+  R.base = (char*)(((uintptr_t)ws + 255) / 256 * 256);
+  R.prec = pl->opts.prec;
+  R.eb = pl->elem_bytes;
+  char* small = R.buf(sq->off_small);
+  R.d_zero = (int32_t*)small;
+  R.d_e = (int32_t*)(small + 4);
+  R.d_mx = (uint32_t*)(small + 8);
+  R.d_part = (double*)(small + 16);
+  static const int32_t zero = 0;
+  hip_check(hipMemcpyAsync(R.d_zero, &zero, 4, hipMemcpyHostToDevice, R.st), "upload zero");
+
+  // quadrant keys: the bits of its sites in frame order
+  auto key = [&](size_t b, int qi) {
+    std::vector<uint8_t> k((size_t)h * h);
+    for (size_t x = 0; x < k.size(); ++x) k[x] = bits[b * nq + sq->q[qi].s[x].qubit];
+    return k;
+  };
+  std::vector<size_t> order(n);
+  for (size_t b = 0; b < n; ++b) order[b] = b;
+  std::vector<std::vector<uint8_t>> keys(n);
+  for (size_t b = 0; b < n; ++b) {
+    std::vector<uint8_t> k;
+    for (int qi = 0; qi < 4; ++qi) {
+      auto kq = key(b, qi);
+      k.insert(k.end(), kq.begin(), kq.end());
+    }
+    keys[b] = k;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return keys[x] < keys[y]; });
+  const size_t qk = (size_t)h * h;
+  auto same = [&](size_t x, size_t y, int upto) {  // keys agree on quadrants 0 .. upto-1
+    return std::equal(keys[x].begin(), keys[x].begin() + qk * upto, keys[y].begin());
+  };
+
+  const int64_t vUL = sq->q[0].dv, vUR = sq->q[1].dv, hU = sq->q[0].dh, hL = sq->q[2].dh;
+  char* A = R.buf(sq->off_a);
+  char* B = R.buf(sq->off_b);
+  char* C = R.buf(sq->off_c);
+  char* P = R.buf(sq->off_p);
+  const int nblk = cdot_blocks();
+  std::vector<double> part((size_t)nblk * 2);
+  int64_t eT = 0, eY = 0, amp_e = 0;
+  double amp_re = 0, amp_im = 0;
+  for (size_t x = 0; x < n; ++x) {
+    const size_t b = order[x];
+    const bool new_upper = x == 0 || !same(order[x - 1], b, 2);
+    const bool new_ll = new_upper || !same(order[x - 1], b, 3);
+    const bool new_lr = new_ll || !same(order[x - 1], b, 4);
+    const uint8_t* bb = bits + b * nq;
+    if (new_upper) {
+      const int64_t eUL = R.quad(0, bb, A);   // Q_UL [vUL][hU]
+      const int64_t eUR = R.quad(1, bb, B);   // Q_UR [vUR][hU]
+      launch_pack_w(R.prec, A, P, vUL, hU, sq->prow[0], sq->pld[0], R.st);
+      R.gemm(B, vUR, hU, P, sq->pld[0], vUL, C);  // T [vUR][vUL]
+      eT = eUL + eUR + R.rescale(C, vUR * vUL);
+    }
+    if (new_ll) {
+      const int64_t eLL = R.quad(2, bb, A);   // Q_LL [hL][vUL]
+      launch_pack_w(R.prec, A, P, hL, vUL, sq->prow[1], sq->pld[1], R.st);
+      R.gemm(C, vUR, vUL, P, sq->pld[1], hL, B);  // Y [vUR][hL]
+      eY = eT + eLL + R.rescale(B, vUR * hL);
+    }
+    if (new_lr) {
+      const int64_t eLR = R.quad(3, bb, A);   // Q_LR [vUR][hL]
+      launch_cdot(R.prec, B, A, vUR * hL, R.d_part, R.st);
+      hip_check(hipMemcpyAsync(part.data(), R.d_part, part.size() * 8, hipMemcpyDeviceToHost, R.st), "download");
+      hip_check(hipStreamSynchronize(R.st), "hipStreamSynchronize");
+      double re = 0, im = 0;
+      for (int k = 0; k < nblk; ++k) {
+        re += part[2 * k];
+        im += part[2 * k + 1];
+      }
+      amp_re = re;
+      amp_im = im;
+      amp_e = eY + eLR;
+    }
+    out[2 * b] = std::ldexp(amp_re, (int)amp_e);
+    out[2 * b + 1] = std::ldexp(amp_im, (int)amp_e);
+  }
+}
+
+}  // namespace psim

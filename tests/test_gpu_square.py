@@ -1,0 +1,93 @@
+"""GPU parity of the square partition (supplement S-II, Fig. S2(b), eqs.
+S9-S10): four quadrant contractions joined by two D^h x D^h x D^h complex
+GEMMs and a final inner product, against the oracle (state vector up to 16
+qubits, the oracle's PEPS contraction above, the 6x6 (1+40+1) golden values
+from the oracle's sliced square partition) and against the row scheme."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import rqcgen
+from oracle import peps as opeps
+from oracle import statevector as sv
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+AMP_BAR = {"fp64": 1e-10, "fp32": 1e-5, "fp32_3m": 1e-5}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ps():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1905_08394_amd as ps
+    ps.lib()
+    return ps
+
+
+def _eps_rms(a, r, nq):
+    return np.abs(np.asarray(a) - np.asarray(r)) * 2.0 ** (nq / 2)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_3m"])
+@pytest.mark.parametrize("L,d,seed,nb", [(2, 8, 0, 16), (4, 16, 1, 48), (4, 24, 2, 48)])
+def test_square_small_vs_state_vector(ps, prec, L, d, seed, nb):
+    c = rqcgen.generate(L, L, d, seed)
+    bits = rqcgen.all_bitstrings(L * L) if L == 2 else rqcgen.bitstrings(L, L, seed, nb)
+    ref = sv.amplitudes(sv.run(c), bits)
+    pl = ps.Plan(ps.Peps(c), prec=prec, sweep=3)
+    assert pl.stats()["sweep"] == 3
+    a = pl.amplitudes(bits)
+    e = _eps_rms(a, ref, L * L)
+    say(f"square {L}x{L} d{d} {prec}: max eps_rms {e.max():.2e}")
+    assert e.max() <= AMP_BAR[prec]
+
+
+def test_square_6x6_d16_vs_oracle_and_row_scheme(ps):
+    c = rqcgen.generate(6, 6, 16, 3)
+    bits = rqcgen.bitstrings(6, 6, 3, 12)
+    ref = opeps.amplitudes(opeps.build(c), bits)
+    P = ps.Peps(c)
+    sq = ps.Plan(P, prec="fp64", sweep=3).amplitudes(bits)
+    row = ps.Plan(P, prec="fp64", max_batch=len(bits)).amplitudes(bits)
+    assert np.max(np.abs(sq - ref)) <= 1e-12 * np.max(np.abs(ref))
+    assert np.max(np.abs(sq - row)) <= 1e-12 * np.max(np.abs(ref))
+    a3 = ps.Plan(P, prec="fp32_3m", sweep=3).amplitudes(bits)
+    assert _eps_rms(a3, ref, 36).max() <= AMP_BAR["fp32_3m"]
+
+
+def test_square_duplicates_and_order(ps):
+    """Bitstrings in any order, with repeats, sharing some quadrants."""
+    c = rqcgen.generate(4, 4, 16, 5)
+    base = rqcgen.bitstrings(4, 4, 5, 6)
+    bits = np.concatenate([base, base[::-1], base[:2]])
+    bits[3, 15] ^= 1                     # differs from base[3] in the lower-right quadrant only
+    ref = sv.amplitudes(sv.run(c), bits)
+    a = ps.Plan(ps.Peps(c), prec="fp64", sweep=3).amplitudes(bits)
+    assert np.max(np.abs(a - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec", ["fp32_3m", "fp64"])
+def test_square_6x6_d40_vs_golden(ps, prec):
+    with open(os.path.join(HERE, "golden", "rqc_6x6_d40_s0.json")) as f:
+        g = json.load(f)
+    c = rqcgen.generate(6, 6, 40, 0)
+    assert c.sha256() == g["sha256"]
+    bits = np.array(g["bits"], dtype=np.uint8)
+    ref = np.array(g["amps_re"]) + 1j * np.array(g["amps_im"])
+    pl = ps.Plan(ps.Peps(c), prec=prec, sweep=3, mem_budget=(64 if prec != "fp64" else 120) << 30)
+    say(f"square 6x6 d40 {prec}: workspace {pl.stats()['workspace_bytes'] / 2**30:.1f} GiB")
+    a = pl.amplitudes(bits)
+    rel = np.abs(a - ref) / np.abs(ref)
+    say(f"square 6x6 d40 {prec}: max eps_rel {rel.max():.2e}")
+    assert rel.max() <= (1e-10 if prec == "fp64" else 1e-5)

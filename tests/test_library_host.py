@@ -145,3 +145,79 @@ def test_bench_kernel_sections_exist():
     import bench
     hs = {p: bench.kernel_source_hash(p) for p in bench.KERNEL_SECTIONS}
     assert len(set(hs.values())) == len(hs) and all(len(h) == 64 for h in hs.values())
+
+
+def _square_cmac_from_oracle(L, dims):
+    """Independent count of the square partition's multiply-adds from the
+    oracle's bond dimensions: every quadrant absorbs its sites row by row from
+    its lattice corner (each absorption costs |running tensor after| times
+    the two contracted bond sizes), then two joins and one inner product."""
+    h = L // 2
+
+    def bond(kind, r, c):
+        return dims.get((kind, r, c), 1)
+
+    total = 0
+    cuts = {}
+    for mr in (0, 1):
+        for mc in (0, 1):
+            def site(i, j):
+                r = L - 1 - i if mr else i
+                c = L - 1 - j if mc else j
+                left = bond("h", r, c - 1) if c > 0 else 1
+                right = bond("h", r, c) if c < L - 1 else 1
+                up = bond("v", r - 1, c) if r > 0 else 1
+                down = bond("v", r, c) if r < L - 1 else 1
+                if mc:
+                    left, right = right, left
+                if mr:
+                    up, down = down, up
+                return left, right, up, down
+            for i in range(h):
+                for j in range(h):
+                    # open legs of the running tensor after absorbing (i, j)
+                    after = 1
+                    for jj in range(h):
+                        after *= site(i, jj)[3] if jj <= j else site(i, jj)[2]
+                    for k in range(i):
+                        after *= site(k, h - 1)[1]
+                    after *= site(i, j)[1]
+                    l, _, u, _ = site(i, j)
+                    total += after * l * u
+            dv = 1
+            for j in range(h):
+                dv *= site(h - 1, j)[3]
+            dh = 1
+            for i in range(h):
+                dh *= site(i, h - 1)[1]
+            cuts[(mr, mc)] = (dv, dh)
+    vUL, hU = cuts[(0, 0)]
+    vUR, _ = cuts[(0, 1)]
+    _, hL = cuts[(1, 0)]
+    return total + vUR * hU * vUL + vUR * vUL * hL + vUR * hL
+
+
+@pytest.mark.parametrize("L,d", [(2, 8), (4, 16), (4, 13), (6, 16), (6, 40)])
+def test_square_plan_count_matches_oracle(ps, L, d):
+    c = rqcgen.generate(L, L, d, 0)
+    s = ps.Plan(ps.Peps(c), prec="fp32_3m", host_only=True, sweep=3, mem_budget=1 << 62).stats()
+    dims = opeps.bond_dims(opeps.build(c))
+    assert s["cmac_per_amplitude"] == _square_cmac_from_oracle(L, dims)
+    assert s["sweep"] == 3 and s["n_gemm_steps"] == L * L + 2
+    if d == 40:
+        # leading term: eq. (S10), 2 D^(3L/2) (quadrant costs add the rest)
+        assert 1.0 <= s["cmac_per_amplitude"] / cx.even_square_time(L, d) < 1.2
+
+
+def test_square_plan_errors(ps):
+    for lv, lh in ((3, 3), (4, 6)):
+        with pytest.raises(ps.PsimError) as e:
+            ps.Plan(ps.Peps(rqcgen.generate(lv, lh, 8, 0)), prec="fp32", host_only=True, sweep=3)
+        assert e.value.status == ps.PSIM_EUNSUPPORTED
+    P = ps.Peps(rqcgen.generate(4, 4, 8, 0))
+    with pytest.raises(ps.PsimError) as e:
+        ps.Plan(P, prec="bf16x3", host_only=True, sweep=3)
+    assert e.value.status == ps.PSIM_EUNSUPPORTED
+    with pytest.raises(ps.PsimError) as e:
+        ps.Plan(P, prec="fp32", host_only=True, sweep=4)
+    assert e.value.status == ps.PSIM_EINVAL
