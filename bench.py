@@ -59,12 +59,12 @@ def workload(lattice, depth, seed=0):
     return c, rqcgen.last_row_variants(base, lattice, lattice, cols)
 
 
-def run_gpu(args, prec, circuit, bits):
+def run_gpu(args, prec, circuit, bits, sweep=0):
     import torch
     import paper_1905_08394_amd as ps
     peps = ps.Peps(circuit)
     plan = ps.Plan(peps, prec=prec, mem_budget=args.mem_gib << 30, max_batch=len(bits),
-                   split_acc=args.split_acc and prec == "fp32")
+                   split_acc=args.split_acc and prec == "fp32", sweep=sweep)
     peps.close()
     stats = plan.stats()
     plan.workspace()                               # allocate before timing
@@ -148,6 +148,33 @@ def cpu_baseline(circuit, bits, target_seconds):
             "sample": f"{tasks} (v,w) slice(s) of one interior row of the 6x6 (1+40+1) row scheme "
                       f"(oracle.peps.row_transfer, numpy complex128, {t:.1f} s), extrapolated by exact "
                       f"multiply-add counts to the 16-bitstring batch ({batch_cmac:.3e} CMAC)"}
+
+
+def square_leg(args, circuit, bits, row_value):
+    """The square partition on the batch the row scheme ran: seconds per
+    amplitude, its exact multiply-add count, and the join GEMMs (the
+    D^h x D^h x D^h steps, class 1 of the profile) against the MFMA peak."""
+    a = argparse.Namespace(**vars(args))
+    a.tune = False
+    log("square partition ...")
+    amps, el, prof, stats = run_gpu(a, args.prec, circuit, bits, sweep=3)
+    n_amp = args.steps * len(bits)
+    issued = ISSUED_PER_CMAC[args.prec]
+    cmac = sum(v["cmac"] for v in prof.values())
+    j = prof["interior_site"]   # class 1 of a square plan: the joins
+    join_tflops = issued * j["cmac"] / (j["ms"] / 1e3) / 1e12 if j["ms"] > 0 else None
+    out = {"s_per_amplitude": el / n_amp, "speedup_vs_row_scheme": row_value / (el / n_amp),
+           "cmac_per_step": cmac, "contraction_tflops": 8 * cmac / el / 1e12,
+           "workspace_gib": round(stats["workspace_bytes"] / 2 ** 30, 2),
+           "kernel_ms": {k: round(v["ms"], 3) for k, v in
+                         zip(("quadrant_sites", "joins", "permute_pack_dot", "rescale"), prof.values())},
+           "joins": {"achieved": join_tflops, "peak": PEAK_TFLOPS[args.prec], "unit": "TFLOP/s",
+                     "frac": join_tflops / PEAK_TFLOPS[args.prec] if join_tflops else None,
+                     "launches": j["launches"]}}
+    err = golden_errors(bits, amps, args.lattice, args.depth)
+    if err:
+        out["vs_oracle"] = err
+    return out
 
 
 def plain_fp64_gpu_baseline(stats, batch_cmac, nbits, reps=3):
@@ -389,6 +416,8 @@ def main():
     ap.add_argument("--no-tune", dest="tune", action="store_false", help="skip the tile autotuner")
     ap.add_argument("--split-acc", action="store_true", help="FP32 4M with per-stage partial sums")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-square", dest="square", action="store_false",
+                    help="skip timing the square partition on the same batch")
     ap.add_argument("--counters", action="store_true", help="short program for rocprofv3 --pmc passes")
     ap.add_argument("--fig2", action="store_true", help="8x8 (1+25+1) Porter-Thomas experiment")
     ap.add_argument("--fig2-count", type=int, default=2048)
@@ -506,6 +535,9 @@ def main():
         log("plain FP64 GPU baseline (torch complex128) ...")
         out["plain_fp64_gpu"] = plain_fp64_gpu_baseline(stats, cmac, len(bits))
         out["vs_plain_fp64_gpu"] = out["plain_fp64_gpu"]["value"] / out["value"]
+    if args.square and args.lattice % 2 == 0 and args.prec in ("fp32", "fp32_3m", "fp64"):
+        # the paper's square partition (Fig. S2(b), eqs. S9-S10) on the same batch
+        out["square_partition"] = square_leg(args, circuit, bits, out["value"])
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(circuit, bits, args.cpu_seconds)

@@ -178,7 +178,10 @@ psim_status psim_tune(psim_plan_t *plan, void *d_workspace, size_t workspace_byt
  * enables, op = 2 reads the accumulated totals into out[4] (nullable for
  * op 1/0), op = 0 disables.  cmac is the algorithmic complex multiply-add
  * count of the timed launches, bytes their algorithmic memory traffic (for
- * the memory-bound classes 0, 2 and 3). */
+ * the memory-bound classes 0, 2 and 3).  Square-partition plans (sweep 3)
+ * use the classes for: 0 = quadrant site contractions, 1 = the two joins
+ * (the D^h x D^h x D^h GEMMs), 2 = permutes, packing and inner products,
+ * 3 = rescales. */
 typedef struct {
   double ms;          /* summed kernel time */
   int64_t launches;

@@ -66,7 +66,8 @@ struct SquarePlan {
   int64_t tmax = 1;            // largest running tensor (complex elements)
   int64_t qmax = 1;            // largest quadrant / joined tensor
   int64_t prow[2] = {0, 0}, pld[2] = {0, 0};  // packed operands of the two joins
-  uint64_t off_w1 = 0, off_w2 = 0, off_a = 0, off_b = 0, off_c = 0, off_p = 0, off_small = 0;
+  uint64_t off_w1 = 0, off_w2 = 0, off_a = 0, off_b = 0, off_c = 0, off_p = 0, off_small = 0, off_y = 0;
+  int ycap = 1;                // Y tensors held at once (lower-left patterns joined per pass)
   double cmac_quads = 0, cmac_joins = 0;
   int64_t n_steps = 0;
   ~SquarePlan() {
@@ -173,6 +174,15 @@ void make_square_plan(psim_plan_t* pl, const psim_peps_t& P) {
   off += al((uint64_t)std::max(sq->prow[0] * sq->pld[0], sq->prow[1] * sq->pld[1]) * rb);
   sq->off_small = off;
   off += al(16 + (uint64_t)cdot_blocks() * 16);
+  // more Y tensors (one per lower-left pattern of a pass) from what the
+  // budget leaves, so each lower-right quadrant is contracted once per pass
+  sq->off_y = off;
+  const uint64_t ysz = al((uint64_t)sq->qmax * eb);
+  const uint64_t budget = pl->opts.mem_budget_bytes;
+  uint64_t extra = budget > off + 256 ? (budget - off - 256) / ysz : 0;
+  extra = std::min<uint64_t>({extra, 15, (uint64_t)std::max(pl->opts.max_batch, 1) - 1});
+  sq->ycap = 1 + (int)extra;
+  off += extra * ysz;
   pl->ws_total = off + 256;
   if (pl->ws_total > pl->opts.mem_budget_bytes)
     fail(PSIM_ENOMEM, "square partition needs " + std::to_string(pl->ws_total) + " bytes; budget is " +
@@ -226,12 +236,54 @@ struct SqRun {
   int32_t* d_e;
   uint32_t* d_mx;
   double* d_part;
+  // optional event timing (psim_profile): class 0 quadrant site contractions,
+  // 1 joins, 2 permutes / packing / inner products, 3 rescales
+  struct Timed {
+    hipEvent_t a, b;
+    int cls;
+    double cmac, bytes;
+  };
+  std::vector<Timed> timed;
+  bool profile = false;
 
   char* buf(uint64_t off) const { return base + off; }
 
+  template <typename F>
+  void run(int cls, double cmac, double bytes, F&& f) {
+    if (!profile) {
+      f();
+      return;
+    }
+    Timed t{};
+    t.cls = cls;
+    t.cmac = cmac;
+    t.bytes = bytes;
+    hip_check(hipEventCreate(&t.a), "hipEventCreate");
+    hip_check(hipEventCreate(&t.b), "hipEventCreate");
+    hip_check(hipEventRecord(t.a, st), "hipEventRecord");
+    f();
+    hip_check(hipEventRecord(t.b, st), "hipEventRecord");
+    timed.push_back(t);
+  }
+
+  void collect(psim_plan_t* p) {
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    for (Timed& t : timed) {
+      float ms = 0;
+      hip_check(hipEventElapsedTime(&ms, t.a, t.b), "hipEventElapsedTime");
+      p->prof[t.cls].ms += ms;
+      p->prof[t.cls].launches += 1;
+      p->prof[t.cls].cmac += t.cmac;
+      p->prof[t.cls].bytes += t.bytes;
+      (void)hipEventDestroy(t.a);
+      (void)hipEventDestroy(t.b);
+    }
+    timed.clear();
+  }
+
   // exact power-of-two rescale of one tensor; returns the exponent taken out
   int64_t rescale(void* T, int64_t elems) {
-    launch_rowscale(prec, T, elems, 1, d_zero, d_zero, d_e, d_mx, st);
+    run(3, 0, 3.0 * eb * elems, [&] { launch_rowscale(prec, T, elems, 1, d_zero, d_zero, d_e, d_mx, st); });
     int32_t e = 0;
     hip_check(hipMemcpyAsync(&e, d_e, 4, hipMemcpyDeviceToHost, st), "download exponent");
     hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
@@ -266,7 +318,8 @@ struct SqRun {
         g.Bz = 1;
         g.sA_node = sh.K1 * sh.M * sh.K2;
         g.sC_node = sh.M * sh.N;
-        launch_site_gemm(g, st);
+        run(0, (double)sh.M * sh.K1 * sh.K2 * sh.N, (double)eb * (sh.M * sh.K1 * sh.K2 + sh.M * sh.N),
+            [&] { launch_site_gemm(g, st); });
         e += w.exp2;
         std::swap(cur, nxt);
         cur_elems = sh.M * sh.N;
@@ -279,11 +332,11 @@ struct SqRun {
       const int64_t Z = Q.s[(size_t)i * h + h - 1].dr;
       if (i + 1 < h) {
         if (X > 1) {
-          launch_permute3(prec, cur, nxt, X, Y, Z, 0, st);
+          run(2, 0, 2.0 * eb * X * Y * Z, [&] { launch_permute3(prec, cur, nxt, X, Y, Z, 0, st); });
           std::swap(cur, nxt);
         }
       } else {
-        launch_permute3(prec, cur, dst, X, Y, Z, qi == 2 ? 1 : 0, st);
+        run(2, 0, 2.0 * eb * X * Y * Z, [&] { launch_permute3(prec, cur, dst, X, Y, Z, qi == 2 ? 1 : 0, st); });
       }
     }
     return e;
@@ -304,7 +357,10 @@ struct SqRun {
     g.Bz = 1;
     g.sA_node = M * K;
     g.sC_node = M * N;
-    launch_site_gemm(g, st);
+    run(1, (double)M * K * N, (double)eb * (M * K + K * N + M * N), [&] { launch_site_gemm(g, st); });
+  }
+  void pack(const void* Q, void* P, int64_t N, int64_t K, int64_t rows, int64_t ld) {
+    run(2, 0, (double)eb * N * K + (double)(eb / 2) * rows * ld, [&] { launch_pack_w(prec, Q, P, N, K, rows, ld, st); });
   }
 };
 
@@ -319,6 +375,7 @@ void run_square(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, void* 
   R.sq = sq;
   R.st = (hipStream_t)stream;
   R.base = (char*)(((uintptr_t)ws + 255) / 256 * 256);
+  R.profile = pl->profile;
   R.prec = pl->opts.prec;
   R.eb = pl->elem_bytes;
   char* small = R.buf(sq->off_small);
@@ -357,46 +414,72 @@ void run_square(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, void* 
   char* B = R.buf(sq->off_b);
   char* C = R.buf(sq->off_c);
   char* P = R.buf(sq->off_p);
+  const uint64_t ysz = ((uint64_t)sq->qmax * R.eb + 255) / 256 * 256;
+  auto ybuf = [&](int k) { return k == 0 ? B : R.buf(sq->off_y) + (uint64_t)(k - 1) * ysz; };
   const int nblk = cdot_blocks();
   std::vector<double> part((size_t)nblk * 2);
-  int64_t eT = 0, eY = 0, amp_e = 0;
-  double amp_re = 0, amp_im = 0;
-  for (size_t x = 0; x < n; ++x) {
-    const size_t b = order[x];
-    const bool new_upper = x == 0 || !same(order[x - 1], b, 2);
-    const bool new_ll = new_upper || !same(order[x - 1], b, 3);
-    const bool new_lr = new_ll || !same(order[x - 1], b, 4);
-    const uint8_t* bb = bits + b * nq;
-    if (new_upper) {
-      const int64_t eUL = R.quad(0, bb, A);   // Q_UL [vUL][hU]
-      const int64_t eUR = R.quad(1, bb, B);   // Q_UR [vUR][hU]
-      launch_pack_w(R.prec, A, P, vUL, hU, sq->prow[0], sq->pld[0], R.st);
-      R.gemm(B, vUR, hU, P, sq->pld[0], vUL, C);  // T [vUR][vUL]
-      eT = eUL + eUR + R.rescale(C, vUR * vUL);
-    }
-    if (new_ll) {
-      const int64_t eLL = R.quad(2, bb, A);   // Q_LL [hL][vUL]
-      launch_pack_w(R.prec, A, P, hL, vUL, sq->prow[1], sq->pld[1], R.st);
-      R.gemm(C, vUR, vUL, P, sq->pld[1], hL, B);  // Y [vUR][hL]
-      eY = eT + eLL + R.rescale(B, vUR * hL);
-    }
-    if (new_lr) {
-      const int64_t eLR = R.quad(3, bb, A);   // Q_LR [vUR][hL]
-      launch_cdot(R.prec, B, A, vUR * hL, R.d_part, R.st);
-      hip_check(hipMemcpyAsync(part.data(), R.d_part, part.size() * 8, hipMemcpyDeviceToHost, R.st), "download");
-      hip_check(hipStreamSynchronize(R.st), "hipStreamSynchronize");
-      double re = 0, im = 0;
-      for (int k = 0; k < nblk; ++k) {
-        re += part[2 * k];
-        im += part[2 * k + 1];
+  size_t x = 0;
+  while (x < n) {
+    // bitstrings [x, xe) share the upper half: T once
+    size_t xe = x + 1;
+    while (xe < n && same(order[x], order[xe], 2)) ++xe;
+    const uint8_t* b0 = bits + order[x] * nq;
+    const int64_t eUL = R.quad(0, b0, A);       // Q_UL [vUL][hU]
+    const int64_t eUR = R.quad(1, b0, B);       // Q_UR [vUR][hU]
+    R.pack(A, P, vUL, hU, sq->prow[0], sq->pld[0]);
+    R.gemm(B, vUR, hU, P, sq->pld[0], vUL, C);  // T [vUR][vUL]
+    const int64_t eT = eUL + eUR + R.rescale(C, vUR * vUL);
+    size_t y = x;
+    while (y < xe) {
+      // one pass: up to ycap lower-left patterns, each joined into its Y
+      std::vector<int64_t> eY;
+      std::vector<int> slot(xe - y);  // Y of each bitstring of the pass
+      size_t ye = y;
+      while (ye < xe && (int)eY.size() < sq->ycap) {
+        const uint8_t* bb = bits + order[ye] * nq;
+        const int k = (int)eY.size();
+        const int64_t eLL = R.quad(2, bb, A);   // Q_LL [hL][vUL]
+        R.pack(A, P, hL, vUL, sq->prow[1], sq->pld[1]);
+        R.gemm(C, vUR, vUL, P, sq->pld[1], hL, ybuf(k));  // Y [vUR][hL]
+        eY.push_back(eT + eLL + R.rescale(ybuf(k), vUR * hL));
+        size_t z = ye;
+        while (z < xe && same(order[ye], order[z], 3)) slot[z++ - y] = k;
+        ye = z;
       }
-      amp_re = re;
-      amp_im = im;
-      amp_e = eY + eLR;
+      // each lower-right pattern of the pass once, dotted with the Y's that need it
+      std::map<std::vector<uint8_t>, std::vector<size_t>> lr;
+      for (size_t z = y; z < ye; ++z)
+        lr[std::vector<uint8_t>(keys[order[z]].begin() + 3 * qk, keys[order[z]].end())].push_back(z);
+      for (auto& kv : lr) {
+        const uint8_t* bb = bits + order[kv.second.front()] * nq;
+        const int64_t eLR = R.quad(3, bb, A);   // Q_LR [vUR][hL]
+        std::map<int, std::pair<double, double>> done;
+        for (size_t z : kv.second) {
+          const int k = slot[z - y];
+          if (!done.count(k)) {
+            R.run(2, (double)vUR * hL, 2.0 * R.eb * vUR * hL,
+                  [&] { launch_cdot(R.prec, ybuf(k), A, vUR * hL, R.d_part, R.st); });
+            hip_check(hipMemcpyAsync(part.data(), R.d_part, part.size() * 8, hipMemcpyDeviceToHost, R.st),
+                      "download");
+            hip_check(hipStreamSynchronize(R.st), "hipStreamSynchronize");
+            double re = 0, im = 0;
+            for (int t = 0; t < nblk; ++t) {
+              re += part[2 * t];
+              im += part[2 * t + 1];
+            }
+            done[k] = {re, im};
+          }
+          const size_t b = order[z];
+          const int64_t e = eY[k] + eLR;
+          out[2 * b] = std::ldexp(done[k].first, (int)e);
+          out[2 * b + 1] = std::ldexp(done[k].second, (int)e);
+        }
+      }
+      y = ye;
     }
-    out[2 * b] = std::ldexp(amp_re, (int)amp_e);
-    out[2 * b + 1] = std::ldexp(amp_im, (int)amp_e);
+    x = xe;
   }
+  R.collect(pl);
 }
 
 }  // namespace psim

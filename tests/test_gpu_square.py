@@ -72,8 +72,11 @@ def test_square_duplicates_and_order(ps):
     bits = np.concatenate([base, base[::-1], base[:2]])
     bits[3, 15] ^= 1                     # differs from base[3] in the lower-right quadrant only
     ref = sv.amplitudes(sv.run(c), bits)
-    a = ps.Plan(ps.Peps(c), prec="fp64", sweep=3).amplitudes(bits)
+    P = ps.Peps(c)
+    a = ps.Plan(P, prec="fp64", sweep=3).amplitudes(bits)            # one lower-left pattern per pass
     assert np.max(np.abs(a - ref)) <= 1e-12 * np.max(np.abs(ref))
+    a2 = ps.Plan(P, prec="fp64", sweep=3, max_batch=len(bits)).amplitudes(bits)   # several per pass
+    assert np.max(np.abs(a2 - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
 @pytest.mark.timeout(600)
@@ -85,7 +88,9 @@ def test_square_6x6_d40_vs_golden(ps, prec):
     assert c.sha256() == g["sha256"]
     bits = np.array(g["bits"], dtype=np.uint8)
     ref = np.array(g["amps_re"]) + 1j * np.array(g["amps_im"])
-    pl = ps.Plan(ps.Peps(c), prec=prec, sweep=3, mem_budget=(64 if prec != "fp64" else 120) << 30)
+    # FP32: two Y tensors fit the budget (both lower-left patterns in one pass); FP64: one per pass
+    pl = ps.Plan(ps.Peps(c), prec=prec, sweep=3, max_batch=len(bits),
+                 mem_budget=(64 if prec != "fp64" else 120) << 30)
     say(f"square 6x6 d40 {prec}: workspace {pl.stats()['workspace_bytes'] / 2**30:.1f} GiB")
     a = pl.amplitudes(bits)
     rel = np.abs(a - ref) / np.abs(ref)
