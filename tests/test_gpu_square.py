@@ -65,6 +65,17 @@ def test_square_6x6_d16_vs_oracle_and_row_scheme(ps):
     assert _eps_rms(a3, ref, 36).max() <= AMP_BAR["fp32_3m"]
 
 
+def test_square_general_gates(ps):
+    """Arbitrary one- and two-qubit gates (bond dimensions up to 4 per gate,
+    uneven bonds) through the square partition."""
+    c = rqcgen.generate_general(4, 4, 3, 7, "U2")
+    bits = rqcgen.bitstrings(4, 4, 7, 24)
+    ref = sv.amplitudes(sv.run(c), bits)
+    for prec, bar in (("fp64", 1e-10), ("fp32_3m", 1e-5)):
+        a = ps.Plan(ps.Peps(c), prec=prec, sweep=3, max_batch=len(bits)).amplitudes(bits)
+        assert _eps_rms(a, ref, 16).max() <= bar, prec
+
+
 def test_square_duplicates_and_order(ps):
     """Bitstrings in any order, with repeats, sharing some quadrants."""
     c = rqcgen.generate(4, 4, 16, 5)

@@ -221,3 +221,15 @@ def test_square_plan_errors(ps):
     with pytest.raises(ps.PsimError) as e:
         ps.Plan(P, prec="fp32", host_only=True, sweep=4)
     assert e.value.status == ps.PSIM_EINVAL
+
+
+def test_square_plan_memory_budget(ps):
+    P = ps.Peps(rqcgen.generate(6, 6, 40, 0))
+    with pytest.raises(ps.PsimError) as e:
+        ps.Plan(P, prec="fp32_3m", host_only=True, sweep=3, mem_budget=16 << 30)
+    assert e.value.status == ps.PSIM_ENOMEM and "bytes" in str(e.value)
+    one = ps.Plan(P, prec="fp32_3m", host_only=True, sweep=3, mem_budget=49 << 30).stats()
+    assert one["workspace_bytes"] <= 49 << 30
+    many = ps.Plan(P, prec="fp32_3m", host_only=True, sweep=3, mem_budget=97 << 30, max_batch=16).stats()
+    # extra Y tensors (8 GiB each) from what the budget leaves
+    assert many["workspace_bytes"] - one["workspace_bytes"] == 6 * (8 << 30)
