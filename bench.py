@@ -394,6 +394,11 @@ def small_configs_program(args):
     pl = ps.Plan(ps.Peps(c), prec=args.prec, max_batch=256, graph=True)
     t = timeit(lambda: pl.amplitudes(bits), 5)
     rows.append(("5x5 (1+32+1), 256 random bitstrings in one call", 256, pl.stats()["cmac_per_amplitude"] * 256, t))
+    if args.prec != "bf16x3":
+        sq = ps.Plan(ps.Peps(c), prec=args.prec, max_batch=256, sweep=3)
+        t = timeit(lambda: sq.amplitudes(bits), 5)
+        rows.append(("5x5 (1+32+1), 256 random bitstrings, square partition (eqs. S11-S12)", 256,
+                     sq.stats()["cmac_per_amplitude"] * 256, t))
     for name, n, cmac, t in rows:
         print(json.dumps({"workload": name, "prec": args.prec, "amplitudes": n, "seconds": t,
                           "amplitudes_per_s": n / t, "cmac": cmac,

@@ -81,8 +81,9 @@ typedef struct {
   uint64_t mem_budget_bytes;  /* device bytes the workspace may use; 0 = 200 GiB */
   int32_t max_batch;          /* most bitstrings per psim_amplitudes call; 0 = 1 */
   int32_t sweep;              /* 0 = along the short side (Fig. S2(a)), 1 = rows, 2 = columns,
-                                 3 = square partition (Fig. S2(b), eqs. S9-S10; L x L lattices with
-                                 L even, FP64 / FP32 4M / FP32 3M; not groupable, not tuned) */
+                                 3 = square partition (Fig. S2(b); eqs. S9-S10 for even and S11-S12
+                                 for odd L x L lattices, any lattice with both sides >= 2; FP64 /
+                                 FP32 4M / FP32 3M; not groupable, not tuned) */
   int32_t device;             /* HIP device ordinal */
   int32_t tile_cfg;           /* FP32 interior-site tile candidate: 0 = default, k > 0 = candidate k
                                  (4M: 1..5, 3M: 1..2); psim_tune may replace it */

@@ -197,7 +197,8 @@ psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o) {
       pl->lv = P->lv;
       pl->lh = P->lh;
       pl->sweep = 3;
-      pl->R = pl->L = P->lv;
+      pl->R = P->lv;
+      pl->L = P->lh;
       pl->host_only = (opts.flags & PSIM_PLAN_HOST_ONLY) != 0;
       pl->elem_bytes = opts.prec == PSIM_FP64 ? 16 : 8;
       pl->chi = 1;

@@ -1,32 +1,36 @@
-// Square partition of an L x L lattice, L even (supplement S-II, Fig. S2(b),
-// eqs. S9-S10).
+// Square partition (supplement S-II, Fig. S2(b); eqs. S9-S10 for an L x L
+// lattice with L even, S11-S12 for L odd), for any Lv x Lh lattice with both
+// sides at least 2.
 //
-// The lattice is cut into four h x h quadrants (h = L/2).  Each quadrant is
-// contracted on its own from its lattice corner inward; what is left open
-// are the bonds it shares with the two neighbouring quadrants: h horizontal
-// bonds of the middle vertical cut and h vertical bonds of the middle
-// horizontal cut.  The four quadrant tensors are then joined, each join
-// being one complex GEMM of size D^h x D^h x D^h (the leading term of eq.
-// S10):
+// The lattice is cut into four blocks ("quadrants") by the middle horizontal
+// cut (a = floor(Lv/2) rows above it) and the middle vertical cut (b =
+// floor(Lh/2) columns left of it).  Each quadrant is contracted on its own
+// from its lattice corner inward; what is left open are the bonds it shares
+// with the two neighbouring quadrants.  The four quadrant tensors are then
+// joined, each join being one complex GEMM (for L x L, L even, both joins are
+// D^(L/2) x D^(L/2) x D^(L/2): the leading term 2 D^(3L/2) of eq. S10; for L
+// odd the two joins are D^((L+1)/2) x D^((L-1)/2) x D^((L-1)/2) and
+// D^((L+1)/2) x D^((L-1)/2) x D^((L+1)/2), whose sum is eq. S12):
 //   T[vUR][vUL] = sum_hU   Q_UR[vUR][hU]  Q_UL[vUL][hU]
 //   Y[vUR][hL]  = sum_vUL  T[vUR][vUL]    Q_LL[hL][vUL]
 //   <tau|psi>   = sum      Y[vUR][hL]     Q_LR[vUR][hL].
 // Bitstrings that agree on the upper half share T, those that also agree on
 // the lower-left quadrant share Y (the reuse of the fast-sampling remark).
 //
-// Quadrant frames.  Quadrant q is walked in a frame (i, j), i, j < h, that
+// Quadrant frames.  Quadrant q (nr x nc sites) is walked in a frame (i, j)
+// that
 // starts at its lattice corner: rows are mirrored for the lower quadrants
 // (bottom-up) and columns for the right ones (right to left), with the legs
 // l/r and u/d swapped accordingly.  Frame row 0 lies on the lattice edge and
 // frame column 0 too, so their u and l legs have size 1; the frame-r legs of
-// column h-1 (o_i) and the frame-d legs of row h-1 stay open.
+// column nc-1 (o_i) and the frame-d legs of row nr-1 stay open.
 //
 // Leg order inside a quadrant.  Before frame row i the running tensor is
-//   [u_0 .. u_{h-1}][o_0 .. o_{i-1}]   (u_j = frame-d leg of site (i-1, j)),
+//   [u_0 .. u_{nc-1}][o_0 .. o_{i-1}]   (u_j = frame-d leg of site (i-1, j)),
 // and site j of the row is one GEMM of the row scheme's rotating layout,
 //   C[m][(d_j, r_j)] = sum_{u_j, r_{j-1}} A[u_j][m][r_{j-1}] W[(u_j, l_j)][(d_j, r_j)],
-// with m = [u_{j+1} .. u_{h-1}][o_0 .. o_{i-1}][d_0 .. d_{j-1}] untouched.
-// After the row the tensor is [o_0 .. o_{i-1}][d_0 .. d_{h-1}][o_i]; one
+// with m = [u_{j+1} .. u_{nc-1}][o_0 .. o_{i-1}][d_0 .. d_{j-1}] untouched.
+// After the row the tensor is [o_0 .. o_{i-1}][d_0 .. d_{nc-1}][o_i]; one
 // permute brings it to [d ...][o_0 .. o_i] for the next row.  The finished
 // quadrant is stored as [d ...][o ...] (UL, UR, LR) or [o ...][d ...] (LL),
 // the layouts the joins read (a quadrant tensor Q[n][k] is the packed W
@@ -55,13 +59,14 @@ struct SqSite {
 
 struct SqQuad {
   int mr = 0, mc = 0;          // mirrored rows / columns
-  std::vector<SqSite> s;       // frame (i, j) at i * h + j
+  int nr = 1, nc = 1;          // frame rows / columns
+  std::vector<SqSite> s;       // frame (i, j) at i * nc + j
   int64_t dv = 1, dh = 1;      // sizes of the open vertical-cut / horizontal-cut legs
   double cmac = 0;
 };
 
 struct SquarePlan {
-  int L = 0, h = 0;
+  int lv = 0, lh = 0;
   SqQuad q[4];                 // UL, UR, LL, LR
   int64_t tmax = 1;            // largest running tensor (complex elements)
   int64_t qmax = 1;            // largest quadrant / joined tensor
@@ -94,15 +99,16 @@ struct Shape {
   int64_t M, K1, K2, N;
 };
 
-Shape site_shape(const SqQuad& Q, int h, int i, int j) {
-  auto at = [&](int a, int b) -> const SqSite& { return Q.s[(size_t)a * h + b]; };
+Shape site_shape(const SqQuad& Q, int i, int j) {
+  const int nc = Q.nc;
+  auto at = [&](int a, int b) -> const SqSite& { return Q.s[(size_t)a * nc + b]; };
   Shape sh;
   sh.K1 = at(i, j).du;
   sh.K2 = at(i, j).dl;
   sh.N = (int64_t)at(i, j).dd * at(i, j).dr;
   int64_t M = 1;
-  for (int jj = j + 1; jj < h; ++jj) M *= at(i, jj).du;
-  for (int k = 0; k < i; ++k) M *= at(k, h - 1).dr;
+  for (int jj = j + 1; jj < nc; ++jj) M *= at(i, jj).du;
+  for (int k = 0; k < i; ++k) M *= at(k, nc - 1).dr;
   for (int jj = 0; jj < j; ++jj) M *= at(i, jj).dd;
   sh.M = M;
   return sh;
@@ -111,36 +117,39 @@ Shape site_shape(const SqQuad& Q, int h, int i, int j) {
 }  // namespace
 
 void make_square_plan(psim_plan_t* pl, const psim_peps_t& P) {
-  const int L = P.lv;
-  if (P.lv != P.lh || L < 2 || L % 2) fail(PSIM_EUNSUPPORTED, "the square partition needs an L x L lattice with L even");
+  const int Lv = P.lv, Lh = P.lh;
+  if (Lv < 2 || Lh < 2) fail(PSIM_EUNSUPPORTED, "the square partition needs at least 2 rows and 2 columns");
   const int prec = pl->opts.prec;
   if (prec == PSIM_BF16X3) fail(PSIM_EUNSUPPORTED, "the square partition runs in FP64, FP32 4M or FP32 3M");
   auto sq = std::make_shared<SquarePlan>();
-  const int h = L / 2;
-  sq->L = L;
-  sq->h = h;
+  sq->lv = Lv;
+  sq->lh = Lh;
+  const int a = Lv / 2, b = Lh / 2;  // rows above / columns left of the cuts
   const int mirror[4][2] = {{0, 0}, {0, 1}, {1, 0}, {1, 1}};
   for (int qi = 0; qi < 4; ++qi) {
     SqQuad& Q = sq->q[qi];
     Q.mr = mirror[qi][0];
     Q.mc = mirror[qi][1];
-    Q.s.resize((size_t)h * h);
-    for (int i = 0; i < h; ++i)
-      for (int j = 0; j < h; ++j) {
-        const int r = Q.mr ? L - 1 - i : i, c = Q.mc ? L - 1 - j : j;
-        SqSite& st = Q.s[(size_t)i * h + j];
-        st.qubit = r * L + c;
+    Q.nr = Q.mr ? Lv - a : a;
+    Q.nc = Q.mc ? Lh - b : b;
+    const int nr = Q.nr, nc = Q.nc;
+    Q.s.resize((size_t)nr * nc);
+    for (int i = 0; i < nr; ++i)
+      for (int j = 0; j < nc; ++j) {
+        const int r = Q.mr ? Lv - 1 - i : i, c = Q.mc ? Lh - 1 - j : j;
+        SqSite& st = Q.s[(size_t)i * nc + j];
+        st.qubit = r * Lh + c;
         const Site& s = P.sites[st.qubit];
         st.dl = Q.mc ? s.dr : s.dl;
         st.dr = Q.mc ? s.dl : s.dr;
         st.du = Q.mr ? s.dd : s.du;
         st.dd = Q.mr ? s.du : s.dd;
       }
-    for (int j = 0; j < h; ++j) Q.dv *= Q.s[(size_t)(h - 1) * h + j].dd;
-    for (int i = 0; i < h; ++i) Q.dh *= Q.s[(size_t)i * h + h - 1].dr;
-    for (int i = 0; i < h; ++i)
-      for (int j = 0; j < h; ++j) {
-        const Shape sh = site_shape(Q, h, i, j);
+    for (int j = 0; j < nc; ++j) Q.dv *= Q.s[(size_t)(nr - 1) * nc + j].dd;
+    for (int i = 0; i < nr; ++i) Q.dh *= Q.s[(size_t)i * nc + nc - 1].dr;
+    for (int i = 0; i < nr; ++i)
+      for (int j = 0; j < nc; ++j) {
+        const Shape sh = site_shape(Q, i, j);
         Q.cmac += (double)sh.M * sh.K1 * sh.K2 * sh.N;
         sq->tmax = std::max({sq->tmax, sh.M * sh.K1 * sh.K2, sh.M * sh.N});
         ++sq->n_steps;
@@ -293,17 +302,17 @@ struct SqRun {
   // Contract quadrant qi for bits into dst; returns its exponent.
   int64_t quad(int qi, const uint8_t* bits, char* dst) {
     const SqQuad& Q = sq->q[qi];
-    const int h = sq->h;
+    const int nr = Q.nr, nc = Q.nc;
     char* cur = buf(sq->off_w1);
     char* nxt = buf(sq->off_w2);
     int64_t e = 0;
     int64_t cur_elems = 1;
-    for (int i = 0; i < h; ++i) {
-      for (int j = 0; j < h; ++j) {
-        const SqSite& st_ = Q.s[(size_t)i * h + j];
+    for (int i = 0; i < nr; ++i) {
+      for (int j = 0; j < nc; ++j) {
+        const SqSite& st_ = Q.s[(size_t)i * nc + j];
         const int tau = bits[st_.qubit];
         const DevMatrix& w = st_.w[tau];
-        const Shape sh = site_shape(Q, h, i, j);
+        const Shape sh = site_shape(Q, i, j);
         GemmLaunch g;
         g.prec = prec;
         g.A = (i == 0 && j == 0) ? pl->d_ones : (const void*)cur;
@@ -327,10 +336,10 @@ struct SqRun {
       e += rescale(cur, cur_elems);
       // [o_0 .. o_{i-1}][d_0 .. d_{h-1}][o_i] -> next layout
       int64_t X = 1, Y = 1;
-      for (int k = 0; k < i; ++k) X *= Q.s[(size_t)k * h + h - 1].dr;
-      for (int j = 0; j < h; ++j) Y *= Q.s[(size_t)i * h + j].dd;
-      const int64_t Z = Q.s[(size_t)i * h + h - 1].dr;
-      if (i + 1 < h) {
+      for (int k = 0; k < i; ++k) X *= Q.s[(size_t)k * nc + nc - 1].dr;
+      for (int j = 0; j < nc; ++j) Y *= Q.s[(size_t)i * nc + j].dd;
+      const int64_t Z = Q.s[(size_t)i * nc + nc - 1].dr;
+      if (i + 1 < nr) {
         if (X > 1) {
           run(2, 0, 2.0 * eb * X * Y * Z, [&] { launch_permute3(prec, cur, nxt, X, Y, Z, 0, st); });
           std::swap(cur, nxt);
@@ -368,7 +377,7 @@ struct SqRun {
 
 void run_square(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, void* stream, double* out) {
   const SquarePlan* sq = pl->sq.get();
-  const int L = sq->L, h = sq->h, nq = L * L;
+  const int nq = sq->lv * sq->lh;
   hip_check(hipSetDevice(pl->opts.device), "hipSetDevice");
   SqRun R;
   R.pl = pl;
@@ -386,27 +395,22 @@ void run_square(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, void* 
   static const int32_t zero = 0;
   hip_check(hipMemcpyAsync(R.d_zero, &zero, 4, hipMemcpyHostToDevice, R.st), "upload zero");
 
-  // quadrant keys: the bits of its sites in frame order
-  auto key = [&](size_t b, int qi) {
-    std::vector<uint8_t> k((size_t)h * h);
-    for (size_t x = 0; x < k.size(); ++x) k[x] = bits[b * nq + sq->q[qi].s[x].qubit];
-    return k;
-  };
+  // key of a bitstring: the bits of UL, UR, LL, LR sites in frame order;
+  // koff[q] = where quadrant q's bits start
+  size_t koff[5] = {0, 0, 0, 0, 0};
+  for (int qi = 0; qi < 4; ++qi) koff[qi + 1] = koff[qi] + sq->q[qi].s.size();
   std::vector<size_t> order(n);
   for (size_t b = 0; b < n; ++b) order[b] = b;
   std::vector<std::vector<uint8_t>> keys(n);
   for (size_t b = 0; b < n; ++b) {
-    std::vector<uint8_t> k;
-    for (int qi = 0; qi < 4; ++qi) {
-      auto kq = key(b, qi);
-      k.insert(k.end(), kq.begin(), kq.end());
-    }
-    keys[b] = k;
+    std::vector<uint8_t>& k = keys[b];
+    k.reserve(koff[4]);
+    for (int qi = 0; qi < 4; ++qi)
+      for (const SqSite& st_ : sq->q[qi].s) k.push_back(bits[b * nq + st_.qubit]);
   }
   std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return keys[x] < keys[y]; });
-  const size_t qk = (size_t)h * h;
   auto same = [&](size_t x, size_t y, int upto) {  // keys agree on quadrants 0 .. upto-1
-    return std::equal(keys[x].begin(), keys[x].begin() + qk * upto, keys[y].begin());
+    return std::equal(keys[x].begin(), keys[x].begin() + koff[upto], keys[y].begin());
   };
 
   const int64_t vUL = sq->q[0].dv, vUR = sq->q[1].dv, hU = sq->q[0].dh, hL = sq->q[2].dh;
@@ -449,7 +453,7 @@ void run_square(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, void* 
       // each lower-right pattern of the pass once, dotted with the Y's that need it
       std::map<std::vector<uint8_t>, std::vector<size_t>> lr;
       for (size_t z = y; z < ye; ++z)
-        lr[std::vector<uint8_t>(keys[order[z]].begin() + 3 * qk, keys[order[z]].end())].push_back(z);
+        lr[std::vector<uint8_t>(keys[order[z]].begin() + koff[3], keys[order[z]].end())].push_back(z);
       for (auto& kv : lr) {
         const uint8_t* bb = bits + order[kv.second.front()] * nq;
         const int64_t eLR = R.quad(3, bb, A);   // Q_LR [vUR][hL]

@@ -52,6 +52,34 @@ def test_square_small_vs_state_vector(ps, prec, L, d, seed, nb):
     assert e.max() <= AMP_BAR[prec]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32_3m"])
+@pytest.mark.parametrize("lv,lh,d,seed", [(3, 3, 8, 0), (3, 5, 16, 1), (5, 4, 16, 2), (2, 6, 13, 3)])
+def test_square_odd_and_rectangular_vs_state_vector(ps, prec, lv, lh, d, seed):
+    """Uneven quadrants: odd sides (eqs. S11-S12) and rectangular lattices."""
+    c = rqcgen.generate(lv, lh, d, seed)
+    bits = rqcgen.all_bitstrings(9) if lv * lh == 9 else rqcgen.bitstrings(lv, lh, seed, 40)
+    ref = sv.amplitudes(sv.run(c), bits)
+    a = ps.Plan(ps.Peps(c), prec=prec, sweep=3, max_batch=len(bits)).amplitudes(bits)
+    e = _eps_rms(a, ref, lv * lh)
+    say(f"square {lv}x{lh} d{d} {prec}: max eps_rms {e.max():.2e}")
+    assert e.max() <= AMP_BAR[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_3m"])
+def test_square_5x5_d32_golden(ps, prec):
+    """5x5 (1+32+1), 256 bitstrings: the odd partition against the state vector."""
+    with open(os.path.join(HERE, "golden", "rqc_5x5_d32_s0.json")) as f:
+        g = json.load(f)
+    c = rqcgen.generate(5, 5, 32, 0)
+    assert c.sha256() == g["sha256"]
+    bits = np.array(g["bits"], dtype=np.uint8)
+    ref = np.array(g["amps_re"]) + 1j * np.array(g["amps_im"])
+    a = ps.Plan(ps.Peps(c), prec=prec, sweep=3, max_batch=len(bits)).amplitudes(bits)
+    e = _eps_rms(a, ref, 25)
+    say(f"square 5x5 d32 {prec}: max eps_rms {e.max():.2e}")
+    assert e.max() <= AMP_BAR[prec]
+
+
 def test_square_6x6_d16_vs_oracle_and_row_scheme(ps):
     c = rqcgen.generate(6, 6, 16, 3)
     bits = rqcgen.bitstrings(6, 6, 3, 12)

@@ -147,12 +147,14 @@ def test_bench_kernel_sections_exist():
     assert len(set(hs.values())) == len(hs) and all(len(h) == 64 for h in hs.values())
 
 
-def _square_cmac_from_oracle(L, dims):
+def _square_cmac_from_oracle(lv, lh, dims):
     """Independent count of the square partition's multiply-adds from the
-    oracle's bond dimensions: every quadrant absorbs its sites row by row from
-    its lattice corner (each absorption costs |running tensor after| times
-    the two contracted bond sizes), then two joins and one inner product."""
-    h = L // 2
+    oracle's bond dimensions: the cuts leave a = lv // 2 rows above and
+    b = lh // 2 columns to the left; every quadrant absorbs its sites row by
+    row from its lattice corner (each absorption costs |running tensor after|
+    times the two contracted bond sizes), then two joins and one inner
+    product."""
+    a, b = lv // 2, lh // 2
 
     def bond(kind, r, c):
         return dims.get((kind, r, c), 1)
@@ -161,35 +163,37 @@ def _square_cmac_from_oracle(L, dims):
     cuts = {}
     for mr in (0, 1):
         for mc in (0, 1):
+            nr = lv - a if mr else a
+            nc = lh - b if mc else b
+
             def site(i, j):
-                r = L - 1 - i if mr else i
-                c = L - 1 - j if mc else j
+                r = lv - 1 - i if mr else i
+                c = lh - 1 - j if mc else j
                 left = bond("h", r, c - 1) if c > 0 else 1
-                right = bond("h", r, c) if c < L - 1 else 1
+                right = bond("h", r, c) if c < lh - 1 else 1
                 up = bond("v", r - 1, c) if r > 0 else 1
-                down = bond("v", r, c) if r < L - 1 else 1
+                down = bond("v", r, c) if r < lv - 1 else 1
                 if mc:
                     left, right = right, left
                 if mr:
                     up, down = down, up
                 return left, right, up, down
-            for i in range(h):
-                for j in range(h):
-                    # open legs of the running tensor after absorbing (i, j)
+            for i in range(nr):
+                for j in range(nc):
                     after = 1
-                    for jj in range(h):
+                    for jj in range(nc):
                         after *= site(i, jj)[3] if jj <= j else site(i, jj)[2]
                     for k in range(i):
-                        after *= site(k, h - 1)[1]
+                        after *= site(k, nc - 1)[1]
                     after *= site(i, j)[1]
                     l, _, u, _ = site(i, j)
                     total += after * l * u
             dv = 1
-            for j in range(h):
-                dv *= site(h - 1, j)[3]
+            for j in range(nc):
+                dv *= site(nr - 1, j)[3]
             dh = 1
-            for i in range(h):
-                dh *= site(i, h - 1)[1]
+            for i in range(nr):
+                dh *= site(i, nc - 1)[1]
             cuts[(mr, mc)] = (dv, dh)
     vUL, hU = cuts[(0, 0)]
     vUR, _ = cuts[(0, 1)]
@@ -197,23 +201,29 @@ def _square_cmac_from_oracle(L, dims):
     return total + vUR * hU * vUL + vUR * vUL * hL + vUR * hL
 
 
-@pytest.mark.parametrize("L,d", [(2, 8), (4, 16), (4, 13), (6, 16), (6, 40)])
-def test_square_plan_count_matches_oracle(ps, L, d):
-    c = rqcgen.generate(L, L, d, 0)
+@pytest.mark.parametrize("lv,lh,d", [(2, 2, 8), (4, 4, 16), (4, 4, 13), (6, 6, 16), (6, 6, 40), (3, 3, 8),
+                                     (5, 5, 32), (4, 5, 24), (3, 6, 16), (5, 4, 16)])
+def test_square_plan_count_matches_oracle(ps, lv, lh, d):
+    c = rqcgen.generate(lv, lh, d, 0)
     s = ps.Plan(ps.Peps(c), prec="fp32_3m", host_only=True, sweep=3, mem_budget=1 << 62).stats()
     dims = opeps.bond_dims(opeps.build(c))
-    assert s["cmac_per_amplitude"] == _square_cmac_from_oracle(L, dims)
-    assert s["sweep"] == 3 and s["n_gemm_steps"] == L * L + 2
-    if d == 40:
+    assert s["cmac_per_amplitude"] == _square_cmac_from_oracle(lv, lh, dims)
+    assert s["sweep"] == 3 and s["n_gemm_steps"] == lv * lh + 2
+    if lv == lh == 6 and d == 40:
         # leading term: eq. (S10), 2 D^(3L/2) (quadrant costs add the rest)
-        assert 1.0 <= s["cmac_per_amplitude"] / cx.even_square_time(L, d) < 1.2
+        assert 1.0 <= s["cmac_per_amplitude"] / cx.even_square_time(6, 40) < 1.2
+    if lv == lh == 5 and d == 32:
+        # odd L: the two joins are exactly eq. (S12), (D + 1) D^((3L-1)/2)
+        D = 16
+        joins = D ** 7 + D ** 8 + D ** 6        # T, Y and the inner product
+        assert joins - D ** 6 == cx.odd_square_time(5, 32)
+        assert s["cmac_per_amplitude"] > joins
 
 
 def test_square_plan_errors(ps):
-    for lv, lh in ((3, 3), (4, 6)):
-        with pytest.raises(ps.PsimError) as e:
-            ps.Plan(ps.Peps(rqcgen.generate(lv, lh, 8, 0)), prec="fp32", host_only=True, sweep=3)
-        assert e.value.status == ps.PSIM_EUNSUPPORTED
+    with pytest.raises(ps.PsimError) as e:
+        ps.Plan(ps.Peps(rqcgen.generate(1, 4, 8, 0)), prec="fp32", host_only=True, sweep=3)
+    assert e.value.status == ps.PSIM_EUNSUPPORTED
     P = ps.Peps(rqcgen.generate(4, 4, 8, 0))
     with pytest.raises(ps.PsimError) as e:
         ps.Plan(P, prec="bf16x3", host_only=True, sweep=3)
