@@ -253,7 +253,7 @@ def fig2_program(args):
     bits = rqcgen.bitstrings(8, 8, 7, n)
     peps = ps.Peps(c)
     chunk = 512
-    plan = ps.Plan(peps, prec=args.prec, max_batch=chunk, mem_budget=args.mem_gib << 30)
+    plan = ps.Plan(peps, prec=args.prec, max_batch=chunk, mem_budget=args.mem_gib << 30, sweep=args.sweep)
     plan.workspace()
     plan.amplitudes(bits[:16])
     torch.cuda.synchronize()
@@ -271,6 +271,7 @@ def fig2_program(args):
     hist, _ = np.histogram(np.log(x), bins=edges, density=True)
     mids = 0.5 * (edges[1:] + edges[:-1])
     print(json.dumps({"workload": f"8x8 (1+25+1), seed 0, {n} random bitstrings", "prec": args.prec,
+                      "scheme": "square partition" if args.sweep == 3 else "row scheme",
                       "seconds": t, "s_per_amplitude": t / n, "cmac_per_amplitude": plan.stats()["cmac_per_amplitude"],
                       "porter_thomas": summ,
                       "log_histogram": [[round(float(m), 3), round(float(h), 4), round(float(stats.log_pt_density(m)), 4)]
@@ -426,6 +427,7 @@ def main():
     ap.add_argument("--counters", action="store_true", help="short program for rocprofv3 --pmc passes")
     ap.add_argument("--fig2", action="store_true", help="8x8 (1+25+1) Porter-Thomas experiment")
     ap.add_argument("--fig2-count", type=int, default=2048)
+    ap.add_argument("--sweep", type=int, default=0, help="--fig2: 0 row scheme, 3 square partition")
     ap.add_argument("--mixed", action="store_true", help="mixed batches of 3x3..6x6 circuits, grouped vs per plan")
     ap.add_argument("--small-configs", action="store_true", help="3x3, 4x5 and 5x5 parity workloads, timed")
     args = ap.parse_args()
