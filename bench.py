@@ -424,6 +424,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-square", dest="square", action="store_false",
                     help="skip timing the square partition on the same batch")
+    ap.add_argument("--square-only", action="store_true",
+                    help="only the square partition on the 6x6 batch (for profiling)")
     ap.add_argument("--counters", action="store_true", help="short program for rocprofv3 --pmc passes")
     ap.add_argument("--fig2", action="store_true", help="8x8 (1+25+1) Porter-Thomas experiment")
     ap.add_argument("--fig2-count", type=int, default=2048)
@@ -455,6 +457,11 @@ def main():
     import torch
     torch.cuda.set_device(0)
     circuit, bits = workload(args.lattice, args.depth)
+    if args.square_only:
+        print(json.dumps({"workload": f"{args.lattice}x{args.lattice} (1+{args.depth}+1), {len(bits)} bitstrings",
+                          "prec": args.prec, "square_partition": square_leg(args, circuit, bits, float("nan"))}),
+              flush=True)
+        return
     log(f"workload {args.lattice}x{args.lattice} (1+{args.depth}+1), {len(bits)} bitstrings, {args.prec}")
     amps, elapsed, prof, stats = run_gpu(args, args.prec, circuit, bits)
     n_amp = args.steps * len(bits)

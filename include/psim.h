@@ -166,7 +166,8 @@ psim_status psim_contract_site(int32_t prec, int64_t batch, int64_t M, int64_t K
  * caller's workspace (>= psim_plan_stats.workspace_bytes, contents are
  * overwritten), and keep the fastest for psim_amplitudes.  best_ms
  * (nullable) receives the chosen time of the costliest shape.  Plans in other
- * precisions keep their single kernel configuration (PSIM_OK, nothing timed).
+ * precisions and square-partition plans keep their single kernel
+ * configuration (PSIM_OK, nothing timed).
  * Errors: EINVAL for a short workspace or reps < 1, EDEVICE. */
 psim_status psim_tune(psim_plan_t *plan, void *d_workspace, size_t workspace_bytes, void *hip_stream,
                       int32_t reps, double *best_ms);
