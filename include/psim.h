@@ -83,7 +83,10 @@ typedef struct {
   int32_t sweep;              /* 0 = along the short side (Fig. S2(a)), 1 = rows, 2 = columns,
                                  3 = square partition (Fig. S2(b); eqs. S9-S10 for even and S11-S12
                                  for odd L x L lattices, any lattice with both sides >= 2; FP64 /
-                                 FP32 4M / FP32 3M; not groupable, not tuned) */
+                                 FP32 4M / FP32 3M; not groupable, not tuned).  When the budget
+                                 holds the tensors of at least 8 bitstrings, the workspace is sized
+                                 for chunks of up to min(32, max_batch) bitstrings contracted
+                                 together; otherwise bitstrings go one by one (same results) */
   int32_t device;             /* HIP device ordinal */
   int32_t tile_cfg;           /* FP32 interior-site tile candidate: 0 = default, k > 0 = candidate k
                                  (4M: 1..5, 3M: 1..2); psim_tune may replace it */

@@ -1130,11 +1130,14 @@ __global__ void copy_segments(const CopySeg* __restrict__ segs) {
 // ---------------------------------------------------------------- square partition helpers
 // Three-index permutes of a complex tensor in[X][Y][Z] (E = float2 or
 // double2, one complex element): mode 0 writes out[Y][X][Z], mode 1
-// out[X][Z][Y].  One thread per output element.
+// out[X][Z][Y].  One thread per output element; blockIdx.y = node, nodes
+// X*Y*Z elements apart in both tensors.
 template <typename E>
 __global__ void permute3(const E* __restrict__ in, E* __restrict__ out, long long X, long long Y, long long Z,
                          int mode) {
   const long long total = X * Y * Z;
+  in += blockIdx.y * total;
+  out += blockIdx.y * total;
   for (long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x; o < total;
        o += (long long)gridDim.x * blockDim.x) {
     long long x, y, z;
@@ -1157,10 +1160,13 @@ __global__ void permute3(const E* __restrict__ in, E* __restrict__ out, long lon
 // of the site kernels for W[k][n] = Q[n][k], zero padded to rows x ld:
 // 3M: P[n][2k + c] = component c of Q[n][k]; 4M (float or double): the real
 // expansion P[2n + a][2k + b] = [[Re, -Im], [Im, Re]][a][b] of Q[n][k].
+// blockIdx.y = node: N*K complex elements apart in Q, rows*ld reals in P.
 template <typename T>
 __global__ void pack_w(const T* __restrict__ Q, T* __restrict__ P, long long N, long long K, long long rows,
                        long long ld, int three_m) {
   const long long total = rows * ld;
+  Q += blockIdx.y * 2 * N * K;
+  P += blockIdx.y * total;
   for (long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x; o < total;
        o += (long long)gridDim.x * blockDim.x) {
     const long long row = o / ld, c = o - row * ld;
@@ -1201,6 +1207,32 @@ __global__ __launch_bounds__(256) void cdot_partial(const T* __restrict__ a, con
   if (threadIdx.x == 0) {
     part[2 * blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
     part[2 * blockIdx.x + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
+}
+
+// Sum of the nblk (re, im) partials of cdot_partial into out[0..1], in a
+// fixed order (one workgroup: strided per-thread sums, then a tree).
+__global__ __launch_bounds__(256) void cdot_finish(const double* __restrict__ part, int nblk,
+                                                   double* __restrict__ out) {
+  __shared__ double red[2][256];
+  double re = 0, im = 0;
+  for (int t = threadIdx.x; t < nblk; t += 256) {
+    re += part[2 * t];
+    im += part[2 * t + 1];
+  }
+  red[0][threadIdx.x] = re;
+  red[1][threadIdx.x] = im;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + h];
+      red[1][threadIdx.x] += red[1][threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = red[0][0];
+    out[1] = red[1][0];
   }
 }
 
@@ -1548,34 +1580,40 @@ static unsigned grid_for(long long total) {
   return (unsigned)std::max<long long>(1, std::min<long long>((total + 255) / 256, 1 << 20));
 }
 
-void launch_permute3(int prec, const void* in, void* out, int64_t X, int64_t Y, int64_t Z, int mode, void* stream) {
-  if (X < 1 || Y < 1 || Z < 1 || (mode != 0 && mode != 1)) fail(PSIM_EINTERNAL, "permute3: bad arguments");
+void launch_permute3(int prec, const void* in, void* out, int64_t X, int64_t Y, int64_t Z, int mode, void* stream,
+                     int64_t nodes) {
+  if (X < 1 || Y < 1 || Z < 1 || (mode != 0 && mode != 1) || nodes < 1 || nodes > 65535)
+    fail(PSIM_EINTERNAL, "permute3: bad arguments");
   hipStream_t st = (hipStream_t)stream;
   const long long total = X * Y * Z;
+  const dim3 grid(grid_for(total), (unsigned)nodes);
   if (prec == PSIM_FP64)
-    hipLaunchKernelGGL(permute3<double2>, dim3(grid_for(total)), dim3(256), 0, st, (const double2*)in, (double2*)out,
-                       (long long)X, (long long)Y, (long long)Z, mode);
+    hipLaunchKernelGGL(permute3<double2>, grid, dim3(256), 0, st, (const double2*)in, (double2*)out, (long long)X,
+                       (long long)Y, (long long)Z, mode);
   else
-    hipLaunchKernelGGL(permute3<float2>, dim3(grid_for(total)), dim3(256), 0, st, (const float2*)in, (float2*)out,
-                       (long long)X, (long long)Y, (long long)Z, mode);
+    hipLaunchKernelGGL(permute3<float2>, grid, dim3(256), 0, st, (const float2*)in, (float2*)out, (long long)X,
+                       (long long)Y, (long long)Z, mode);
   hip_check(hipGetLastError(), "permute3 launch");
 }
 
-void launch_pack_w(int prec, const void* Q, void* P, int64_t N, int64_t K, int64_t rows, int64_t ld, void* stream) {
+void launch_pack_w(int prec, const void* Q, void* P, int64_t N, int64_t K, int64_t rows, int64_t ld, void* stream,
+                   int64_t nodes) {
+  if (nodes < 1 || nodes > 65535) fail(PSIM_EINTERNAL, "pack_w: bad node count");
   hipStream_t st = (hipStream_t)stream;
   const long long total = rows * ld;
+  const dim3 grid(grid_for(total), (unsigned)nodes);
   if (prec == PSIM_FP64)
-    hipLaunchKernelGGL(pack_w<double>, dim3(grid_for(total)), dim3(256), 0, st, (const double*)Q, (double*)P,
-                       (long long)N, (long long)K, (long long)rows, (long long)ld, 0);
+    hipLaunchKernelGGL(pack_w<double>, grid, dim3(256), 0, st, (const double*)Q, (double*)P, (long long)N,
+                       (long long)K, (long long)rows, (long long)ld, 0);
   else
-    hipLaunchKernelGGL(pack_w<float>, dim3(grid_for(total)), dim3(256), 0, st, (const float*)Q, (float*)P,
-                       (long long)N, (long long)K, (long long)rows, (long long)ld, prec == PSIM_FP32_3M ? 1 : 0);
+    hipLaunchKernelGGL(pack_w<float>, grid, dim3(256), 0, st, (const float*)Q, (float*)P, (long long)N, (long long)K,
+                       (long long)rows, (long long)ld, prec == PSIM_FP32_3M ? 1 : 0);
   hip_check(hipGetLastError(), "pack_w launch");
 }
 
 int cdot_blocks() { return 1024; }
 
-void launch_cdot(int prec, const void* a, const void* b, int64_t n, double* part, void* stream) {
+void launch_cdot(int prec, const void* a, const void* b, int64_t n, double* part, double* out, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   if (prec == PSIM_FP64)
     hipLaunchKernelGGL(cdot_partial<double>, dim3(cdot_blocks()), dim3(256), 0, st, (const double*)a, (const double*)b,
@@ -1583,6 +1621,7 @@ void launch_cdot(int prec, const void* a, const void* b, int64_t n, double* part
   else
     hipLaunchKernelGGL(cdot_partial<float>, dim3(cdot_blocks()), dim3(256), 0, st, (const float*)a, (const float*)b,
                        (long long)n, part);
+  hipLaunchKernelGGL(cdot_finish, dim3(1), dim3(256), 0, st, (const double*)part, cdot_blocks(), out);
   hip_check(hipGetLastError(), "cdot launch");
 }
 

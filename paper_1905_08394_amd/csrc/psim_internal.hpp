@@ -208,16 +208,21 @@ struct CopySeg {
   int64_t bytes;
 };
 void launch_copy_segments(const CopySeg* d_segs, int n, int64_t max_bytes, void* stream);
-// square partition: complex in[X][Y][Z] -> out[Y][X][Z] (mode 0) or out[X][Z][Y] (mode 1)
-void launch_permute3(int prec, const void* in, void* out, int64_t X, int64_t Y, int64_t Z, int mode, void* stream);
-// device Q[n][k] (N x K complex) -> packed W operand for W[k][n] = Q[n][k] (rows x ld, zero padded)
-void launch_pack_w(int prec, const void* Q, void* P, int64_t N, int64_t K, int64_t rows, int64_t ld, void* stream);
-// sum_i a[i] b[i] over n complex elements: cdot_blocks() (re, im) partial sums in FP64
+// square partition: complex in[X][Y][Z] -> out[Y][X][Z] (mode 0) or out[X][Z][Y]
+// (mode 1), for `nodes` tensors X*Y*Z elements apart
+void launch_permute3(int prec, const void* in, void* out, int64_t X, int64_t Y, int64_t Z, int mode, void* stream,
+                     int64_t nodes = 1);
+// device Q[n][k] (N x K complex) -> packed W operand for W[k][n] = Q[n][k]
+// (rows x ld, zero padded), for `nodes` matrices N*K complex / rows*ld reals apart
+void launch_pack_w(int prec, const void* Q, void* P, int64_t N, int64_t K, int64_t rows, int64_t ld, void* stream,
+                   int64_t nodes = 1);
+// sum_i a[i] b[i] over n complex elements in FP64: cdot_blocks() (re, im)
+// partial sums in part, their sum in out[0..1]
 int cdot_blocks();
 // square.cpp
 void make_square_plan(psim_plan_t* pl, const psim_peps_t& P);
 void run_square(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, void* stream, double* out);
-void launch_cdot(int prec, const void* a, const void* b, int64_t n, double* part, void* stream);
+void launch_cdot(int prec, const void* a, const void* b, int64_t n, double* part, double* out, void* stream);
 bool rescale_fusable(int64_t per_node);
 int max_scale_group();
 void launch_rescale_group(int prec, const RescaleJob* jobs, int n, void* stream);

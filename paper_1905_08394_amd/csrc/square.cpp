@@ -37,9 +37,13 @@
 // operand of W[k][n] = Q[n][k]).
 //
 // Every tensor is rescaled by an exact power of two after each row and each
-// join; the exponents are summed on the host in FP64 with the site-matrix
+// join.  The exponents stay on the device (one slot per rescale) with the
+// inner products (one slot per amplitude) until a flush downloads them all at
+// once, so the host does not wait on the stream between launches; each
+// amplitude's exponent is then summed on the host with the site-matrix
 // exponents.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -50,6 +54,14 @@
 #include "psim_internal.hpp"
 
 namespace psim {
+
+// device slots for rescale exponents and inner products between flushes
+constexpr int64_t kSqExpSlots = 8192;
+constexpr int64_t kSqDotSlots = 1024;
+// batched form: at most this many bitstrings per chunk, and used only when
+// the budget holds at least kSqMinChunk
+constexpr int64_t kSqChunk = 32;
+constexpr int64_t kSqMinChunk = 8;
 
 struct SqSite {
   int qubit = 0;
@@ -73,6 +85,13 @@ struct SquarePlan {
   int64_t prow[2] = {0, 0}, pld[2] = {0, 0};  // packed operands of the two joins
   uint64_t off_w1 = 0, off_w2 = 0, off_a = 0, off_b = 0, off_c = 0, off_p = 0, off_small = 0, off_y = 0;
   int ycap = 1;                // Y tensors held at once (lower-left patterns joined per pass)
+  // batched form (chunk > 0): the bitstrings of a chunk have every quadrant
+  // pattern contracted in one set of launches (the pattern is the node
+  // index), each join per pattern pair; buffers [node][elements] with
+  // exact node strides
+  int64_t chunk = 0;
+  uint64_t boff_run[2] = {0, 0}, boff_q[4] = {0, 0, 0, 0}, boff_t = 0, boff_y = 0, boff_pk[2] = {0, 0};
+  uint64_t boff_tau = 0, boff_zeros = 0, boff_mx = 0;
   double cmac_quads = 0, cmac_joins = 0;
   int64_t n_steps = 0;
   ~SquarePlan() {
@@ -182,7 +201,7 @@ void make_square_plan(psim_plan_t* pl, const psim_peps_t& P) {
   sq->off_p = off;
   off += al((uint64_t)std::max(sq->prow[0] * sq->pld[0], sq->prow[1] * sq->pld[1]) * rb);
   sq->off_small = off;
-  off += al(16 + (uint64_t)cdot_blocks() * 16);
+  off += al(16 + (uint64_t)cdot_blocks() * 16 + (uint64_t)kSqExpSlots * 4 + (uint64_t)kSqDotSlots * 16);
   // more Y tensors (one per lower-left pattern of a pass) from what the
   // budget leaves, so each lower-right quadrant is contracted once per pass
   sq->off_y = off;
@@ -192,7 +211,41 @@ void make_square_plan(psim_plan_t* pl, const psim_peps_t& P) {
   extra = std::min<uint64_t>({extra, 15, (uint64_t)std::max(pl->opts.max_batch, 1) - 1});
   sq->ycap = 1 + (int)extra;
   off += extra * ysz;
-  pl->ws_total = off + 256;
+  const uint64_t seq_total = off + 256;
+
+  // batched form, when the budget holds a chunk of at least kSqMinChunk
+  {
+    const int64_t sq_[4] = {sq->q[0].dv * sq->q[0].dh, sq->q[1].dv * sq->q[1].dh, sq->q[2].dv * sq->q[2].dh,
+                            sq->q[3].dv * sq->q[3].dh};
+    const uint64_t per = eb * (2 * (uint64_t)sq->tmax + sq_[0] + sq_[1] + sq_[2] + sq_[3] + (uint64_t)vUR * vUL +
+                               (uint64_t)vUR * hL) +
+                         rb * (uint64_t)(sq->prow[0] * sq->pld[0] + sq->prow[1] * sq->pld[1]) + (uint64_t)Lv * Lh + 8;
+    const uint64_t fixed = sq->off_y + 16 * 256 + 256;  // small region and per-region alignment
+    int64_t c = budget > fixed ? (int64_t)((budget - fixed) / per) : 0;
+    c = std::min<int64_t>({c, kSqChunk, (int64_t)std::max(pl->opts.max_batch, 1)});
+    if (c >= kSqMinChunk) {
+      sq->chunk = c;
+      uint64_t bo = sq->off_y;
+      auto take = [&](uint64_t bytes) {
+        const uint64_t at = bo;
+        bo += al(bytes);
+        return at;
+      };
+      sq->boff_run[0] = take((uint64_t)c * sq->tmax * eb);
+      sq->boff_run[1] = take((uint64_t)c * sq->tmax * eb);
+      for (int qi = 0; qi < 4; ++qi) sq->boff_q[qi] = take((uint64_t)c * sq_[qi] * eb);
+      sq->boff_t = take((uint64_t)c * vUR * vUL * eb);
+      sq->boff_y = take((uint64_t)c * vUR * hL * eb);
+      sq->boff_pk[0] = take((uint64_t)c * sq->prow[0] * sq->pld[0] * rb);
+      sq->boff_pk[1] = take((uint64_t)c * sq->prow[1] * sq->pld[1] * rb);
+      sq->boff_tau = take((uint64_t)c * Lv * Lh);
+      sq->boff_zeros = take((uint64_t)c * 4);
+      sq->boff_mx = take((uint64_t)c * 4);
+      sq->ycap = 1;
+      off = bo;
+    }
+  }
+  pl->ws_total = sq->chunk ? off + 256 : seq_total;
   if (pl->ws_total > pl->opts.mem_budget_bytes)
     fail(PSIM_ENOMEM, "square partition needs " + std::to_string(pl->ws_total) + " bytes; budget is " +
                           std::to_string(pl->opts.mem_budget_bytes));
@@ -242,9 +295,32 @@ struct SqRun {
   int prec;
   uint64_t eb;
   int32_t* d_zero;
-  int32_t* d_e;
   uint32_t* d_mx;
   double* d_part;
+  int32_t* d_exps;       // kSqExpSlots exponent slots
+  double* d_dots;        // kSqDotSlots (re, im) inner products
+  double* out = nullptr;
+
+  // Exponent of a tensor: a host part (site matrices) plus device slots
+  // (rescales), identified by ids that are never reused within a call.
+  struct Exp {
+    int64_t host = 0;
+    std::vector<int64_t> slots;
+    Exp& operator+=(const Exp& o) {
+      host += o.host;
+      slots.insert(slots.end(), o.slots.begin(), o.slots.end());
+      return *this;
+    }
+  };
+  int64_t exp_next = 0, exp_base = 0, dot_next = 0, dot_base = 0;
+  std::vector<int64_t> exp_val;   // downloaded exponent of every slot id below exp_base
+  std::vector<double> dot_val;    // downloaded (re, im) of every dot id below dot_base
+  struct Pend {
+    size_t b;                     // output index
+    int64_t dot;
+    Exp e;
+  };
+  std::vector<Pend> pend;         // amplitudes waiting for the next flush
   // optional event timing (psim_profile): class 0 quadrant site contractions,
   // 1 joins, 2 permutes / packing / inner products, 3 rescales
   struct Timed {
@@ -290,22 +366,54 @@ struct SqRun {
     timed.clear();
   }
 
-  // exact power-of-two rescale of one tensor; returns the exponent taken out
-  int64_t rescale(void* T, int64_t elems) {
-    run(3, 0, 3.0 * eb * elems, [&] { launch_rowscale(prec, T, elems, 1, d_zero, d_zero, d_e, d_mx, st); });
-    int32_t e = 0;
-    hip_check(hipMemcpyAsync(&e, d_e, 4, hipMemcpyDeviceToHost, st), "download exponent");
+  // Download every slot written since the last flush (one synchronisation)
+  // and write the amplitudes that waited for them.
+  void flush() {
+    const int64_t ne = exp_next - exp_base, nd = dot_next - dot_base;
+    if (ne == 0 && nd == 0 && pend.empty()) return;
+    std::vector<int32_t> he((size_t)ne);
+    std::vector<double> hd((size_t)(2 * nd));
+    if (ne) hip_check(hipMemcpyAsync(he.data(), d_exps, (size_t)ne * 4, hipMemcpyDeviceToHost, st), "download exponents");
+    if (nd) hip_check(hipMemcpyAsync(hd.data(), d_dots, (size_t)nd * 16, hipMemcpyDeviceToHost, st), "download dots");
     hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    exp_val.insert(exp_val.end(), he.begin(), he.end());
+    dot_val.insert(dot_val.end(), hd.begin(), hd.end());
+    exp_base = exp_next;
+    dot_base = dot_next;
+    for (const Pend& p : pend) {
+      int64_t e = p.e.host;
+      for (int64_t id : p.e.slots) e += exp_val[(size_t)id];
+      out[2 * p.b] = std::ldexp(dot_val[(size_t)(2 * p.dot)], (int)e);
+      out[2 * p.b + 1] = std::ldexp(dot_val[(size_t)(2 * p.dot + 1)], (int)e);
+    }
+    pend.clear();
+  }
+
+  // exact power-of-two rescale of one tensor; its exponent goes to a slot
+  Exp rescale(void* T, int64_t elems) {
+    if (exp_next - exp_base == kSqExpSlots) flush();
+    int32_t* slot = d_exps + (exp_next - exp_base);
+    run(3, 0, 3.0 * eb * elems, [&] { launch_rowscale(prec, T, elems, 1, d_zero, d_zero, slot, d_mx, st); });
+    Exp e;
+    e.slots.push_back(exp_next++);
     return e;
   }
 
+  // sum_i a[i] b[i] over n complex elements into a dot slot; returns its id
+  int64_t dot(const void* a, const void* b, int64_t n) {
+    if (dot_next - dot_base == kSqDotSlots) flush();
+    double* o = d_dots + 2 * (dot_next - dot_base);
+    run(2, (double)n, 2.0 * eb * n, [&] { launch_cdot(prec, a, b, n, d_part, o, st); });
+    return dot_next++;
+  }
+
   // Contract quadrant qi for bits into dst; returns its exponent.
-  int64_t quad(int qi, const uint8_t* bits, char* dst) {
+  Exp quad(int qi, const uint8_t* bits, char* dst) {
     const SqQuad& Q = sq->q[qi];
     const int nr = Q.nr, nc = Q.nc;
     char* cur = buf(sq->off_w1);
     char* nxt = buf(sq->off_w2);
-    int64_t e = 0;
+    Exp e;
     int64_t cur_elems = 1;
     for (int i = 0; i < nr; ++i) {
       for (int j = 0; j < nc; ++j) {
@@ -329,7 +437,7 @@ struct SqRun {
         g.sC_node = sh.M * sh.N;
         run(0, (double)sh.M * sh.K1 * sh.K2 * sh.N, (double)eb * (sh.M * sh.K1 * sh.K2 + sh.M * sh.N),
             [&] { launch_site_gemm(g, st); });
-        e += w.exp2;
+        e.host += w.exp2;
         std::swap(cur, nxt);
         cur_elems = sh.M * sh.N;
       }
@@ -351,6 +459,79 @@ struct SqRun {
     return e;
   }
 
+  // Batched form: rescale of `nodes` tensors per_node elements apart, one
+  // exponent slot each; returns the first slot id.
+  int32_t* d_zeros = nullptr;  // parent index 0 for every node
+  uint32_t* d_mxn = nullptr;   // per-node scratch of the rescale
+  int64_t rescale_nodes(void* T, int64_t per_node, int64_t nodes) {
+    if (exp_next - exp_base + nodes > kSqExpSlots) flush();
+    int32_t* slot = d_exps + (exp_next - exp_base);
+    run(3, 0, 3.0 * eb * per_node * nodes,
+        [&] { launch_rowscale(prec, T, per_node, nodes, d_zeros, d_zero, slot, d_mxn, st); });
+    const int64_t first = exp_next;
+    exp_next += nodes;
+    return first;
+  }
+
+  // Batched form: quadrant qi for `nodes` patterns at once (pattern p's bits
+  // at d_tau[p * sites + s], s in frame order), running tensors in r0 / r1,
+  // the finished tensors in dst (node stride dv * dh).  Returns the first
+  // exponent slot of each frame row; pattern p's slot of row i is
+  // row_slot[i] + p.
+  std::vector<int64_t> quad_nodes(int qi, int64_t nodes, const uint8_t* d_tau, char* r0, char* r1, char* dst) {
+    const SqQuad& Q = sq->q[qi];
+    const int nr = Q.nr, nc = Q.nc;
+    const int64_t sites = (int64_t)Q.s.size();
+    char* cur = r0;
+    char* nxt = r1;
+    std::vector<int64_t> row_slot;
+    int64_t cur_elems = 1;
+    for (int i = 0; i < nr; ++i) {
+      for (int j = 0; j < nc; ++j) {
+        const SqSite& st_ = Q.s[(size_t)i * nc + j];
+        if (st_.w[0].ld != st_.w[1].ld) fail(PSIM_EINTERNAL, "site matrices of one site differ in layout");
+        const Shape sh = site_shape(Q, i, j);
+        const bool first = i == 0 && j == 0;
+        GemmLaunch g;
+        g.prec = prec;
+        g.A = first ? pl->d_ones : (const void*)cur;
+        g.C = nxt;
+        g.W0 = st_.w[0].ptr;
+        g.W1 = st_.w[1].ptr;
+        g.tau = d_tau + (i * nc + j);
+        g.tau_stride = sites;
+        g.ldw = st_.w[0].ld;
+        g.M = sh.M;
+        g.K1 = sh.K1;
+        g.K2 = sh.K2;
+        g.N = sh.N;
+        g.nodes = nodes;
+        g.Bz = 1;
+        g.sA_node = first ? 0 : sh.K1 * sh.M * sh.K2;  // every node reads the scalar 1 first
+        g.sC_node = sh.M * sh.N;
+        run(0, (double)nodes * sh.M * sh.K1 * sh.K2 * sh.N,
+            (double)eb * nodes * (sh.M * sh.K1 * sh.K2 + sh.M * sh.N), [&] { launch_site_gemm(g, st); });
+        std::swap(cur, nxt);
+        cur_elems = sh.M * sh.N;
+      }
+      row_slot.push_back(rescale_nodes(cur, cur_elems, nodes));
+      int64_t X = 1, Y = 1;
+      for (int k = 0; k < i; ++k) X *= Q.s[(size_t)k * nc + nc - 1].dr;
+      for (int j = 0; j < nc; ++j) Y *= Q.s[(size_t)i * nc + j].dd;
+      const int64_t Z = Q.s[(size_t)i * nc + nc - 1].dr;
+      if (i + 1 < nr) {
+        if (X > 1) {
+          run(2, 0, 2.0 * eb * X * Y * Z * nodes, [&] { launch_permute3(prec, cur, nxt, X, Y, Z, 0, st, nodes); });
+          std::swap(cur, nxt);
+        }
+      } else {
+        run(2, 0, 2.0 * eb * X * Y * Z * nodes,
+            [&] { launch_permute3(prec, cur, dst, X, Y, Z, qi == 2 ? 1 : 0, st, nodes); });
+      }
+    }
+    return row_slot;
+  }
+
   void gemm(const void* A, int64_t M, int64_t K, const void* P, int64_t ld, int64_t N, void* C) {
     GemmLaunch g;
     g.prec = prec;
@@ -368,10 +549,132 @@ struct SqRun {
     g.sC_node = M * N;
     run(1, (double)M * K * N, (double)eb * (M * K + K * N + M * N), [&] { launch_site_gemm(g, st); });
   }
-  void pack(const void* Q, void* P, int64_t N, int64_t K, int64_t rows, int64_t ld) {
-    run(2, 0, (double)eb * N * K + (double)(eb / 2) * rows * ld, [&] { launch_pack_w(prec, Q, P, N, K, rows, ld, st); });
+  void pack(const void* Q, void* P, int64_t N, int64_t K, int64_t rows, int64_t ld, int64_t nodes = 1) {
+    run(2, 0, nodes * ((double)eb * N * K + (double)(eb / 2) * rows * ld),
+        [&] { launch_pack_w(prec, Q, P, N, K, rows, ld, st, nodes); });
   }
 };
+
+}  // namespace
+
+namespace {
+
+// Batched form: consecutive bitstrings of the sorted order in chunks of up to
+// sq->chunk.  Per chunk, each quadrant's distinct patterns are contracted
+// together (the pattern is the node index of every launch), then one join per
+// distinct (UL, UR) pair (T) and per distinct (pair, LL) (Y), then one inner
+// product per distinct (Y, LR).  Same launches per tensor as the one-by-one
+// form, so the same results bit for bit.
+void run_chunks(SqRun& R, const uint8_t* bits, const std::vector<size_t>& order,
+                const std::vector<std::vector<uint8_t>>& keys, const size_t koff[5]) {
+  const SquarePlan* sq = R.sq;
+  const int nq = sq->lv * sq->lh;
+  const size_t n = order.size();
+  const int64_t vUL = sq->q[0].dv, vUR = sq->q[1].dv, hU = sq->q[0].dh, hL = sq->q[2].dh;
+  const uint64_t eb = R.eb, rb = R.eb / 2;
+  int64_t qsz[4];
+  for (int qi = 0; qi < 4; ++qi) qsz[qi] = sq->q[qi].dv * sq->q[qi].dh;
+  char* run0 = R.buf(sq->boff_run[0]);
+  char* run1 = R.buf(sq->boff_run[1]);
+  char* Tst = R.buf(sq->boff_t);
+  char* Yst = R.buf(sq->boff_y);
+  R.d_zeros = (int32_t*)R.buf(sq->boff_zeros);
+  R.d_mxn = (uint32_t*)R.buf(sq->boff_mx);
+  hip_check(hipMemsetAsync(R.d_zeros, 0, (size_t)sq->chunk * 4, R.st), "clear parents");
+  uint8_t* d_tau = (uint8_t*)R.buf(sq->boff_tau);
+  std::vector<std::vector<uint8_t>> uploads;  // host copies stay alive until the final flush
+  using Key = std::vector<uint8_t>;
+  for (size_t c0 = 0; c0 < n; c0 += (size_t)sq->chunk) {
+    const size_t c1 = std::min(n, c0 + (size_t)sq->chunk);
+    // distinct patterns of each quadrant in the chunk
+    std::map<Key, int> pid[4];
+    std::vector<std::array<int, 4>> bp(c1 - c0);
+    std::vector<size_t> rep[4];  // a bitstring of each pattern
+    for (size_t z = c0; z < c1; ++z) {
+      const Key& k = keys[order[z]];
+      for (int qi = 0; qi < 4; ++qi) {
+        Key part(k.begin() + koff[qi], k.begin() + koff[qi + 1]);
+        auto it = pid[qi].find(part);
+        if (it == pid[qi].end()) {
+          it = pid[qi].emplace(std::move(part), (int)rep[qi].size()).first;
+          rep[qi].push_back(order[z]);
+        }
+        bp[z - c0][qi] = it->second;
+      }
+    }
+    // bits of every pattern in frame order, all four quadrants in one upload
+    uploads.emplace_back();
+    std::vector<uint8_t>& tab = uploads.back();
+    size_t toff[4];
+    std::vector<int64_t> host_e[4];
+    for (int qi = 0; qi < 4; ++qi) {
+      toff[qi] = tab.size();
+      for (size_t b : rep[qi]) {
+        int64_t e = 0;
+        for (const SqSite& st_ : sq->q[qi].s) {
+          const uint8_t t = bits[b * nq + st_.qubit];
+          tab.push_back(t);
+          e += st_.w[t].exp2;
+        }
+        host_e[qi].push_back(e);
+      }
+    }
+    hip_check(hipMemcpyAsync(d_tau, tab.data(), tab.size(), hipMemcpyHostToDevice, R.st), "upload pattern bits");
+    auto quad = [&](int qi) {
+      return R.quad_nodes(qi, (int64_t)rep[qi].size(), d_tau + toff[qi], run0, run1, R.buf(sq->boff_q[qi]));
+    };
+    auto qptr = [&](int qi, int p) { return R.buf(sq->boff_q[qi]) + (uint64_t)p * qsz[qi] * eb; };
+    // upper half: T per distinct (UL, UR)
+    const std::vector<int64_t> sUL = quad(0), sUR = quad(1);
+    const int64_t nUL = (int64_t)rep[0].size();
+    R.pack(qptr(0, 0), R.buf(sq->boff_pk[0]), vUL, hU, sq->prow[0], sq->pld[0], nUL);
+    std::map<std::pair<int, int>, int> pair_id;
+    std::vector<std::pair<int, int>> pairs;
+    for (const auto& b : bp)
+      if (pair_id.emplace(std::make_pair(b[0], b[1]), (int)pairs.size()).second) pairs.emplace_back(b[0], b[1]);
+    for (size_t t = 0; t < pairs.size(); ++t)
+      R.gemm(qptr(1, pairs[t].second), vUR, hU,
+             R.buf(sq->boff_pk[0]) + (uint64_t)pairs[t].first * sq->prow[0] * sq->pld[0] * rb, sq->pld[0], vUL,
+             Tst + (uint64_t)t * vUR * vUL * eb);
+    const int64_t sT = R.rescale_nodes(Tst, vUR * vUL, (int64_t)pairs.size());
+    // lower-left: Y per distinct (pair, LL)
+    const std::vector<int64_t> sLL = quad(2);
+    R.pack(qptr(2, 0), R.buf(sq->boff_pk[1]), hL, vUL, sq->prow[1], sq->pld[1], (int64_t)rep[2].size());
+    std::map<std::pair<int, int>, int> tri_id;
+    std::vector<std::pair<int, int>> tris;  // (pair, LL)
+    for (const auto& b : bp) {
+      const int pr = pair_id[std::make_pair(b[0], b[1])];
+      if (tri_id.emplace(std::make_pair(pr, b[2]), (int)tris.size()).second) tris.emplace_back(pr, b[2]);
+    }
+    for (size_t t = 0; t < tris.size(); ++t)
+      R.gemm(Tst + (uint64_t)tris[t].first * vUR * vUL * eb, vUR, vUL,
+             R.buf(sq->boff_pk[1]) + (uint64_t)tris[t].second * sq->prow[1] * sq->pld[1] * rb, sq->pld[1], hL,
+             Yst + (uint64_t)t * vUR * hL * eb);
+    const int64_t sY = R.rescale_nodes(Yst, vUR * hL, (int64_t)tris.size());
+    // lower-right, then one inner product per distinct (Y, LR)
+    const std::vector<int64_t> sLR = quad(3);
+    std::map<std::pair<int, int>, int64_t> dot_id;
+    for (size_t z = c0; z < c1; ++z) {
+      const auto& b = bp[z - c0];
+      const int pr = pair_id[std::make_pair(b[0], b[1])];
+      const int tr = tri_id[std::make_pair(pr, b[2])];
+      auto it = dot_id.find(std::make_pair(tr, b[3]));
+      if (it == dot_id.end())
+        it = dot_id.emplace(std::make_pair(tr, b[3]),
+                            R.dot(Yst + (uint64_t)tr * vUR * hL * eb, qptr(3, b[3]), vUR * hL)).first;
+      SqRun::Pend p{order[z], it->second, {}};
+      p.e.host = host_e[0][b[0]] + host_e[1][b[1]] + host_e[2][b[2]] + host_e[3][b[3]];
+      for (int64_t x : sUL) p.e.slots.push_back(x + b[0]);
+      for (int64_t x : sUR) p.e.slots.push_back(x + b[1]);
+      p.e.slots.push_back(sT + pr);
+      for (int64_t x : sLL) p.e.slots.push_back(x + b[2]);
+      p.e.slots.push_back(sY + tr);
+      for (int64_t x : sLR) p.e.slots.push_back(x + b[3]);
+      R.pend.push_back(std::move(p));
+    }
+  }
+  R.flush();
+}
 
 }  // namespace
 
@@ -389,9 +692,11 @@ void run_square(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, void* 
   R.eb = pl->elem_bytes;
   char* small = R.buf(sq->off_small);
   R.d_zero = (int32_t*)small;
-  R.d_e = (int32_t*)(small + 4);
   R.d_mx = (uint32_t*)(small + 8);
   R.d_part = (double*)(small + 16);
+  R.d_exps = (int32_t*)(small + 16 + (size_t)cdot_blocks() * 16);
+  R.d_dots = (double*)(small + 16 + (size_t)cdot_blocks() * 16 + (size_t)kSqExpSlots * 4);
+  R.out = out;
   static const int32_t zero = 0;
   hip_check(hipMemcpyAsync(R.d_zero, &zero, 4, hipMemcpyHostToDevice, R.st), "upload zero");
 
@@ -414,38 +719,44 @@ void run_square(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, void* 
   };
 
   const int64_t vUL = sq->q[0].dv, vUR = sq->q[1].dv, hU = sq->q[0].dh, hL = sq->q[2].dh;
+  if (sq->chunk > 0) {
+    run_chunks(R, bits, order, keys, koff);
+    R.flush();
+    R.collect(pl);
+    return;
+  }
   char* A = R.buf(sq->off_a);
   char* B = R.buf(sq->off_b);
   char* C = R.buf(sq->off_c);
   char* P = R.buf(sq->off_p);
   const uint64_t ysz = ((uint64_t)sq->qmax * R.eb + 255) / 256 * 256;
   auto ybuf = [&](int k) { return k == 0 ? B : R.buf(sq->off_y) + (uint64_t)(k - 1) * ysz; };
-  const int nblk = cdot_blocks();
-  std::vector<double> part((size_t)nblk * 2);
   size_t x = 0;
   while (x < n) {
     // bitstrings [x, xe) share the upper half: T once
     size_t xe = x + 1;
     while (xe < n && same(order[x], order[xe], 2)) ++xe;
     const uint8_t* b0 = bits + order[x] * nq;
-    const int64_t eUL = R.quad(0, b0, A);       // Q_UL [vUL][hU]
-    const int64_t eUR = R.quad(1, b0, B);       // Q_UR [vUR][hU]
+    SqRun::Exp eT = R.quad(0, b0, A);           // Q_UL [vUL][hU]
+    eT += R.quad(1, b0, B);                     // Q_UR [vUR][hU]
     R.pack(A, P, vUL, hU, sq->prow[0], sq->pld[0]);
     R.gemm(B, vUR, hU, P, sq->pld[0], vUL, C);  // T [vUR][vUL]
-    const int64_t eT = eUL + eUR + R.rescale(C, vUR * vUL);
+    eT += R.rescale(C, vUR * vUL);
     size_t y = x;
     while (y < xe) {
       // one pass: up to ycap lower-left patterns, each joined into its Y
-      std::vector<int64_t> eY;
+      std::vector<SqRun::Exp> eY;
       std::vector<int> slot(xe - y);  // Y of each bitstring of the pass
       size_t ye = y;
       while (ye < xe && (int)eY.size() < sq->ycap) {
         const uint8_t* bb = bits + order[ye] * nq;
         const int k = (int)eY.size();
-        const int64_t eLL = R.quad(2, bb, A);   // Q_LL [hL][vUL]
+        SqRun::Exp e = eT;
+        e += R.quad(2, bb, A);                  // Q_LL [hL][vUL]
         R.pack(A, P, hL, vUL, sq->prow[1], sq->pld[1]);
         R.gemm(C, vUR, vUL, P, sq->pld[1], hL, ybuf(k));  // Y [vUR][hL]
-        eY.push_back(eT + eLL + R.rescale(ybuf(k), vUR * hL));
+        e += R.rescale(ybuf(k), vUR * hL);
+        eY.push_back(e);
         size_t z = ye;
         while (z < xe && same(order[ye], order[z], 3)) slot[z++ - y] = k;
         ye = z;
@@ -456,33 +767,21 @@ void run_square(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, void* 
         lr[std::vector<uint8_t>(keys[order[z]].begin() + koff[3], keys[order[z]].end())].push_back(z);
       for (auto& kv : lr) {
         const uint8_t* bb = bits + order[kv.second.front()] * nq;
-        const int64_t eLR = R.quad(3, bb, A);   // Q_LR [vUR][hL]
-        std::map<int, std::pair<double, double>> done;
+        const SqRun::Exp eLR = R.quad(3, bb, A);  // Q_LR [vUR][hL]
+        std::map<int, int64_t> done;            // Y slot -> dot id
         for (size_t z : kv.second) {
           const int k = slot[z - y];
-          if (!done.count(k)) {
-            R.run(2, (double)vUR * hL, 2.0 * R.eb * vUR * hL,
-                  [&] { launch_cdot(R.prec, ybuf(k), A, vUR * hL, R.d_part, R.st); });
-            hip_check(hipMemcpyAsync(part.data(), R.d_part, part.size() * 8, hipMemcpyDeviceToHost, R.st),
-                      "download");
-            hip_check(hipStreamSynchronize(R.st), "hipStreamSynchronize");
-            double re = 0, im = 0;
-            for (int t = 0; t < nblk; ++t) {
-              re += part[2 * t];
-              im += part[2 * t + 1];
-            }
-            done[k] = {re, im};
-          }
-          const size_t b = order[z];
-          const int64_t e = eY[k] + eLR;
-          out[2 * b] = std::ldexp(done[k].first, (int)e);
-          out[2 * b + 1] = std::ldexp(done[k].second, (int)e);
+          if (!done.count(k)) done[k] = R.dot(ybuf(k), A, vUR * hL);
+          SqRun::Pend p{order[z], done[k], eY[k]};
+          p.e += eLR;
+          R.pend.push_back(std::move(p));
         }
       }
       y = ye;
     }
     x = xe;
   }
+  R.flush();
   R.collect(pl);
 }
 

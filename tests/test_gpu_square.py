@@ -135,3 +135,60 @@ def test_square_6x6_d40_vs_golden(ps, prec):
     rel = np.abs(a - ref) / np.abs(ref)
     say(f"square 6x6 d40 {prec}: max eps_rel {rel.max():.2e}")
     assert rel.max() <= (1e-10 if prec == "fp64" else 1e-5)
+
+
+def _shared_batch(lv, lh, seed, n):
+    """n random bitstrings, then copies of the first 30 with the last qubit
+    (a lower-right site) flipped (same upper half and lower-left quadrant),
+    then repeats of the first 5: 35 + n bitstrings."""
+    base = rqcgen.bitstrings(lv, lh, seed, n)
+    flip = base[:30].copy()
+    flip[:, lv * lh - 1] ^= 1
+    return np.concatenate([base, flip, base[:5]])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_3m"])
+@pytest.mark.parametrize("lv,lh,d,seed", [(3, 3, 8, 0), (4, 4, 16, 1), (3, 5, 16, 2), (5, 4, 16, 3),
+                                          (2, 6, 13, 4), (4, 5, 16, 5)])
+def test_square_chunks_match_one_by_one(ps, prec, lv, lh, d, seed):
+    """The batched form (a chunk of up to 32 bitstrings, each quadrant's
+    distinct patterns as the node index of one set of launches) against the
+    one-by-one form (max_batch 1): the same launches per tensor, so the same
+    amplitudes bit for bit; 75 bitstrings = three chunks, the last one ragged,
+    with shared halves and repeats; and the state vector within the bar."""
+    c = rqcgen.generate(lv, lh, d, seed)
+    bits = _shared_batch(lv, lh, seed, 40)
+    P = ps.Peps(c)
+    one = ps.Plan(P, prec=prec, sweep=3, max_batch=1)
+    chunked = ps.Plan(P, prec=prec, sweep=3, max_batch=len(bits))
+    assert chunked.stats()["workspace_bytes"] > one.stats()["workspace_bytes"]
+    a1 = one.amplitudes(bits)
+    chunked.profile_start()
+    a2 = chunked.amplitudes(bits)
+    prof = chunked.profile_read()
+    chunked.profile_stop()
+    assert np.array_equal(a1, a2), np.max(np.abs(a1 - a2))
+    # every quadrant site contracted once per chunk: 3 chunks x all sites
+    assert prof["first_site"]["launches"] == 3 * lv * lh, prof["first_site"]
+    ref = sv.amplitudes(sv.run(c), bits)
+    e = _eps_rms(a2, ref, lv * lh)
+    say(f"square chunks {lv}x{lh} d{d} {prec}: bitwise equal to one by one, max eps_rms {e.max():.2e}")
+    assert e.max() <= AMP_BAR[prec]
+
+
+def test_square_chunk_budget_and_repeat_calls(ps):
+    """A budget too small for a chunk of 8 gives the one-by-one form; a
+    chunked plan called twice in a row (the second call smaller) repeats its
+    results exactly."""
+    c = rqcgen.generate(5, 5, 24, 6)
+    bits = _shared_batch(5, 5, 6, 20)
+    P = ps.Peps(c)
+    full = ps.Plan(P, prec="fp32_3m", sweep=3, max_batch=len(bits))
+    one = ps.Plan(P, prec="fp32_3m", sweep=3, max_batch=1)
+    small = ps.Plan(P, prec="fp32_3m", sweep=3, max_batch=len(bits),
+                    mem_budget=one.stats()["workspace_bytes"] + (1 << 20))
+    assert small.stats()["workspace_bytes"] == one.stats()["workspace_bytes"]
+    a = full.amplitudes(bits)
+    assert np.array_equal(a, small.amplitudes(bits))
+    assert np.array_equal(full.amplitudes(bits[7:20]), a[7:20])
+    assert np.array_equal(full.amplitudes(bits), a)
