@@ -91,7 +91,7 @@ struct SquarePlan {
   // exact node strides
   int64_t chunk = 0;
   uint64_t boff_run[2] = {0, 0}, boff_q[4] = {0, 0, 0, 0}, boff_t = 0, boff_y = 0, boff_pk[2] = {0, 0};
-  uint64_t boff_tau = 0, boff_zeros = 0, boff_mx = 0;
+  uint64_t boff_tau = 0, boff_zeros = 0, boff_mx = 0, boff_desc[2] = {0, 0};
   double cmac_quads = 0, cmac_joins = 0;
   int64_t n_steps = 0;
   ~SquarePlan() {
@@ -220,7 +220,8 @@ void make_square_plan(psim_plan_t* pl, const psim_peps_t& P) {
     const uint64_t per = eb * (2 * (uint64_t)sq->tmax + sq_[0] + sq_[1] + sq_[2] + sq_[3] + (uint64_t)vUR * vUL +
                                (uint64_t)vUR * hL) +
                          rb * (uint64_t)(sq->prow[0] * sq->pld[0] + sq->prow[1] * sq->pld[1]) + (uint64_t)Lv * Lh + 8;
-    const uint64_t fixed = sq->off_y + 16 * 256 + 256;  // small region and per-region alignment
+    const uint64_t fixed = sq->off_y + 16 * 256 + 256 +  // small region and per-region alignment
+                           2 * (uint64_t)max_group() * kargs_bytes();
     int64_t c = budget > fixed ? (int64_t)((budget - fixed) / per) : 0;
     c = std::min<int64_t>({c, kSqChunk, (int64_t)std::max(pl->opts.max_batch, 1)});
     if (c >= kSqMinChunk) {
@@ -241,6 +242,8 @@ void make_square_plan(psim_plan_t* pl, const psim_peps_t& P) {
       sq->boff_tau = take((uint64_t)c * Lv * Lh);
       sq->boff_zeros = take((uint64_t)c * 4);
       sq->boff_mx = take((uint64_t)c * 4);
+      sq->boff_desc[0] = take((uint64_t)max_group() * kargs_bytes());
+      sq->boff_desc[1] = take((uint64_t)max_group() * kargs_bytes());
       sq->ycap = 1;
       off = bo;
     }
@@ -532,6 +535,63 @@ struct SqRun {
     return row_slot;
   }
 
+  static GemmLaunch join_launch(int prec, const void* A, int64_t M, int64_t K, const void* P, int64_t ld, int64_t N,
+                                void* C) {
+    GemmLaunch g;
+    g.prec = prec;
+    g.A = A;
+    g.C = C;
+    g.W0 = g.W1 = P;
+    g.ldw = ld;
+    g.M = M;
+    g.K1 = 1;
+    g.K2 = K;
+    g.N = N;
+    g.nodes = 1;
+    g.Bz = 1;
+    g.sA_node = M * K;
+    g.sC_node = M * N;
+    return g;
+  }
+
+  // Several joins of one shape: one grouped launch (the same kernel body and
+  // tiles as separate launches) when the kernel has a grouped form, else one
+  // launch each.  d_desc holds max_group() descriptors; host copies of the
+  // descriptors are appended to keep (alive until the next synchronisation).
+  void joins(const std::vector<GemmLaunch>& gl, char* d_desc, std::vector<std::vector<uint8_t>>& keep) {
+    if (gl.empty()) return;
+    const int kb = kargs_bytes();
+    double cmac = 0, bytes = 0;
+    for (const GemmLaunch& g : gl) {
+      cmac += (double)g.M * g.K2 * g.N;
+      bytes += (double)eb * (g.M * g.K2 + g.K2 * g.N + g.M * g.N);
+    }
+    if (gl.size() > 1 && (int)gl.size() <= max_group()) {
+      keep.emplace_back(gl.size() * (size_t)kb);
+      std::vector<uint8_t>& desc = keep.back();
+      std::vector<long long> start(gl.size() + 1, 0);
+      std::vector<const void*> probs(gl.size());
+      int var = -1;
+      bool ok = true;
+      for (size_t i = 0; i < gl.size() && ok; ++i) {
+        long long tiles = 0;
+        const int v = group_variant(gl[i], desc.data() + i * kb, &tiles);
+        ok = v >= 0 && (var < 0 || v == var);
+        var = v;
+        start[i + 1] = start[i] + tiles;
+        probs[i] = d_desc + i * kb;
+      }
+      if (ok) {
+        hip_check(hipMemcpyAsync(d_desc, desc.data(), desc.size(), hipMemcpyHostToDevice, st), "upload join descriptors");
+        run(1, cmac, bytes, [&] { launch_group(var, probs.data(), start.data(), (int)gl.size(), st); });
+        return;
+      }
+    }
+    for (const GemmLaunch& g : gl)
+      run(1, (double)g.M * g.K2 * g.N, (double)eb * (g.M * g.K2 + g.K2 * g.N + g.M * g.N),
+          [&] { launch_site_gemm(g, st); });
+  }
+
   void gemm(const void* A, int64_t M, int64_t K, const void* P, int64_t ld, int64_t N, void* C) {
     GemmLaunch g;
     g.prec = prec;
@@ -563,8 +623,10 @@ namespace {
 // sq->chunk.  Per chunk, each quadrant's distinct patterns are contracted
 // together (the pattern is the node index of every launch), then one join per
 // distinct (UL, UR) pair (T) and per distinct (pair, LL) (Y), then one inner
-// product per distinct (Y, LR).  Same launches per tensor as the one-by-one
-// form, so the same results bit for bit.
+// product per distinct (Y, LR).  Each tensor is computed by the same kernel
+// body on the same tiles as in the one-by-one form (the joins of a chunk in
+// one grouped launch where the kernel has a grouped form), so the results
+// are the same bit for bit.
 void run_chunks(SqRun& R, const uint8_t* bits, const std::vector<size_t>& order,
                 const std::vector<std::vector<uint8_t>>& keys, const size_t koff[5]) {
   const SquarePlan* sq = R.sq;
@@ -632,10 +694,13 @@ void run_chunks(SqRun& R, const uint8_t* bits, const std::vector<size_t>& order,
     std::vector<std::pair<int, int>> pairs;
     for (const auto& b : bp)
       if (pair_id.emplace(std::make_pair(b[0], b[1]), (int)pairs.size()).second) pairs.emplace_back(b[0], b[1]);
+    std::vector<GemmLaunch> gl;
     for (size_t t = 0; t < pairs.size(); ++t)
-      R.gemm(qptr(1, pairs[t].second), vUR, hU,
-             R.buf(sq->boff_pk[0]) + (uint64_t)pairs[t].first * sq->prow[0] * sq->pld[0] * rb, sq->pld[0], vUL,
-             Tst + (uint64_t)t * vUR * vUL * eb);
+      gl.push_back(SqRun::join_launch(
+          R.prec, qptr(1, pairs[t].second), vUR, hU,
+          R.buf(sq->boff_pk[0]) + (uint64_t)pairs[t].first * sq->prow[0] * sq->pld[0] * rb, sq->pld[0], vUL,
+          Tst + (uint64_t)t * vUR * vUL * eb));
+    R.joins(gl, R.buf(sq->boff_desc[0]), uploads);
     const int64_t sT = R.rescale_nodes(Tst, vUR * vUL, (int64_t)pairs.size());
     // lower-left: Y per distinct (pair, LL)
     const std::vector<int64_t> sLL = quad(2);
@@ -646,10 +711,13 @@ void run_chunks(SqRun& R, const uint8_t* bits, const std::vector<size_t>& order,
       const int pr = pair_id[std::make_pair(b[0], b[1])];
       if (tri_id.emplace(std::make_pair(pr, b[2]), (int)tris.size()).second) tris.emplace_back(pr, b[2]);
     }
+    gl.clear();
     for (size_t t = 0; t < tris.size(); ++t)
-      R.gemm(Tst + (uint64_t)tris[t].first * vUR * vUL * eb, vUR, vUL,
-             R.buf(sq->boff_pk[1]) + (uint64_t)tris[t].second * sq->prow[1] * sq->pld[1] * rb, sq->pld[1], hL,
-             Yst + (uint64_t)t * vUR * hL * eb);
+      gl.push_back(SqRun::join_launch(
+          R.prec, Tst + (uint64_t)tris[t].first * vUR * vUL * eb, vUR, vUL,
+          R.buf(sq->boff_pk[1]) + (uint64_t)tris[t].second * sq->prow[1] * sq->pld[1] * rb, sq->pld[1], hL,
+          Yst + (uint64_t)t * vUR * hL * eb));
+    R.joins(gl, R.buf(sq->boff_desc[1]), uploads);
     const int64_t sY = R.rescale_nodes(Yst, vUR * hL, (int64_t)tris.size());
     // lower-right, then one inner product per distinct (Y, LR)
     const std::vector<int64_t> sLR = quad(3);
