@@ -125,6 +125,38 @@ psim_status psim_peps_info(const psim_peps_t *peps, int32_t *lv, int32_t *lh, in
 
 void psim_peps_free(psim_peps_t *peps);
 
+/* Double-layer network of a PEPS (main text: observables of the stored
+ * state): the norm network <psi|psi> with a one-qubit operator between the
+ * bra and ket layers of every site, returned as a PEPS whose bonds are the
+ * squared bonds (doubled leg index = bra * D + ket) and whose two physical
+ * slices at site n are
+ *   E_{n,s}[(l l')][(r r')][(u u')][(d d')]
+ *       = sum_{a,b} conj(A_n[a][l][r][u][d]) O_{n,s}[a][b] A_n[b][l'][r'][u'][d'],  s = 0, 1.
+ * ops: host, lv*lh*2 complex 2x2 matrices (row-major (re, im) pairs), O_{n,s}
+ * at ops + (2n + s) * 8.  Planned and contracted like any PEPS, its
+ * "amplitude" of bitstring b is <psi| prod_n O_{n,b_n} |psi> (e.g. O_{n,0} =
+ * Z_n, O_{m,0} = I elsewhere, bits all 0: <Z_n>).  *out is a new handle.
+ * Errors: EINVAL for NULL or non-finite ops; EUNSUPPORTED when a doubled site
+ * tensor exceeds 2^28 elements per slice. */
+psim_status psim_double_layer(const psim_peps_t *peps, const double *ops, psim_peps_t **out);
+
+/* Sequential measurement of every qubit in the computational basis, qubit 0
+ * first (main text: sequences of measurements on the stored state): with the
+ * prefix t_0..t_{k-1} drawn, qubit k is 0 when u[s * N + k] < p(t_0..t_{k-1}, 0)
+ * / (p(.., 0) + p(.., 1)), p being the double-layer value with |t><t| on the
+ * measured sites and I elsewhere (N = lv*lh double-layer contractions per call,
+ * each over all samples at once, planned with opts: precision, scheme,
+ * max_batch, memory budget).  u: host, n_samples * N numbers in [0, 1) (the
+ * caller's random numbers).  Writes bits (host, n_samples * N bytes) and, if
+ * out_prob is not NULL, p(bits) per sample (host, n_samples doubles).
+ * d_workspace: device memory of psim_sample_workspace bytes.
+ * Errors: EINVAL for NULL arguments, u outside [0, 1), a short workspace or a
+ * host-only opts; ENOMEM / EDEVICE as psim_plan / psim_amplitudes. */
+psim_status psim_sample_workspace(const psim_peps_t *peps, const psim_plan_opts *opts, uint64_t *bytes);
+psim_status psim_sample(const psim_peps_t *peps, const psim_plan_opts *opts, const double *u, size_t n_samples,
+                        void *d_workspace, size_t workspace_bytes, void *hip_stream, uint8_t *bits,
+                        double *out_prob);
+
 /* Plan the exact contraction (supplement S-II, Fig. S2(a)): sweep axis, leg
  * orders, v-slicing of the boundary for the memory budget, exact work count.
  * Unless PSIM_PLAN_HOST_ONLY is set, projects both values of every site

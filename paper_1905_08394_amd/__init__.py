@@ -25,7 +25,8 @@ PLAN_SPLIT_ACC = 2
 PLAN_GRAPH = 4
 EXPORTED = ("psim_build", "psim_peps_info", "psim_peps_free", "psim_plan", "psim_plan_info", "psim_plan_free",
             "psim_amplitudes", "psim_contract_site", "psim_tune", "psim_profile", "psim_group", "psim_group_info",
-            "psim_group_amplitudes", "psim_group_free", "psim_last_error", "psim_version")
+            "psim_group_amplitudes", "psim_group_free", "psim_double_layer", "psim_sample_workspace", "psim_sample",
+            "psim_last_error", "psim_version")
 KERNEL_CLASSES = ("first_site", "interior_site", "last_site", "rescale")
 
 
@@ -103,11 +104,15 @@ def lib(need_torch: bool = True) -> ctypes.CDLL:
                                         ctypes.POINTER(ctypes.POINTER(ctypes.c_double))]
     L.psim_group_free.argtypes = [vp]
     L.psim_group_free.restype = None
+    L.psim_double_layer.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(vp)]
+    L.psim_sample_workspace.argtypes = [vp, ctypes.POINTER(PlanOpts), ctypes.POINTER(u64)]
+    L.psim_sample.argtypes = [vp, ctypes.POINTER(PlanOpts), ctypes.POINTER(ctypes.c_double), sz, vp, sz, vp,
+                              ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_double)]
     L.psim_last_error.restype = ctypes.c_char_p
     L.psim_version.restype = ctypes.c_char_p
     for f in ("psim_build", "psim_peps_info", "psim_plan", "psim_plan_info", "psim_amplitudes",
               "psim_contract_site", "psim_profile", "psim_tune", "psim_group", "psim_group_info",
-              "psim_group_amplitudes"):
+              "psim_group_amplitudes", "psim_double_layer", "psim_sample_workspace", "psim_sample"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -145,6 +150,23 @@ class Peps:
         self._h = h
         self.lv, self.lh = circuit.lv, circuit.lh
 
+    @classmethod
+    def _wrap(cls, h, lv, lh):
+        obj = cls.__new__(cls)
+        obj._h, obj.lv, obj.lh = h, lv, lh
+        return obj
+
+    def double_layer(self, ops) -> "Peps":
+        """Double-layer network (psim_double_layer): ops has shape (lv*lh, 2,
+        2, 2) complex, ops[n, s] the operator of slice s at site n."""
+        o = np.ascontiguousarray(np.asarray(ops, dtype=np.complex128))
+        if o.shape != (self.lv * self.lh, 2, 2, 2):
+            raise ValueError(f"ops must have shape ({self.lv * self.lh}, 2, 2, 2)")
+        d = np.ascontiguousarray(o.view(np.float64).reshape(-1))
+        h = ctypes.c_void_p()
+        _check(lib().psim_double_layer(self._h, d.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(h)))
+        return Peps._wrap(h, self.lv, self.lh)
+
     def info(self):
         L = lib()
         nb = self.lv * (self.lh - 1) + (self.lv - 1) * self.lh
@@ -163,6 +185,52 @@ class Peps:
             self.close()
         except Exception:
             pass
+
+
+def expectation(peps: Peps, ops: dict, **plan_kw) -> complex:
+    """<psi| prod_n ops[n] |psi> for a dict {qubit: 2x2 matrix}: the
+    double-layer network with slice 0 = ops[n] (identity elsewhere), one
+    contraction of bitstring 0 (psim_double_layer, psim_plan,
+    psim_amplitudes; plan_kw as for Plan)."""
+    n = peps.lv * peps.lh
+    o = np.zeros((n, 2, 2, 2), dtype=np.complex128)
+    o[:, :] = np.eye(2)
+    for q, m in ops.items():
+        o[q, 0] = np.asarray(m, dtype=np.complex128)
+    dl = peps.double_layer(o)
+    plan = Plan(dl, **plan_kw)
+    try:
+        return complex(plan.amplitudes(np.zeros((1, n), dtype=np.uint8))[0])
+    finally:
+        plan.close()
+        dl.close()
+
+
+def _opts(prec="fp64", mem_budget=0, max_batch=1, sweep=0, device=0, graph=False, tile_cfg=0):
+    return PlanOpts(PREC[prec], PLAN_GRAPH if graph else 0, mem_budget, max_batch, sweep, device, tile_cfg)
+
+
+def sample(peps: Peps, u, stream=None, **plan_kw):
+    """Sequential measurement of every qubit (psim_sample) with the uniform
+    numbers u (shape (n_samples, lv*lh), in [0, 1)).  Returns (bits uint8
+    (n_samples, lv*lh), p(bits) per sample)."""
+    import torch
+    n = peps.lv * peps.lh
+    uu = np.ascontiguousarray(np.asarray(u, dtype=np.float64))
+    if uu.ndim != 2 or uu.shape[1] != n:
+        raise ValueError(f"u must have shape (n_samples, {n})")
+    o = _opts(**plan_kw)
+    need = ctypes.c_uint64()
+    _check(lib().psim_sample_workspace(peps._h, ctypes.byref(o), ctypes.byref(need)))
+    ws = torch.empty(max(int(need.value), 1), dtype=torch.uint8, device=f"cuda:{o.device}")
+    st = stream if stream is not None else torch.cuda.current_stream(o.device).cuda_stream
+    bits = np.zeros(uu.shape, dtype=np.uint8)
+    prob = np.zeros(uu.shape[0])
+    _check(lib().psim_sample(peps._h, ctypes.byref(o), uu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                             uu.shape[0], ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(st),
+                             bits.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                             prob.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return bits, prob
 
 
 class Plan:

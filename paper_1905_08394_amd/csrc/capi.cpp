@@ -83,6 +83,30 @@ psim_status psim_peps_info(const psim_peps_t* P, int32_t* lv, int32_t* lh, int32
 
 void psim_peps_free(psim_peps_t* P) { delete P; }
 
+psim_status psim_double_layer(const psim_peps_t* P, const double* ops, psim_peps_t** out) {
+  return guarded([&] {
+    if (!P || !out) fail(PSIM_EINVAL, "peps or out is NULL");
+    *out = double_layer(*P, ops);
+  });
+}
+
+psim_status psim_sample_workspace(const psim_peps_t* P, const psim_plan_opts* opts, uint64_t* bytes) {
+  return guarded([&] {
+    if (!P || !opts || !bytes) fail(PSIM_EINVAL, "peps, opts or bytes is NULL");
+    *bytes = sample_workspace(*P, *opts);
+  });
+}
+
+psim_status psim_sample(const psim_peps_t* P, const psim_plan_opts* opts, const double* u, size_t n_samples,
+                        void* d_workspace, size_t workspace_bytes, void* hip_stream, uint8_t* bits,
+                        double* out_prob) {
+  return guarded([&] {
+    if (!P || !opts) fail(PSIM_EINVAL, "peps or opts is NULL");
+    if (opts->flags & PSIM_PLAN_HOST_ONLY) fail(PSIM_EINVAL, "sampling needs a device plan");
+    sample(*P, *opts, u, n_samples, d_workspace, workspace_bytes, hip_stream, bits, out_prob);
+  });
+}
+
 psim_status psim_plan(const psim_peps_t* P, const psim_plan_opts* opts, psim_plan_t** out) {
   return guarded([&] {
     if (!out) fail(PSIM_EINVAL, "out is NULL");

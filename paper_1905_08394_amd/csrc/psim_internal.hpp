@@ -229,4 +229,10 @@ void launch_rescale_group(int prec, const RescaleJob* jobs, int n, void* stream)
 
 void hip_check(int err, const char* what);
 
+// measure.cpp: double-layer networks and sequential measurement
+psim_peps_t* double_layer(const psim_peps_t& P, const double* ops);
+uint64_t sample_workspace(const psim_peps_t& P, const psim_plan_opts& o);
+void sample(const psim_peps_t& P, const psim_plan_opts& o, const double* u, size_t n_samples, void* ws,
+            size_t ws_bytes, void* stream, uint8_t* bits, double* prob);
+
 }  // namespace psim

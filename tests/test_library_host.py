@@ -243,3 +243,48 @@ def test_square_plan_memory_budget(ps):
     many = ps.Plan(P, prec="fp32_3m", host_only=True, sweep=3, mem_budget=97 << 30, max_batch=16).stats()
     # extra Y tensors (8 GiB each) from what the budget leaves
     assert many["workspace_bytes"] - one["workspace_bytes"] == 6 * (8 << 30)
+
+
+def test_double_layer_host(ps):
+    """Double-layer network on the host: squared bonds, plan sizes of the
+    squared network, and the error paths (no device needed)."""
+    c = rqcgen.generate(3, 4, 13, 1)
+    P = ps.Peps(c)
+    n = 12
+    o = np.zeros((n, 2, 2, 2), dtype=complex)
+    o[:, :] = np.eye(2)
+    V = P.double_layer(o)
+    assert V.info()["bond_dims"] == [b * b for b in P.info()["bond_dims"]]
+    assert V.info()["chi"] == P.info()["chi"] ** 2
+    st = ps.Plan(V, prec="fp64", host_only=True).stats()
+    assert st["chi"] == P.info()["chi"] ** 2
+    bad = o.copy()
+    bad[3, 1, 0, 1] = np.inf
+    with pytest.raises(ps.PsimError) as e:
+        P.double_layer(bad)
+    assert e.value.status == ps.PSIM_EINVAL and "not finite" in str(e.value)
+    L = ps.lib()
+    out = ctypes.c_void_p()
+    assert L.psim_double_layer(P._h, None, ctypes.byref(out)) == ps.PSIM_EINVAL
+
+
+def test_sample_host_errors(ps):
+    c = rqcgen.generate(2, 2, 8, 0)
+    P = ps.Peps(c)
+    L = ps.lib()
+    o = ps._opts(max_batch=8)
+    need = ctypes.c_uint64()
+    assert L.psim_sample_workspace(P._h, ctypes.byref(o), ctypes.byref(need)) == ps.PSIM_OK
+    assert need.value > 0
+    u = np.full((2, 4), 0.5)
+    bits = np.zeros((2, 4), dtype=np.uint8)
+    PD = ctypes.POINTER(ctypes.c_double)
+    PU8 = ctypes.POINTER(ctypes.c_uint8)
+    host = ps._opts(max_batch=8)
+    host.flags = ps.PLAN_HOST_ONLY
+    st = L.psim_sample(P._h, ctypes.byref(host), u.ctypes.data_as(PD), 2, None, 0, None, bits.ctypes.data_as(PU8), None)
+    assert st == ps.PSIM_EINVAL and "device" in L.psim_last_error().decode()
+    u[1, 2] = 1.0  # outside [0, 1): rejected before any device work
+    st = L.psim_sample(P._h, ctypes.byref(o), u.ctypes.data_as(PD), 2, None, 0, None, bits.ctypes.data_as(PU8), None)
+    assert st == ps.PSIM_EINVAL and "not in [0, 1)" in L.psim_last_error().decode()
+    assert not bits.any()
