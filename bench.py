@@ -354,6 +354,88 @@ def mixed_program(args):
             "merged_launches_per_call": merged["grouped"], "all_bitwise_equal_to_per_plan": same}), flush=True)
 
 
+def measure_program(args):
+    """Observables and sequential measurement through the double-layer
+    network (psim_double_layer, psim_sample).  One double-layer PEPS with the
+    slices (Z, I) at every site gives every product of Z's in one batched
+    call: bitstring 0 at the sites the product covers, 1 elsewhere.
+    Square partition, FP64 by default.  4x5 (1+16+1) (20 qubits): all <Z_q>,
+    all nearest-neighbour <Z_a Z_b> and 512 sequential samples, against the
+    oracle's state vector (timed beside it); 6x6 (1+16+1) (36 qubits, beyond a
+    state vector): the same with 16 samples, checked by <psi|psi> = 1 and by
+    p(bits) of every sample against |<bits|psi>|^2 from the ordinary
+    amplitude path."""
+    import numpy as np
+    import torch
+    import paper_1905_08394_amd as ps
+    import rqcgen
+    torch.cuda.set_device(0)
+    Z = np.diag([1.0, -1.0]).astype(complex)
+    prec = args.prec if args.prec != "bf16x3" else "fp64"
+
+    def edges(lv, lh):
+        return [(r * lh + c, r * lh + c + 1) for r in range(lv) for c in range(lh - 1)] + \
+               [(r * lh + c, (r + 1) * lh + c) for r in range(lv - 1) for c in range(lh)]
+
+    sweep = args.sweep or 3
+    for lv, lh, d, S in ((4, 5, 16, 512), (6, 6, 16, 16)):
+        c = rqcgen.generate(lv, lh, d, 0)
+        n = lv * lh
+        P = ps.Peps(c)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o = np.zeros((n, 2, 2, 2), dtype=complex)
+        o[:, 0] = Z
+        o[:, 1] = np.eye(2)
+        V = P.double_layer(o)
+        E = edges(lv, lh)
+        q = np.ones((1 + n + len(E), n), dtype=np.uint8)
+        for k in range(n):
+            q[1 + k, k] = 0
+        for k, (a, b) in enumerate(E):
+            q[1 + n + k, [a, b]] = 0
+        plan = ps.Plan(V, prec=prec, max_batch=len(q), sweep=sweep)
+        vals = plan.amplitudes(q)
+        plan.close()
+        torch.cuda.synchronize()
+        t_obs = time.perf_counter() - t0
+        norm = vals[0].real  # bitstring of all ones: identity everywhere
+        zq, zz = vals[1:1 + n].real, vals[1 + n:].real
+        u = np.random.default_rng(11).random((S, n))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bits, prob = ps.sample(P, u, prec=prec, sweep=sweep, max_batch=2 * S)
+        torch.cuda.synchronize()
+        t_smp = time.perf_counter() - t0
+        out = {"workload": f"{lv}x{lh} (1+{d}+1), seed 0", "prec": prec, "scheme": "square partition" if sweep == 3
+               else "row scheme", "double_layer_bond": int(V.info()["chi"]),
+               "observables": {"count": len(q), "seconds": t_obs, "norm_minus_1": float(norm - 1)},
+               "sampling": {"samples": S, "seconds": t_smp, "samples_per_s": S / t_smp,
+                            "contractions": n, "bitstrings_per_contraction": 2 * S}}
+        if n <= 20:
+            from oracle import measure as om
+            from oracle import statevector as sv
+            t0 = time.perf_counter()
+            psi = sv.run(c)
+            ref_z = np.array([om.expectation(psi, {k: Z}).real for k in range(n)])
+            ref_zz = np.array([om.expectation(psi, {a: Z, b: Z}).real for a, b in E])
+            t_cpu_obs = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            obits, oprob = om.sample_sequential(psi, u)
+            t_cpu_smp = time.perf_counter() - t0
+            out["vs_oracle"] = {"max_abs_err_z": float(np.max(np.abs(zq - ref_z))),
+                                "max_abs_err_zz": float(np.max(np.abs(zz - ref_zz))),
+                                "samples_identical": int(np.sum(np.all(bits == obits, axis=1))),
+                                "max_rel_err_prob": float(np.max(np.abs(prob - oprob) / oprob)),
+                                "cpu_seconds_observables": t_cpu_obs, "cpu_seconds_sampling": t_cpu_smp}
+        else:
+            amp = ps.Plan(P, prec="fp64", max_batch=S).amplitudes(bits)
+            out["check"] = {"max_rel_err_prob_vs_amplitude_path": float(np.max(np.abs(prob - np.abs(amp) ** 2)
+                                                                             / np.abs(amp) ** 2))}
+        out["mean_z"] = float(np.mean(zq))
+        print(json.dumps(out), flush=True)
+
+
 def small_configs_program(args):
     """The smaller lattices of the parity suite timed through the library:
     3x3 (1+8+1) all 512 amplitudes, 4x5 (1+24+1) 64 random bitstrings for each
@@ -432,7 +514,13 @@ def main():
     ap.add_argument("--sweep", type=int, default=0, help="--fig2: 0 row scheme, 3 square partition")
     ap.add_argument("--mixed", action="store_true", help="mixed batches of 3x3..6x6 circuits, grouped vs per plan")
     ap.add_argument("--small-configs", action="store_true", help="3x3, 4x5 and 5x5 parity workloads, timed")
+    ap.add_argument("--measure", action="store_true",
+                    help="observables and sequential measurement through the double-layer network")
     args = ap.parse_args()
+    if args.measure:
+        args.prec = "fp64" if args.prec == "fp32_3m" and "--prec" not in sys.argv else args.prec
+        measure_program(args)
+        return
     if args.small_configs:
         small_configs_program(args)
         return
