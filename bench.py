@@ -278,6 +278,41 @@ def fig2_program(args):
                                         for m, h in zip(mids, hist)]}), flush=True)
 
 
+def fast_sampling_program(args):
+    """The fast-sampling reuse of the square partition (supplement S-II, the
+    remark on sampling in one partition while the other regions' results are
+    reused): 8x8 (1+25+1), one random bitstring and 4096 variants of it with
+    random lower-right quadrants (16 qubits), against 4096 independent random
+    bitstrings; seconds per amplitude of each."""
+    import numpy as np
+    import torch
+    import paper_1905_08394_amd as ps
+    import rqcgen
+    torch.cuda.set_device(0)
+    c = rqcgen.generate(8, 8, 25, 0)
+    n = 4096
+    base = rqcgen.bitstrings(8, 8, 3, 1)[0]
+    lr = [r * 8 + col for r in range(4, 8) for col in range(4, 8)]
+    fast = np.repeat(base[None, :], n, axis=0)
+    fast[:, lr] = np.random.default_rng(5).integers(0, 2, size=(n, len(lr)), dtype=np.uint8)
+    rand = rqcgen.bitstrings(8, 8, 7, n)
+    plan = ps.Plan(ps.Peps(c), prec=args.prec, max_batch=512, mem_budget=(args.mem_gib or 64) << 30, sweep=3)
+    plan.workspace()
+    plan.amplitudes(rand[:16])
+    out = {"workload": f"8x8 (1+25+1), seed 0, {n} bitstrings", "prec": args.prec, "scheme": "square partition"}
+    for name, bits in (("lower_right_variants", fast), ("random", rand)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s0 in range(0, n, 512):
+            plan.amplitudes(bits[s0:s0 + 512])
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        out[name] = {"seconds": t, "s_per_amplitude": t / n}
+        log(f"fast sampling {name}: {t:.2f}s")
+    out["speedup"] = out["random"]["seconds"] / out["lower_right_variants"]["seconds"]
+    print(json.dumps(out), flush=True)
+
+
 # Mixed batches: (lv, lh, depth) of circuits with uneven lattices and depths,
 # seed = position in the list, a fixed number of random bitstrings each.
 # "large": 3x3 .. 6x6 up to depth (1+24+1), 64 bitstrings each (the 6x6 d24
@@ -514,9 +549,14 @@ def main():
     ap.add_argument("--sweep", type=int, default=0, help="--fig2: 0 row scheme, 3 square partition")
     ap.add_argument("--mixed", action="store_true", help="mixed batches of 3x3..6x6 circuits, grouped vs per plan")
     ap.add_argument("--small-configs", action="store_true", help="3x3, 4x5 and 5x5 parity workloads, timed")
+    ap.add_argument("--fast-sampling", action="store_true",
+                    help="square partition: bitstrings differing in one quadrant vs random ones (8x8 (1+25+1))")
     ap.add_argument("--measure", action="store_true",
                     help="observables and sequential measurement through the double-layer network")
     args = ap.parse_args()
+    if args.fast_sampling:
+        fast_sampling_program(args)
+        return
     if args.measure:
         args.prec = "fp64" if args.prec == "fp32_3m" and "--prec" not in sys.argv else args.prec
         measure_program(args)

@@ -623,7 +623,10 @@ namespace {
 // sq->chunk.  Per chunk, each quadrant's distinct patterns are contracted
 // together (the pattern is the node index of every launch), then one join per
 // distinct (UL, UR) pair (T) and per distinct (pair, LL) (Y), then one inner
-// product per distinct (Y, LR).  Each tensor is computed by the same kernel
+// product per distinct (Y, LR); a chunk whose (UL, UR) pairs, and (UL, UR,
+// LL) triples, were all in the previous chunk reuses its T, and Y, tensors
+// (bitstrings that differ only in the lower quadrants: the fast-sampling
+// reuse of the square partition).  Each tensor is computed by the same kernel
 // body on the same tiles as in the one-by-one form (the joins of a chunk in
 // one grouped launch where the kernel has a grouped form), so the results
 // are the same bit for bit.
@@ -646,25 +649,43 @@ void run_chunks(SqRun& R, const uint8_t* bits, const std::vector<size_t>& order,
   uint8_t* d_tau = (uint8_t*)R.buf(sq->boff_tau);
   std::vector<std::vector<uint8_t>> uploads;  // host copies stay alive until the final flush
   using Key = std::vector<uint8_t>;
+  using Pair = std::pair<Key, Key>;     // (UL, UR) patterns
+  using Tri = std::array<Key, 3>;       // (UL, UR, LL) patterns
+  // T and Y tensors left in their stores by the previous chunk; a chunk all
+  // of whose pairs (triples) are among them reuses them instead of
+  // recomputing (bitstrings that differ only in the lower quadrants)
+  std::map<Pair, int> t_of;
+  std::vector<SqRun::Exp> eT;
+  std::map<Tri, int> y_of;
+  std::vector<SqRun::Exp> eY;
   for (size_t c0 = 0; c0 < n; c0 += (size_t)sq->chunk) {
     const size_t c1 = std::min(n, c0 + (size_t)sq->chunk);
-    // distinct patterns of each quadrant in the chunk
+    std::vector<std::array<Key, 4>> kq(c1 - c0);
+    for (size_t z = c0; z < c1; ++z)
+      for (int qi = 0; qi < 4; ++qi)
+        kq[z - c0][qi] = Key(keys[order[z]].begin() + koff[qi], keys[order[z]].begin() + koff[qi + 1]);
+    bool new_t = false, new_y = false;
+    for (const auto& k : kq) {
+      new_t = new_t || !t_of.count(Pair(k[0], k[1]));
+      new_y = new_y || !y_of.count(Tri{k[0], k[1], k[2]});
+    }
+    new_y = new_y || new_t;
+    // distinct patterns of the quadrants to contract
+    const bool need[4] = {new_t, new_t, new_y, true};
     std::map<Key, int> pid[4];
-    std::vector<std::array<int, 4>> bp(c1 - c0);
     std::vector<size_t> rep[4];  // a bitstring of each pattern
-    for (size_t z = c0; z < c1; ++z) {
-      const Key& k = keys[order[z]];
+    std::vector<std::array<int, 4>> bp(c1 - c0, std::array<int, 4>{-1, -1, -1, -1});
+    for (size_t z = c0; z < c1; ++z)
       for (int qi = 0; qi < 4; ++qi) {
-        Key part(k.begin() + koff[qi], k.begin() + koff[qi + 1]);
-        auto it = pid[qi].find(part);
+        if (!need[qi]) continue;
+        auto it = pid[qi].find(kq[z - c0][qi]);
         if (it == pid[qi].end()) {
-          it = pid[qi].emplace(std::move(part), (int)rep[qi].size()).first;
+          it = pid[qi].emplace(kq[z - c0][qi], (int)rep[qi].size()).first;
           rep[qi].push_back(order[z]);
         }
         bp[z - c0][qi] = it->second;
       }
-    }
-    // bits of every pattern in frame order, all four quadrants in one upload
+    // bits of every pattern in frame order, the quadrants to contract in one upload
     uploads.emplace_back();
     std::vector<uint8_t>& tab = uploads.back();
     size_t toff[4];
@@ -686,58 +707,78 @@ void run_chunks(SqRun& R, const uint8_t* bits, const std::vector<size_t>& order,
       return R.quad_nodes(qi, (int64_t)rep[qi].size(), d_tau + toff[qi], run0, run1, R.buf(sq->boff_q[qi]));
     };
     auto qptr = [&](int qi, int p) { return R.buf(sq->boff_q[qi]) + (uint64_t)p * qsz[qi] * eb; };
-    // upper half: T per distinct (UL, UR)
-    const std::vector<int64_t> sUL = quad(0), sUR = quad(1);
-    const int64_t nUL = (int64_t)rep[0].size();
-    R.pack(qptr(0, 0), R.buf(sq->boff_pk[0]), vUL, hU, sq->prow[0], sq->pld[0], nUL);
-    std::map<std::pair<int, int>, int> pair_id;
-    std::vector<std::pair<int, int>> pairs;
-    for (const auto& b : bp)
-      if (pair_id.emplace(std::make_pair(b[0], b[1]), (int)pairs.size()).second) pairs.emplace_back(b[0], b[1]);
+    auto pattern_exp = [&](int qi, int p, const std::vector<int64_t>& row_slot) {
+      SqRun::Exp e;
+      e.host = host_e[qi][p];
+      for (int64_t x : row_slot) e.slots.push_back(x + p);
+      return e;
+    };
     std::vector<GemmLaunch> gl;
-    for (size_t t = 0; t < pairs.size(); ++t)
-      gl.push_back(SqRun::join_launch(
-          R.prec, qptr(1, pairs[t].second), vUR, hU,
-          R.buf(sq->boff_pk[0]) + (uint64_t)pairs[t].first * sq->prow[0] * sq->pld[0] * rb, sq->pld[0], vUL,
-          Tst + (uint64_t)t * vUR * vUL * eb));
-    R.joins(gl, R.buf(sq->boff_desc[0]), uploads);
-    const int64_t sT = R.rescale_nodes(Tst, vUR * vUL, (int64_t)pairs.size());
-    // lower-left: Y per distinct (pair, LL)
-    const std::vector<int64_t> sLL = quad(2);
-    R.pack(qptr(2, 0), R.buf(sq->boff_pk[1]), hL, vUL, sq->prow[1], sq->pld[1], (int64_t)rep[2].size());
-    std::map<std::pair<int, int>, int> tri_id;
-    std::vector<std::pair<int, int>> tris;  // (pair, LL)
-    for (const auto& b : bp) {
-      const int pr = pair_id[std::make_pair(b[0], b[1])];
-      if (tri_id.emplace(std::make_pair(pr, b[2]), (int)tris.size()).second) tris.emplace_back(pr, b[2]);
+    if (new_t) {
+      // upper half: T per distinct (UL, UR)
+      const std::vector<int64_t> sUL = quad(0), sUR = quad(1);
+      R.pack(qptr(0, 0), R.buf(sq->boff_pk[0]), vUL, hU, sq->prow[0], sq->pld[0], (int64_t)rep[0].size());
+      t_of.clear();
+      eT.clear();
+      std::vector<std::pair<int, int>> pairs;
+      for (size_t z = c0; z < c1; ++z) {
+        const auto& b = bp[z - c0];
+        if (t_of.emplace(Pair(kq[z - c0][0], kq[z - c0][1]), (int)pairs.size()).second) {
+          pairs.emplace_back(b[0], b[1]);
+          SqRun::Exp e = pattern_exp(0, b[0], sUL);
+          e += pattern_exp(1, b[1], sUR);
+          eT.push_back(e);
+        }
+      }
+      for (size_t t = 0; t < pairs.size(); ++t)
+        gl.push_back(SqRun::join_launch(
+            R.prec, qptr(1, pairs[t].second), vUR, hU,
+            R.buf(sq->boff_pk[0]) + (uint64_t)pairs[t].first * sq->prow[0] * sq->pld[0] * rb, sq->pld[0], vUL,
+            Tst + (uint64_t)t * vUR * vUL * eb));
+      R.joins(gl, R.buf(sq->boff_desc[0]), uploads);
+      const int64_t sT = R.rescale_nodes(Tst, vUR * vUL, (int64_t)pairs.size());
+      for (size_t t = 0; t < pairs.size(); ++t) eT[t].slots.push_back(sT + (int64_t)t);
     }
-    gl.clear();
-    for (size_t t = 0; t < tris.size(); ++t)
-      gl.push_back(SqRun::join_launch(
-          R.prec, Tst + (uint64_t)tris[t].first * vUR * vUL * eb, vUR, vUL,
-          R.buf(sq->boff_pk[1]) + (uint64_t)tris[t].second * sq->prow[1] * sq->pld[1] * rb, sq->pld[1], hL,
-          Yst + (uint64_t)t * vUR * hL * eb));
-    R.joins(gl, R.buf(sq->boff_desc[1]), uploads);
-    const int64_t sY = R.rescale_nodes(Yst, vUR * hL, (int64_t)tris.size());
+    if (new_y) {
+      // lower-left: Y per distinct (pair, LL)
+      const std::vector<int64_t> sLL = quad(2);
+      R.pack(qptr(2, 0), R.buf(sq->boff_pk[1]), hL, vUL, sq->prow[1], sq->pld[1], (int64_t)rep[2].size());
+      y_of.clear();
+      eY.clear();
+      std::vector<std::pair<int, int>> tris;  // (T index, LL pattern)
+      for (size_t z = c0; z < c1; ++z) {
+        const auto& k = kq[z - c0];
+        const int ti = t_of.at(Pair(k[0], k[1]));
+        if (y_of.emplace(Tri{k[0], k[1], k[2]}, (int)tris.size()).second) {
+          tris.emplace_back(ti, bp[z - c0][2]);
+          SqRun::Exp e = eT[ti];
+          e += pattern_exp(2, bp[z - c0][2], sLL);
+          eY.push_back(e);
+        }
+      }
+      gl.clear();
+      for (size_t t = 0; t < tris.size(); ++t)
+        gl.push_back(SqRun::join_launch(
+            R.prec, Tst + (uint64_t)tris[t].first * vUR * vUL * eb, vUR, vUL,
+            R.buf(sq->boff_pk[1]) + (uint64_t)tris[t].second * sq->prow[1] * sq->pld[1] * rb, sq->pld[1], hL,
+            Yst + (uint64_t)t * vUR * hL * eb));
+      R.joins(gl, R.buf(sq->boff_desc[1]), uploads);
+      const int64_t sY = R.rescale_nodes(Yst, vUR * hL, (int64_t)tris.size());
+      for (size_t t = 0; t < tris.size(); ++t) eY[t].slots.push_back(sY + (int64_t)t);
+    }
     // lower-right, then one inner product per distinct (Y, LR)
     const std::vector<int64_t> sLR = quad(3);
     std::map<std::pair<int, int>, int64_t> dot_id;
     for (size_t z = c0; z < c1; ++z) {
-      const auto& b = bp[z - c0];
-      const int pr = pair_id[std::make_pair(b[0], b[1])];
-      const int tr = tri_id[std::make_pair(pr, b[2])];
-      auto it = dot_id.find(std::make_pair(tr, b[3]));
+      const auto& k = kq[z - c0];
+      const int lr = bp[z - c0][3];
+      const int yi = y_of.at(Tri{k[0], k[1], k[2]});
+      auto it = dot_id.find(std::make_pair(yi, lr));
       if (it == dot_id.end())
-        it = dot_id.emplace(std::make_pair(tr, b[3]),
-                            R.dot(Yst + (uint64_t)tr * vUR * hL * eb, qptr(3, b[3]), vUR * hL)).first;
-      SqRun::Pend p{order[z], it->second, {}};
-      p.e.host = host_e[0][b[0]] + host_e[1][b[1]] + host_e[2][b[2]] + host_e[3][b[3]];
-      for (int64_t x : sUL) p.e.slots.push_back(x + b[0]);
-      for (int64_t x : sUR) p.e.slots.push_back(x + b[1]);
-      p.e.slots.push_back(sT + pr);
-      for (int64_t x : sLL) p.e.slots.push_back(x + b[2]);
-      p.e.slots.push_back(sY + tr);
-      for (int64_t x : sLR) p.e.slots.push_back(x + b[3]);
+        it = dot_id.emplace(std::make_pair(yi, lr),
+                            R.dot(Yst + (uint64_t)yi * vUR * hL * eb, qptr(3, lr), vUR * hL)).first;
+      SqRun::Pend p{order[z], it->second, eY[yi]};
+      p.e += pattern_exp(3, lr, sLR);
       R.pend.push_back(std::move(p));
     }
   }

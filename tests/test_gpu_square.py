@@ -168,8 +168,10 @@ def test_square_chunks_match_one_by_one(ps, prec, lv, lh, d, seed):
     prof = chunked.profile_read()
     chunked.profile_stop()
     assert np.array_equal(a1, a2), np.max(np.abs(a1 - a2))
-    # every quadrant site contracted once per chunk: 3 chunks x all sites
-    assert prof["first_site"]["launches"] == 3 * lv * lh, prof["first_site"]
+    # each quadrant's sites once per chunk (3 chunks), the upper and
+    # lower-left ones only where a chunk cannot reuse the previous T / Y
+    n_lr = (lv - lv // 2) * (lh - lh // 2)
+    assert lv * lh + 2 * n_lr <= prof["first_site"]["launches"] <= 3 * lv * lh, prof["first_site"]
     ref = sv.amplitudes(sv.run(c), bits)
     e = _eps_rms(a2, ref, lv * lh)
     say(f"square chunks {lv}x{lh} d{d} {prec}: bitwise equal to one by one, max eps_rms {e.max():.2e}")
@@ -192,3 +194,32 @@ def test_square_chunk_budget_and_repeat_calls(ps):
     assert np.array_equal(a, small.amplitudes(bits))
     assert np.array_equal(full.amplitudes(bits[7:20]), a[7:20])
     assert np.array_equal(full.amplitudes(bits), a)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_3m"])
+def test_square_fast_sampling_reuse(ps, prec):
+    """Bitstrings that differ only in the lower-right quadrant (the
+    fast-sampling case): the first chunk contracts T and Y, the next two
+    reuse them (2 join launches in all, lower-right sites only after the
+    first chunk); bit for bit equal to one by one, and the state vector."""
+    c = rqcgen.generate(4, 5, 16, 7)
+    base = rqcgen.bitstrings(4, 5, 7, 1)[0]
+    lr = [12, 13, 14, 17, 18, 19]              # rows 2-3, columns 2-4
+    vals = rqcgen.all_bitstrings(6)
+    bits = np.repeat(base[None, :], 75, axis=0)
+    bits[:64, lr] = vals
+    bits[64:, lr] = vals[5:16]                 # repeats
+    P = ps.Peps(c)
+    one = ps.Plan(P, prec=prec, sweep=3, max_batch=1)
+    chunked = ps.Plan(P, prec=prec, sweep=3, max_batch=len(bits))
+    chunked.profile_start()
+    a2 = chunked.amplitudes(bits)
+    prof = chunked.profile_read()
+    chunked.profile_stop()
+    assert np.array_equal(one.amplitudes(bits), a2)
+    assert prof["interior_site"]["launches"] == 2, prof["interior_site"]
+    assert prof["first_site"]["launches"] == 20 + 2 * 6, prof["first_site"]
+    ref = sv.amplitudes(sv.run(c), bits)
+    e = _eps_rms(a2, ref, 20)
+    say(f"square fast sampling 4x5 d16 {prec}: max eps_rms {e.max():.2e}")
+    assert e.max() <= AMP_BAR[prec]
