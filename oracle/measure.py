@@ -2,9 +2,12 @@
 definitions the double-layer contractions must reproduce (test
 infrastructure only, like the rest of oracle/).
 
-The main text notes that the simulator keeps the whole state, so it yields
-expectation values and sequences of measurements besides single amplitudes.
-Written out on the state vector psi (shape (2,)*N, axis n = qubit n):
+The main text (the remark after eq. 7, and the conclusions) notes that the
+simulator keeps the whole state, so it yields expectation values and
+sequences of measurements besides single amplitudes: measure one qubit
+(probabilities of |0> and |1>), project a copy of the state on the outcome,
+measure the next qubit, and so on.  Written out on the state vector psi
+(shape (2,)*N, axis n = qubit n):
   <psi| prod_n O_n |psi>                 one-qubit operators on any sites;
   p(t_S) = sum over the other qubits of |psi|^2 with qubits S fixed to t_S;
   sequential measurement, qubit 0 first: qubit k is 0 when the caller's
@@ -17,7 +20,8 @@ from .statevector import apply_1q
 
 
 def expectation(psi: np.ndarray, ops: dict) -> complex:
-    """<psi| prod_n ops[n] |psi> for a dict {qubit: 2x2 matrix}."""
+    """<psi| prod_n ops[n] |psi> for a dict {qubit: 2x2 matrix} (conclusions:
+    expectation values of the stored state)."""
     phi = psi
     for q, o in ops.items():
         phi = apply_1q(phi, np.asarray(o, dtype=np.complex128), q)
@@ -25,7 +29,8 @@ def expectation(psi: np.ndarray, ops: dict) -> complex:
 
 
 def marginal(psi: np.ndarray, qubits, values) -> float:
-    """Probability that measuring the given qubits yields the given values."""
+    """Probability that measuring the given qubits yields the given values
+    (the probabilities the remark after eq. 7 computes qubit by qubit)."""
     p = np.abs(psi) ** 2
     idx = [slice(None)] * psi.ndim
     for q, v in zip(qubits, values):
@@ -35,7 +40,8 @@ def marginal(psi: np.ndarray, qubits, values) -> float:
 
 def sample_sequential(psi: np.ndarray, u: np.ndarray):
     """Bitstrings drawn qubit by qubit with the given uniforms u (shape
-    (S, N)); returns (bits (S, N) uint8, p(bits) per sample)."""
+    (S, N)), the measured qubit projected before the next is measured (the
+    remark after eq. 7); returns (bits (S, N) uint8, p(bits) per sample)."""
     u = np.asarray(u, dtype=np.float64)
     S, N = u.shape
     p_all = np.abs(psi) ** 2
