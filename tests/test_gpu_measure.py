@@ -124,3 +124,15 @@ def test_sequential_measurement(ps, lv, lh, d, seed, prec, sweep):
     assert np.allclose(prob, p_all[tuple(bits.T)], rtol=rtol, atol=atol)
     say(f"sample {lv}x{lh} d{d} {prec} sweep {sweep}: {len(u) - mism}/{len(u)} identical to the oracle")
     assert mism <= 2
+
+
+def test_sample_zero_samples_and_repeat(ps):
+    """No samples: nothing written; the same uniforms twice: the same bits."""
+    c = rqcgen.generate(3, 3, 8, 4)
+    P = ps.Peps(c)
+    bits, prob = ps.sample(P, np.zeros((0, 9)), prec="fp64")
+    assert bits.shape == (0, 9) and prob.shape == (0,)
+    u = np.random.default_rng(8).random((16, 9))
+    b1, p1 = ps.sample(P, u, prec="fp64", max_batch=32)
+    b2, p2 = ps.sample(P, u, prec="fp64", max_batch=32)
+    assert np.array_equal(b1, b2) and np.array_equal(p1, p2)

@@ -223,3 +223,17 @@ def test_square_fast_sampling_reuse(ps, prec):
     e = _eps_rms(a2, ref, 20)
     say(f"square fast sampling 4x5 d16 {prec}: max eps_rms {e.max():.2e}")
     assert e.max() <= AMP_BAR[prec]
+
+
+def test_square_empty_and_single(ps):
+    """No bitstrings: nothing to do, an empty result; one bitstring in a
+    chunked plan equals the one-by-one form."""
+    c = rqcgen.generate(4, 4, 16, 9)
+    P = ps.Peps(c)
+    for mb in (1, 64):
+        pl = ps.Plan(P, prec="fp32_3m", sweep=3, max_batch=mb)
+        assert pl.amplitudes(np.zeros((0, 16), dtype=np.uint8)).size == 0
+    b = rqcgen.bitstrings(4, 4, 9, 1)
+    a1 = ps.Plan(P, prec="fp32_3m", sweep=3, max_batch=1).amplitudes(b)
+    a2 = ps.Plan(P, prec="fp32_3m", sweep=3, max_batch=64).amplitudes(b)
+    assert np.array_equal(a1, a2)
