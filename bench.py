@@ -109,8 +109,12 @@ def golden_errors(bits, amps, lattice, depth):
     r = ref[idx]
     d = np.abs(amps - r)
     n = lattice * lattice
+    # every amplitude's error, with x = 2^N |a_ref|^2 beside it (Porter-Thomas
+    # tail amplitudes, x << 1, stay visible)
     return {"max_eps_rel": float(np.max(d / np.abs(r))), "median_eps_rel": float(np.median(d / np.abs(r))),
-            "max_eps_rms": float(np.max(d) * 2 ** (n / 2)), "n": int(len(r))}
+            "max_eps_rms": float(np.max(d) * 2 ** (n / 2)), "n": int(len(r)),
+            "eps_rel": [float("%.3e" % v) for v in d / np.abs(r)],
+            "x": [float("%.4g" % v) for v in np.abs(r) ** 2 * 2.0 ** n]}
 
 
 def cpu_baseline(circuit, bits, target_seconds):
