@@ -125,6 +125,19 @@ psim_status psim_peps_info(const psim_peps_t *peps, int32_t *lv, int32_t *lh, in
 
 void psim_peps_free(psim_peps_t *peps);
 
+/* More gates on a built (possibly projected) PEPS, in array order, with the
+ * rules of psim_build (the remark after eq. 7: gates may be applied between
+ * measurements).  All or nothing: on an error the PEPS is unchanged. */
+psim_status psim_apply(psim_peps_t *peps, const psim_gate *gates, size_t n_gates);
+
+/* Records a measurement outcome: qubit's state projected on |value>
+ * (A_q[s] = 0 for s != value), without renormalising, so the squared norm
+ * becomes the outcome's probability times the previous squared norm, and
+ * double-layer values of the result are unnormalised (divide by the
+ * all-identity value for conditional ones).  Errors: EINVAL for a bad qubit
+ * or a value other than 0 / 1. */
+psim_status psim_project(psim_peps_t *peps, int32_t qubit, int32_t value);
+
 /* Double-layer network of a PEPS (main text: observables of the stored
  * state): the norm network <psi|psi> with a one-qubit operator between the
  * bra and ket layers of every site, returned as a PEPS whose bonds are the

@@ -38,6 +38,17 @@ def marginal(psi: np.ndarray, qubits, values) -> float:
     return float(np.sum(p[tuple(idx)]))
 
 
+def project(psi: np.ndarray, qubit: int, value: int) -> np.ndarray:
+    """The state after measuring qubit with outcome value, unnormalised
+    (the copy projected on the outcome in the remark after eq. 7): entries
+    whose qubit differs from value set to zero."""
+    out = np.array(psi, copy=True)
+    idx = [slice(None)] * psi.ndim
+    idx[qubit] = 1 - int(value)
+    out[tuple(idx)] = 0
+    return out
+
+
 def sample_sequential(psi: np.ndarray, u: np.ndarray):
     """Bitstrings drawn qubit by qubit with the given uniforms u (shape
     (S, N)), the measured qubit projected before the next is measured (the

@@ -25,7 +25,8 @@ PLAN_SPLIT_ACC = 2
 PLAN_GRAPH = 4
 EXPORTED = ("psim_build", "psim_peps_info", "psim_peps_free", "psim_plan", "psim_plan_info", "psim_plan_free",
             "psim_amplitudes", "psim_contract_site", "psim_tune", "psim_profile", "psim_group", "psim_group_info",
-            "psim_group_amplitudes", "psim_group_free", "psim_double_layer", "psim_sample_workspace", "psim_sample",
+            "psim_group_amplitudes", "psim_group_free", "psim_apply", "psim_project", "psim_double_layer",
+            "psim_sample_workspace", "psim_sample",
             "psim_last_error", "psim_version")
 KERNEL_CLASSES = ("first_site", "interior_site", "last_site", "rescale")
 
@@ -104,6 +105,8 @@ def lib(need_torch: bool = True) -> ctypes.CDLL:
                                         ctypes.POINTER(ctypes.POINTER(ctypes.c_double))]
     L.psim_group_free.argtypes = [vp]
     L.psim_group_free.restype = None
+    L.psim_apply.argtypes = [vp, ctypes.POINTER(_Gate), sz]
+    L.psim_project.argtypes = [vp, i32, i32]
     L.psim_double_layer.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(vp)]
     L.psim_sample_workspace.argtypes = [vp, ctypes.POINTER(PlanOpts), ctypes.POINTER(u64)]
     L.psim_sample.argtypes = [vp, ctypes.POINTER(PlanOpts), ctypes.POINTER(ctypes.c_double), sz, vp, sz, vp,
@@ -112,7 +115,8 @@ def lib(need_torch: bool = True) -> ctypes.CDLL:
     L.psim_version.restype = ctypes.c_char_p
     for f in ("psim_build", "psim_peps_info", "psim_plan", "psim_plan_info", "psim_amplitudes",
               "psim_contract_site", "psim_profile", "psim_tune", "psim_group", "psim_group_info",
-              "psim_group_amplitudes", "psim_double_layer", "psim_sample_workspace", "psim_sample"):
+              "psim_group_amplitudes", "psim_apply", "psim_project", "psim_double_layer", "psim_sample_workspace",
+              "psim_sample"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -155,6 +159,20 @@ class Peps:
         obj = cls.__new__(cls)
         obj._h, obj.lv, obj.lh = h, lv, lh
         return obj
+
+    def apply(self, gates):
+        """More gates (rqcgen.Gate objects, or a circuit's .gates) on this
+        state (psim_apply)."""
+        class _C:
+            pass
+        c = _C()
+        c.gates = list(gates)
+        arr, n, keep = _c_gates(c)
+        _check(lib().psim_apply(self._h, arr, n))
+
+    def project(self, qubit: int, value: int):
+        """Record the outcome |value> of measuring qubit (psim_project; unnormalised)."""
+        _check(lib().psim_project(self._h, int(qubit), int(value)))
 
     def double_layer(self, ops) -> "Peps":
         """Double-layer network (psim_double_layer): ops has shape (lv*lh, 2,

@@ -213,6 +213,28 @@ void apply_2q(psim_peps_t& P, int kind, const double* m, int q0, int q1) {
 
 using namespace psim;
 
+// Gates in array order on an existing PEPS (eqs. 3-6).
+static void apply_gates(psim_peps_t& P, const psim_gate* gates, size_t n_gates) {
+  if (n_gates && !gates) fail(PSIM_EINVAL, "gates is NULL");
+  const int n = P.lv * P.lh;
+  int last_cycle = INT32_MIN;
+  for (size_t g = 0; g < n_gates; ++g) {
+    const psim_gate& G = gates[g];
+    if (G.cycle < last_cycle) fail(PSIM_EINVAL, "gate cycles must be non-decreasing");
+    last_cycle = G.cycle;
+    if (G.q0 < 0 || G.q0 >= n) fail(PSIM_EINVAL, "gate " + std::to_string(g) + ": qubit out of range");
+    if (is_two_qubit(G.kind)) {
+      if (G.q1 < 0 || G.q1 >= n || G.q1 == G.q0)
+        fail(PSIM_EINVAL, "gate " + std::to_string(g) + ": bad second qubit");
+      apply_2q(P, G.kind, G.m, G.q0, G.q1);
+    } else {
+      cd U[4];
+      gate_matrix_1q(G.kind, G.m, U);
+      apply_1q(P.sites[G.q0], U);
+    }
+  }
+}
+
 psim_peps_t* build_peps(int32_t lv, int32_t lh, const psim_gate* gates, size_t n_gates) {
   if (lv < 1 || lh < 1 || (int64_t)lv * lh > 4096) fail(PSIM_EINVAL, "lattice size out of range");
   if (n_gates && !gates) fail(PSIM_EINVAL, "gates is NULL");
@@ -226,25 +248,29 @@ psim_peps_t* build_peps(int32_t lv, int32_t lh, const psim_gate* gates, size_t n
     s.t[0] = 1.0;  // |0>
   }
   try {
-    int last_cycle = INT32_MIN;
-    for (size_t g = 0; g < n_gates; ++g) {
-      const psim_gate& G = gates[g];
-      if (G.cycle < last_cycle) fail(PSIM_EINVAL, "gate cycles must be non-decreasing");
-      last_cycle = G.cycle;
-      if (G.q0 < 0 || G.q0 >= n) fail(PSIM_EINVAL, "gate " + std::to_string(g) + ": qubit out of range");
-      if (is_two_qubit(G.kind)) {
-        if (G.q1 < 0 || G.q1 >= n || G.q1 == G.q0)
-          fail(PSIM_EINVAL, "gate " + std::to_string(g) + ": bad second qubit");
-        apply_2q(*P, G.kind, G.m, G.q0, G.q1);
-      } else {
-        cd U[4];
-        gate_matrix_1q(G.kind, G.m, U);
-        apply_1q(P->sites[G.q0], U);
-      }
-    }
+    apply_gates(*P, gates, n_gates);
   } catch (...) {
     delete P;
     throw;
   }
   return P;
+}
+
+// More gates on an existing state (the remark after eq. 7: gates may follow
+// a measurement); applied to a copy, so a failing gate leaves P unchanged.
+void apply_more_gates(psim_peps_t& P, const psim_gate* gates, size_t n_gates) {
+  psim_peps_t tmp = P;
+  apply_gates(tmp, gates, n_gates);
+  P = std::move(tmp);
+}
+
+// Measurement outcome |value> on one qubit: the physical slice sigma != value
+// of its site tensor is set to zero (unnormalised: the new squared norm is
+// the outcome's probability times the old one).
+void project_qubit(psim_peps_t& P, int32_t qubit, int32_t value) {
+  if (qubit < 0 || qubit >= P.lv * P.lh) fail(PSIM_EINVAL, "qubit out of range");
+  if (value != 0 && value != 1) fail(PSIM_EINVAL, "value must be 0 or 1");
+  Site& s = P.sites[(size_t)qubit];
+  const size_t half = s.t.size() / 2;  // sigma is the slowest index
+  std::fill(s.t.begin() + (value ? 0 : half), s.t.begin() + (value ? half : 2 * half), cd(0.0));
 }

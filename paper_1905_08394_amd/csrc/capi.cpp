@@ -9,6 +9,8 @@
 #include "psim_internal.hpp"
 
 psim_peps_t* build_peps(int32_t lv, int32_t lh, const psim_gate* gates, size_t n_gates);
+void apply_more_gates(psim_peps_t& P, const psim_gate* gates, size_t n_gates);
+void project_qubit(psim_peps_t& P, int32_t qubit, int32_t value);
 psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o);
 void free_plan(psim_plan_t* pl);
 void run_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, size_t ws_bytes, void* stream,
@@ -82,6 +84,20 @@ psim_status psim_peps_info(const psim_peps_t* P, int32_t* lv, int32_t* lh, int32
 }
 
 void psim_peps_free(psim_peps_t* P) { delete P; }
+
+psim_status psim_apply(psim_peps_t* P, const psim_gate* gates, size_t n_gates) {
+  return guarded([&] {
+    if (!P) fail(PSIM_EINVAL, "peps is NULL");
+    apply_more_gates(*P, gates, n_gates);
+  });
+}
+
+psim_status psim_project(psim_peps_t* P, int32_t qubit, int32_t value) {
+  return guarded([&] {
+    if (!P) fail(PSIM_EINVAL, "peps is NULL");
+    project_qubit(*P, qubit, value);
+  });
+}
 
 psim_status psim_double_layer(const psim_peps_t* P, const double* ops, psim_peps_t** out) {
   return guarded([&] {

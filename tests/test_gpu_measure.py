@@ -136,3 +136,45 @@ def test_sample_zero_samples_and_repeat(ps):
     b1, p1 = ps.sample(P, u, prec="fp64", max_batch=32)
     b2, p2 = ps.sample(P, u, prec="fp64", max_batch=32)
     assert np.array_equal(b1, b2) and np.array_equal(p1, p2)
+
+
+def _sv_apply(psi, gates):
+    from oracle import gates as G
+    for g in gates:
+        m = G.matrix_of(g)
+        psi = sv.apply_2q(psi, m, g.q0, g.q1) if G.is_two_qubit(g) else sv.apply_1q(psi, m, g.q0)
+    return psi
+
+
+@pytest.mark.parametrize("prec,sweep", [("fp64", 0), ("fp64", 3), ("fp32_3m", 0)])
+def test_measurements_with_gates_in_between(ps, prec, sweep):
+    """Measure a qubit (double-layer probability, outcome from a fixed
+    uniform), record it on the PEPS, apply more gates, measure another: every
+    probability and the final unnormalised amplitudes against the oracle doing
+    the same on the state vector (the remark after eq. 7)."""
+    c = rqcgen.generate(3, 4, 8, 2)
+    more = rqcgen.generate_general(3, 4, 2, 5, "U2").gates
+    n = 12
+    P = ps.Peps(c)
+    psi = sv.run(c)
+    P0 = np.diag([1.0, 0.0]).astype(complex)
+    tol = 1e-11 if prec == "fp64" else 2e-5
+    kw = dict(prec=prec, sweep=sweep)
+    for q, u, gates in ((5, 0.37, more), (2, 0.61, ())):
+        norm = ps.expectation(P, {}, **kw).real
+        p0 = ps.expectation(P, {q: P0}, **kw).real / norm
+        o_norm = np.vdot(psi, psi).real
+        o_p0 = om.marginal(psi, [q], [0]) / o_norm
+        assert abs(p0 - o_p0) <= tol, (q, p0, o_p0)
+        assert abs(norm - o_norm) <= tol * max(1.0, o_norm)
+        t = 0 if u < o_p0 else 1
+        P.project(q, t)
+        psi = om.project(psi, q, t)
+        if gates:
+            P.apply(gates)
+            psi = _sv_apply(psi, gates)
+    bits = rqcgen.bitstrings(3, 4, 2, 24)
+    a = ps.Plan(P, prec=prec, sweep=sweep, max_batch=len(bits)).amplitudes(bits)
+    ref = sv.amplitudes(psi, bits)
+    scale = np.sqrt(np.vdot(psi, psi).real)
+    assert np.max(np.abs(a - ref)) * 2 ** (n / 2) <= tol * 10 * scale, np.max(np.abs(a - ref))

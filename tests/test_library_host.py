@@ -288,3 +288,24 @@ def test_sample_host_errors(ps):
     st = L.psim_sample(P._h, ctypes.byref(o), u.ctypes.data_as(PD), 2, None, 0, None, bits.ctypes.data_as(PU8), None)
     assert st == ps.PSIM_EINVAL and "not in [0, 1)" in L.psim_last_error().decode()
     assert not bits.any()
+
+
+def test_apply_and_project_host(ps):
+    """psim_apply grows the bonds like psim_build and is all-or-nothing;
+    psim_project checks its arguments."""
+    full = rqcgen.generate(3, 3, 16, 0)
+    k = 70
+    P = ps.Peps(rqcgen.Circuit(3, 3, 16, 0, list(full.gates[:k])))
+    before = P.info()["bond_dims"]
+    bad = list(full.gates[k:k + 5]) + [rqcgen.Gate(99, "CZ", 0, 4)]   # diagonal pair last
+    with pytest.raises(ps.PsimError) as e:
+        P.apply(bad)
+    assert e.value.status == ps.PSIM_EINVAL
+    assert P.info()["bond_dims"] == before
+    P.apply(full.gates[k:])                 # the rest of the circuit on top of its first k gates
+    assert P.info()["bond_dims"] == ps.Peps(full).info()["bond_dims"]
+    for q, v in ((-1, 0), (9, 0), (3, 2)):
+        with pytest.raises(ps.PsimError) as e:
+            P.project(q, v)
+        assert e.value.status == ps.PSIM_EINVAL
+    P.project(3, 1)

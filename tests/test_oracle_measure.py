@@ -154,3 +154,16 @@ def test_sampling_frequencies_follow_born_rule():
     exp = p * len(u)
     chi2 = float(np.sum((counts - exp) ** 2 / exp))
     assert chi2 < 24.3  # 7 degrees of freedom, p = 0.001
+
+
+def test_projection_norm_is_the_marginal_and_idempotent():
+    c = rqcgen.generate(3, 3, 8, 6)
+    psi = sv.run(c)
+    for q in (0, 4, 8):
+        for v in (0, 1):
+            ph = om.project(psi, q, v)
+            assert abs(np.vdot(ph, ph).real - om.marginal(psi, [q], [v])) < 1e-14
+            assert np.array_equal(om.project(ph, q, v), ph)
+            assert not np.any(np.take(ph, 1 - v, axis=q))
+    # the two outcomes add back to the state
+    assert np.allclose(om.project(psi, 2, 0) + om.project(psi, 2, 1), psi, atol=0)
