@@ -117,6 +117,28 @@ def golden_errors(bits, amps, lattice, depth):
             "x": [float("%.4g" % v) for v in np.abs(r) ** 2 * 2.0 ** n]}
 
 
+def host_description():
+    """Host CPU model, logical CPUs and numpy's BLAS, for the CPU timings."""
+    import numpy as np
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = None
+    try:
+        cfg = np.show_config(mode="dicts")
+        b = cfg.get("Build Dependencies", {}).get("blas", {})
+        blas = f"{b.get('name')} {b.get('version')}".strip()
+    except Exception:
+        pass
+    return {"cpu": model, "logical_cpus": os.cpu_count(), "blas": blas}
+
+
 def cpu_baseline(circuit, bits, target_seconds):
     """The oracle's row scheme (numpy FP64) on (v, w) slices of one interior row."""
     import numpy as np
@@ -148,7 +170,7 @@ def cpu_baseline(circuit, bits, target_seconds):
     s_per_amp = t / tasks * batch_cmac / task_cmac / len(bits)
     threads = int(os.environ.get("OPENBLAS_NUM_THREADS", os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
     return {"value": s_per_amp, "unit": "s/amplitude", "cores": min(threads, os.cpu_count() or 1),
-            "kind": "oracle",
+            "kind": "oracle", "host": host_description(),
             "sample": f"{tasks} (v,w) slice(s) of one interior row of the 6x6 (1+40+1) row scheme "
                       f"(oracle.peps.row_transfer, numpy complex128, {t:.1f} s), extrapolated by exact "
                       f"multiply-add counts to the 16-bitstring batch ({batch_cmac:.3e} CMAC)"}
