@@ -648,6 +648,10 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
+        # the paper's own timings (FP64, CPUs; no 6x6 figure is published): context only
+        "paper_context": {"7x7 (1+40+1)": "31 min per amplitude, 4096 Tianhe-2 fat nodes, FP64",
+                          "7x7 (1+39+1)": "9 min per amplitude, 4096 Tianhe-2 nodes, FP64",
+                          "8x8 (1+25+1)": "under 1 h per amplitude, 2-core 2.8 GHz PC"},
         "dtype": {"fp64": "f64", "bf16x3": "bf16x3"}.get(args.prec, "f32"),
         "data": "synthetic",
         "split_accumulation": bool(args.split_acc and args.prec == "fp32"),
