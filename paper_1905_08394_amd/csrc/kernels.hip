@@ -1131,13 +1131,16 @@ __global__ void copy_segments(const CopySeg* __restrict__ segs) {
 // Three-index permutes of a complex tensor in[X][Y][Z] (E = float2 or
 // double2, one complex element): mode 0 writes out[Y][X][Z], mode 1
 // out[X][Z][Y].  One thread per output element; blockIdx.y = node, nodes
-// X*Y*Z elements apart in both tensors.
+// X*Y*Z elements apart in both tensors.  With mx (per node: exponent + 4096,
+// as row_exponent leaves it) every element is scaled by 2^-exponent on the
+// way, exactly as row_apply would have done in place.
 template <typename E>
 __global__ void permute3(const E* __restrict__ in, E* __restrict__ out, long long X, long long Y, long long Z,
-                         int mode) {
+                         int mode, const uint32_t* __restrict__ mx) {
   const long long total = X * Y * Z;
   in += blockIdx.y * total;
   out += blockIdx.y * total;
+  const int e = mx ? (int)mx[blockIdx.y] - 4096 : 0;
   for (long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x; o < total;
        o += (long long)gridDim.x * blockDim.x) {
     long long x, y, z;
@@ -1152,7 +1155,12 @@ __global__ void permute3(const E* __restrict__ in, E* __restrict__ out, long lon
       z = q % Z;
       x = q / Z;
     }
-    out[o] = in[(x * Y + y) * Z + z];
+    E v = in[(x * Y + y) * Z + z];
+    if (e != 0) {
+      v.x = ldexp(v.x, -e);
+      v.y = ldexp(v.y, -e);
+    }
+    out[o] = v;
   }
 }
 
@@ -1581,7 +1589,7 @@ static unsigned grid_for(long long total) {
 }
 
 void launch_permute3(int prec, const void* in, void* out, int64_t X, int64_t Y, int64_t Z, int mode, void* stream,
-                     int64_t nodes) {
+                     int64_t nodes, const uint32_t* mx) {
   if (X < 1 || Y < 1 || Z < 1 || (mode != 0 && mode != 1) || nodes < 1 || nodes > 65535)
     fail(PSIM_EINTERNAL, "permute3: bad arguments");
   hipStream_t st = (hipStream_t)stream;
@@ -1589,10 +1597,10 @@ void launch_permute3(int prec, const void* in, void* out, int64_t X, int64_t Y, 
   const dim3 grid(grid_for(total), (unsigned)nodes);
   if (prec == PSIM_FP64)
     hipLaunchKernelGGL(permute3<double2>, grid, dim3(256), 0, st, (const double2*)in, (double2*)out, (long long)X,
-                       (long long)Y, (long long)Z, mode);
+                       (long long)Y, (long long)Z, mode, mx);
   else
     hipLaunchKernelGGL(permute3<float2>, grid, dim3(256), 0, st, (const float2*)in, (float2*)out, (long long)X,
-                       (long long)Y, (long long)Z, mode);
+                       (long long)Y, (long long)Z, mode, mx);
   hip_check(hipGetLastError(), "permute3 launch");
 }
 
@@ -1682,6 +1690,23 @@ void launch_rowscale(int prec, void* F, int64_t per_node, int64_t nodes, const i
   else
     hipLaunchKernelGGL(row_apply<float>, dim3(gx, (unsigned)nodes), dim3(256), 0, st, (float*)F, per_node, mx);
   hip_check(hipGetLastError(), "rowscale launch");
+}
+
+void launch_row_exponents(int prec, const void* F, int64_t per_node, int64_t nodes, const int32_t* parent,
+                          const int32_t* exp_prev, int32_t* exp_cur, uint32_t* mx, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const unsigned nb = (unsigned)((nodes + 255) / 256);
+  if (nodes > 65535) fail(PSIM_EUNSUPPORTED, "too many nodes for one rescale launch");
+  hipLaunchKernelGGL(zero_u32, dim3(nb), dim3(256), 0, st, mx, nodes);
+  long long per_block = 256 * 16;
+  unsigned gx = (unsigned)std::min<long long>((2 * per_node + per_block - 1) / per_block, 4096);
+  if (gx == 0) gx = 1;
+  if (prec == PSIM_FP64)
+    hipLaunchKernelGGL(row_absmax<double>, dim3(gx, (unsigned)nodes), dim3(256), 0, st, (const double*)F, per_node, mx);
+  else
+    hipLaunchKernelGGL(row_absmax<float>, dim3(gx, (unsigned)nodes), dim3(256), 0, st, (const float*)F, per_node, mx);
+  hipLaunchKernelGGL(row_exponent, dim3(nb), dim3(256), 0, st, nodes, parent, exp_prev, exp_cur, mx);
+  hip_check(hipGetLastError(), "row exponent launch");
 }
 
 void launch_fill_ones(int prec, void* p, void* stream) {

@@ -210,8 +210,13 @@ struct CopySeg {
 void launch_copy_segments(const CopySeg* d_segs, int n, int64_t max_bytes, void* stream);
 // square partition: complex in[X][Y][Z] -> out[Y][X][Z] (mode 0) or out[X][Z][Y]
 // (mode 1), for `nodes` tensors X*Y*Z elements apart
+// (mx, nullable: per-node exponent + 4096 from launch_row_exponents; the
+// permute then also scales each node by 2^-exponent)
 void launch_permute3(int prec, const void* in, void* out, int64_t X, int64_t Y, int64_t Z, int mode, void* stream,
-                     int64_t nodes = 1);
+                     int64_t nodes = 1, const uint32_t* mx = nullptr);
+// the exponent half of launch_rowscale (nothing scaled; mx keeps exponent + 4096)
+void launch_row_exponents(int prec, const void* F, int64_t per_node, int64_t nodes, const int32_t* parent,
+                          const int32_t* exp_prev, int32_t* exp_cur, uint32_t* mx, void* stream);
 // device Q[n][k] (N x K complex) -> packed W operand for W[k][n] = Q[n][k]
 // (rows x ld, zero padded), for `nodes` matrices N*K complex / rows*ld reals apart
 void launch_pack_w(int prec, const void* Q, void* P, int64_t N, int64_t K, int64_t rows, int64_t ld, void* stream,

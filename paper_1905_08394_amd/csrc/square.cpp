@@ -36,8 +36,11 @@
 // the layouts the joins read (a quadrant tensor Q[n][k] is the packed W
 // operand of W[k][n] = Q[n][k]).
 //
-// Every tensor is rescaled by an exact power of two after each row and each
-// join.  The exponents stay on the device (one slot per rescale) with the
+// Every quadrant tensor is rescaled by an exact power of two after each of
+// its rows (its largest component in [1/2, 1)).  The joins are not: T and Y
+// are sums of at most D^h products of such components, far inside the FP32
+// range, and their magnitudes only pass into the final FP64 inner product.
+// The exponents stay on the device (one slot per rescale) with the
 // inner products (one slot per amplitude) until a flush downloads them all at
 // once, so the host does not wait on the stream between launches; each
 // amplitude's exponent is then summed on the host with the site-matrix
@@ -392,14 +395,30 @@ struct SqRun {
     pend.clear();
   }
 
-  // exact power-of-two rescale of one tensor; its exponent goes to a slot
-  Exp rescale(void* T, int64_t elems) {
-    if (exp_next - exp_base == kSqExpSlots) flush();
+  // End of a quadrant row for `nodes` running tensors T (per_node elements
+  // apart): exact power-of-two rescale, one exponent slot per node, then,
+  // when out is set, the permute [X][Y][Z] -> out (mode as launch_permute3).
+  // Small tensors are scaled in place by the fused kernel; for large ones
+  // only the exponents are found here and the permute applies the scaling
+  // (one pass over the tensor fewer).  parents: `nodes` zeros; mx: `nodes`
+  // scratch words.  Returns the first slot id.
+  int64_t row_end(void* T, int64_t per_node, int64_t nodes, const int32_t* parents, uint32_t* mx, void* out,
+                  int64_t X, int64_t Y, int64_t Z, int mode) {
+    if (exp_next - exp_base + nodes > kSqExpSlots) flush();
     int32_t* slot = d_exps + (exp_next - exp_base);
-    run(3, 0, 3.0 * eb * elems, [&] { launch_rowscale(prec, T, elems, 1, d_zero, d_zero, slot, d_mx, st); });
-    Exp e;
-    e.slots.push_back(exp_next++);
-    return e;
+    const bool fold = out && !rescale_fusable(per_node);
+    if (fold)
+      run(3, 0, 1.0 * eb * per_node * nodes,
+          [&] { launch_row_exponents(prec, T, per_node, nodes, parents, d_zero, slot, mx, st); });
+    else
+      run(3, 0, 3.0 * eb * per_node * nodes,
+          [&] { launch_rowscale(prec, T, per_node, nodes, parents, d_zero, slot, mx, st); });
+    if (out)
+      run(2, 0, 2.0 * eb * X * Y * Z * nodes,
+          [&] { launch_permute3(prec, T, out, X, Y, Z, mode, st, nodes, fold ? mx : nullptr); });
+    const int64_t first = exp_next;
+    exp_next += nodes;
+    return first;
   }
 
   // sum_i a[i] b[i] over n complex elements into a dot slot; returns its id
@@ -444,37 +463,21 @@ struct SqRun {
         std::swap(cur, nxt);
         cur_elems = sh.M * sh.N;
       }
-      e += rescale(cur, cur_elems);
-      // [o_0 .. o_{i-1}][d_0 .. d_{h-1}][o_i] -> next layout
+      // rescale; [o_0 .. o_{i-1}][d_0 .. d_{h-1}][o_i] -> next layout
       int64_t X = 1, Y = 1;
       for (int k = 0; k < i; ++k) X *= Q.s[(size_t)k * nc + nc - 1].dr;
       for (int j = 0; j < nc; ++j) Y *= Q.s[(size_t)i * nc + j].dd;
       const int64_t Z = Q.s[(size_t)i * nc + nc - 1].dr;
-      if (i + 1 < nr) {
-        if (X > 1) {
-          run(2, 0, 2.0 * eb * X * Y * Z, [&] { launch_permute3(prec, cur, nxt, X, Y, Z, 0, st); });
-          std::swap(cur, nxt);
-        }
-      } else {
-        run(2, 0, 2.0 * eb * X * Y * Z, [&] { launch_permute3(prec, cur, dst, X, Y, Z, qi == 2 ? 1 : 0, st); });
-      }
+      const bool last = i + 1 == nr;
+      char* out = last ? dst : (X > 1 ? nxt : nullptr);
+      e.slots.push_back(row_end(cur, cur_elems, 1, d_zero, d_mx, out, X, Y, Z, last && qi == 2 ? 1 : 0));
+      if (out == nxt) std::swap(cur, nxt);
     }
     return e;
   }
 
-  // Batched form: rescale of `nodes` tensors per_node elements apart, one
-  // exponent slot each; returns the first slot id.
-  int32_t* d_zeros = nullptr;  // parent index 0 for every node
-  uint32_t* d_mxn = nullptr;   // per-node scratch of the rescale
-  int64_t rescale_nodes(void* T, int64_t per_node, int64_t nodes) {
-    if (exp_next - exp_base + nodes > kSqExpSlots) flush();
-    int32_t* slot = d_exps + (exp_next - exp_base);
-    run(3, 0, 3.0 * eb * per_node * nodes,
-        [&] { launch_rowscale(prec, T, per_node, nodes, d_zeros, d_zero, slot, d_mxn, st); });
-    const int64_t first = exp_next;
-    exp_next += nodes;
-    return first;
-  }
+  int32_t* d_zeros = nullptr;  // batched form: parent index 0 for every node
+  uint32_t* d_mxn = nullptr;   // batched form: per-node rescale scratch
 
   // Batched form: quadrant qi for `nodes` patterns at once (pattern p's bits
   // at d_tau[p * sites + s], s in frame order), running tensors in r0 / r1,
@@ -517,20 +520,14 @@ struct SqRun {
         std::swap(cur, nxt);
         cur_elems = sh.M * sh.N;
       }
-      row_slot.push_back(rescale_nodes(cur, cur_elems, nodes));
       int64_t X = 1, Y = 1;
       for (int k = 0; k < i; ++k) X *= Q.s[(size_t)k * nc + nc - 1].dr;
       for (int j = 0; j < nc; ++j) Y *= Q.s[(size_t)i * nc + j].dd;
       const int64_t Z = Q.s[(size_t)i * nc + nc - 1].dr;
-      if (i + 1 < nr) {
-        if (X > 1) {
-          run(2, 0, 2.0 * eb * X * Y * Z * nodes, [&] { launch_permute3(prec, cur, nxt, X, Y, Z, 0, st, nodes); });
-          std::swap(cur, nxt);
-        }
-      } else {
-        run(2, 0, 2.0 * eb * X * Y * Z * nodes,
-            [&] { launch_permute3(prec, cur, dst, X, Y, Z, qi == 2 ? 1 : 0, st, nodes); });
-      }
+      const bool last = i + 1 == nr;
+      char* out = last ? dst : (X > 1 ? nxt : nullptr);
+      row_slot.push_back(row_end(cur, cur_elems, nodes, d_zeros, d_mxn, out, X, Y, Z, last && qi == 2 ? 1 : 0));
+      if (out == nxt) std::swap(cur, nxt);
     }
     return row_slot;
   }
@@ -736,8 +733,6 @@ void run_chunks(SqRun& R, const uint8_t* bits, const std::vector<size_t>& order,
             R.buf(sq->boff_pk[0]) + (uint64_t)pairs[t].first * sq->prow[0] * sq->pld[0] * rb, sq->pld[0], vUL,
             Tst + (uint64_t)t * vUR * vUL * eb));
       R.joins(gl, R.buf(sq->boff_desc[0]), uploads);
-      const int64_t sT = R.rescale_nodes(Tst, vUR * vUL, (int64_t)pairs.size());
-      for (size_t t = 0; t < pairs.size(); ++t) eT[t].slots.push_back(sT + (int64_t)t);
     }
     if (new_y) {
       // lower-left: Y per distinct (pair, LL)
@@ -763,8 +758,6 @@ void run_chunks(SqRun& R, const uint8_t* bits, const std::vector<size_t>& order,
             R.buf(sq->boff_pk[1]) + (uint64_t)tris[t].second * sq->prow[1] * sq->pld[1] * rb, sq->pld[1], hL,
             Yst + (uint64_t)t * vUR * hL * eb));
       R.joins(gl, R.buf(sq->boff_desc[1]), uploads);
-      const int64_t sY = R.rescale_nodes(Yst, vUR * hL, (int64_t)tris.size());
-      for (size_t t = 0; t < tris.size(); ++t) eY[t].slots.push_back(sY + (int64_t)t);
     }
     // lower-right, then one inner product per distinct (Y, LR)
     const std::vector<int64_t> sLR = quad(3);
@@ -850,7 +843,6 @@ void run_square(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, void* 
     eT += R.quad(1, b0, B);                     // Q_UR [vUR][hU]
     R.pack(A, P, vUL, hU, sq->prow[0], sq->pld[0]);
     R.gemm(B, vUR, hU, P, sq->pld[0], vUL, C);  // T [vUR][vUL]
-    eT += R.rescale(C, vUR * vUL);
     size_t y = x;
     while (y < xe) {
       // one pass: up to ycap lower-left patterns, each joined into its Y
@@ -864,7 +856,6 @@ void run_square(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, void* 
         e += R.quad(2, bb, A);                  // Q_LL [hL][vUL]
         R.pack(A, P, hL, vUL, sq->prow[1], sq->pld[1]);
         R.gemm(C, vUR, vUL, P, sq->pld[1], hL, ybuf(k));  // Y [vUR][hL]
-        e += R.rescale(ybuf(k), vUR * hL);
         eY.push_back(e);
         size_t z = ye;
         while (z < xe && same(order[ye], order[z], 3)) slot[z++ - y] = k;
