@@ -337,6 +337,16 @@ struct SqRun {
   std::vector<Timed> timed;
   bool profile = false;
 
+  SqRun() = default;
+  SqRun(const SqRun&) = delete;
+  SqRun& operator=(const SqRun&) = delete;
+  ~SqRun() {  // events left by a run that ended in an error
+    for (Timed& t : timed) {
+      (void)hipEventDestroy(t.a);
+      (void)hipEventDestroy(t.b);
+    }
+  }
+
   char* buf(uint64_t off) const { return base + off; }
 
   template <typename F>
