@@ -86,6 +86,9 @@ struct SquarePlan {
   int64_t tmax = 1;            // largest running tensor (complex elements)
   int64_t qmax = 1;            // largest quadrant / joined tensor
   int64_t prow[2] = {0, 0}, pld[2] = {0, 0};  // packed operands of the two joins
+  // join j reads its quadrant tensor itself as the W operand (ld = 2K, no
+  // packing): FP32 3M with every tile interior (the direct-to-LDS kernel)
+  bool direct[2] = {false, false};
   uint64_t off_w1 = 0, off_w2 = 0, off_a = 0, off_b = 0, off_c = 0, off_p = 0, off_small = 0, off_y = 0;
   int ycap = 1;                // Y tensors held at once (lower-left patterns joined per pass)
   // batched form (chunk > 0): the bitstrings of a chunk have every quadrant
@@ -186,10 +189,13 @@ void make_square_plan(psim_plan_t* pl, const psim_peps_t& P) {
   sq->cmac_joins = (double)vUR * hU * vUL + (double)vUR * vUL * hL + (double)vUR * hL;
   sq->n_steps += 2;
   // packed W operands: join 1 reads Q_UL as (N = vUL) x (K = hU), join 2 reads Q_LL as (N = hL) x (K = vUL)
-  sq->prow[0] = packed_rows(prec, vUL);
-  sq->pld[0] = packed_ld(prec, hU);
-  sq->prow[1] = packed_rows(prec, hL);
-  sq->pld[1] = packed_ld(prec, vUL);
+  // join 1 reads Q_UL as W (N = vUL, K = hU), join 2 reads Q_LL (N = hL, K = vUL); M = vUR for both
+  const int64_t jn[2] = {vUL, hL}, jk[2] = {hU, vUL};
+  for (int j = 0; j < 2; ++j) {
+    sq->direct[j] = prec == PSIM_FP32_3M && vUR % 128 == 0 && jn[j] % 128 == 0 && jk[j] % 32 == 0;
+    sq->prow[j] = sq->direct[j] ? 0 : packed_rows(prec, jn[j]);
+    sq->pld[j] = sq->direct[j] ? 2 * jk[j] : packed_ld(prec, jk[j]);
+  }
 
   // ---------------------------------------------------------- workspace
   const uint64_t eb = pl->elem_bytes;  // bytes per complex element
@@ -724,7 +730,11 @@ void run_chunks(SqRun& R, const uint8_t* bits, const std::vector<size_t>& order,
     if (new_t) {
       // upper half: T per distinct (UL, UR)
       const std::vector<int64_t> sUL = quad(0), sUR = quad(1);
-      R.pack(qptr(0, 0), R.buf(sq->boff_pk[0]), vUL, hU, sq->prow[0], sq->pld[0], (int64_t)rep[0].size());
+      if (!sq->direct[0])
+        R.pack(qptr(0, 0), R.buf(sq->boff_pk[0]), vUL, hU, sq->prow[0], sq->pld[0], (int64_t)rep[0].size());
+      auto w_ul = [&](int p) -> const char* {
+        return sq->direct[0] ? qptr(0, p) : R.buf(sq->boff_pk[0]) + (uint64_t)p * sq->prow[0] * sq->pld[0] * rb;
+      };
       t_of.clear();
       eT.clear();
       std::vector<std::pair<int, int>> pairs;
@@ -740,14 +750,18 @@ void run_chunks(SqRun& R, const uint8_t* bits, const std::vector<size_t>& order,
       for (size_t t = 0; t < pairs.size(); ++t)
         gl.push_back(SqRun::join_launch(
             R.prec, qptr(1, pairs[t].second), vUR, hU,
-            R.buf(sq->boff_pk[0]) + (uint64_t)pairs[t].first * sq->prow[0] * sq->pld[0] * rb, sq->pld[0], vUL,
+            w_ul(pairs[t].first), sq->pld[0], vUL,
             Tst + (uint64_t)t * vUR * vUL * eb));
       R.joins(gl, R.buf(sq->boff_desc[0]), uploads);
     }
     if (new_y) {
       // lower-left: Y per distinct (pair, LL)
       const std::vector<int64_t> sLL = quad(2);
-      R.pack(qptr(2, 0), R.buf(sq->boff_pk[1]), hL, vUL, sq->prow[1], sq->pld[1], (int64_t)rep[2].size());
+      if (!sq->direct[1])
+        R.pack(qptr(2, 0), R.buf(sq->boff_pk[1]), hL, vUL, sq->prow[1], sq->pld[1], (int64_t)rep[2].size());
+      auto w_ll = [&](int p) -> const char* {
+        return sq->direct[1] ? qptr(2, p) : R.buf(sq->boff_pk[1]) + (uint64_t)p * sq->prow[1] * sq->pld[1] * rb;
+      };
       y_of.clear();
       eY.clear();
       std::vector<std::pair<int, int>> tris;  // (T index, LL pattern)
@@ -765,7 +779,7 @@ void run_chunks(SqRun& R, const uint8_t* bits, const std::vector<size_t>& order,
       for (size_t t = 0; t < tris.size(); ++t)
         gl.push_back(SqRun::join_launch(
             R.prec, Tst + (uint64_t)tris[t].first * vUR * vUL * eb, vUR, vUL,
-            R.buf(sq->boff_pk[1]) + (uint64_t)tris[t].second * sq->prow[1] * sq->pld[1] * rb, sq->pld[1], hL,
+            w_ll(tris[t].second), sq->pld[1], hL,
             Yst + (uint64_t)t * vUR * hL * eb));
       R.joins(gl, R.buf(sq->boff_desc[1]), uploads);
     }
@@ -851,8 +865,8 @@ void run_square(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, void* 
     const uint8_t* b0 = bits + order[x] * nq;
     SqRun::Exp eT = R.quad(0, b0, A);           // Q_UL [vUL][hU]
     eT += R.quad(1, b0, B);                     // Q_UR [vUR][hU]
-    R.pack(A, P, vUL, hU, sq->prow[0], sq->pld[0]);
-    R.gemm(B, vUR, hU, P, sq->pld[0], vUL, C);  // T [vUR][vUL]
+    if (!sq->direct[0]) R.pack(A, P, vUL, hU, sq->prow[0], sq->pld[0]);
+    R.gemm(B, vUR, hU, sq->direct[0] ? A : P, sq->pld[0], vUL, C);  // T [vUR][vUL]
     size_t y = x;
     while (y < xe) {
       // one pass: up to ycap lower-left patterns, each joined into its Y
@@ -864,8 +878,8 @@ void run_square(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, void* 
         const int k = (int)eY.size();
         SqRun::Exp e = eT;
         e += R.quad(2, bb, A);                  // Q_LL [hL][vUL]
-        R.pack(A, P, hL, vUL, sq->prow[1], sq->pld[1]);
-        R.gemm(C, vUR, vUL, P, sq->pld[1], hL, ybuf(k));  // Y [vUR][hL]
+        if (!sq->direct[1]) R.pack(A, P, hL, vUL, sq->prow[1], sq->pld[1]);
+        R.gemm(C, vUR, vUL, sq->direct[1] ? A : P, sq->pld[1], hL, ybuf(k));  // Y [vUR][hL]
         eY.push_back(e);
         size_t z = ye;
         while (z < xe && same(order[ye], order[z], 3)) slot[z++ - y] = k;

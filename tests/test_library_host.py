@@ -238,11 +238,16 @@ def test_square_plan_memory_budget(ps):
     with pytest.raises(ps.PsimError) as e:
         ps.Plan(P, prec="fp32_3m", host_only=True, sweep=3, mem_budget=16 << 30)
     assert e.value.status == ps.PSIM_ENOMEM and "bytes" in str(e.value)
-    one = ps.Plan(P, prec="fp32_3m", host_only=True, sweep=3, mem_budget=49 << 30).stats()
-    assert one["workspace_bytes"] <= 49 << 30
+    # FP32 3M: two running tensors (16 GiB), Q, T, Y (24 GiB), the joins read
+    # the quadrant tensors directly (no packed copy)
+    one = ps.Plan(P, prec="fp32_3m", host_only=True, sweep=3, mem_budget=41 << 30).stats()
+    assert 40 << 30 < one["workspace_bytes"] <= 41 << 30
     many = ps.Plan(P, prec="fp32_3m", host_only=True, sweep=3, mem_budget=97 << 30, max_batch=16).stats()
     # extra Y tensors (8 GiB each) from what the budget leaves
-    assert many["workspace_bytes"] - one["workspace_bytes"] == 6 * (8 << 30)
+    assert many["workspace_bytes"] - one["workspace_bytes"] == 7 * (8 << 30)
+    # FP64 packs the joins' W operands (the 4M real expansion)
+    f64 = ps.Plan(P, prec="fp64", host_only=True, sweep=3, mem_budget=1 << 62).stats()
+    assert f64["workspace_bytes"] > 2 * one["workspace_bytes"]
 
 
 def test_double_layer_host(ps):
