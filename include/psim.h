@@ -96,7 +96,8 @@ typedef struct {
   uint64_t workspace_bytes;   /* device workspace psim_amplitudes needs for max_batch bitstrings */
   uint64_t weights_bytes;     /* device memory the plan itself holds (packed site matrices) */
   uint64_t peak_tensor_elems; /* largest tensor held at once for one bitstring (all v-slices) */
-  double cmac_per_amplitude;  /* exact complex multiply-adds of the row scheme, one bitstring */
+  double cmac_per_amplitude;  /* exact complex multiply-adds for one bitstring in the plan's scheme
+                                 (row sweep, or the square partition's quadrants and joins) */
   int64_t n_gemm_steps;       /* site contractions per bitstring */
   int32_t L;                  /* boundary width (legs of the row boundary F) */
   int32_t R;                  /* number of rows swept */
