@@ -314,3 +314,25 @@ def test_apply_and_project_host(ps):
             P.project(q, v)
         assert e.value.status == ps.PSIM_EINVAL
     P.project(3, 1)
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU: --gpus 2 ends with a message and status 2,
+    before touching any device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_bench_host_description():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    b = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(b)
+    h = b.host_description()
+    assert h["logical_cpus"] == os.cpu_count()
+    assert set(h) == {"cpu", "logical_cpus", "blas"}
