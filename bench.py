@@ -543,11 +543,58 @@ def small_configs_program(args):
         t = timeit(lambda: sq.amplitudes(bits), 5)
         rows.append(("5x5 (1+32+1), 256 random bitstrings, square partition (eqs. S11-S12)", 256,
                      sq.stats()["cmac_per_amplitude"] * 256, t))
+    cpu = small_configs_oracle_times() if not args.no_cpu_baseline else {}
     for name, n, cmac, t in rows:
-        print(json.dumps({"workload": name, "prec": args.prec, "amplitudes": n, "seconds": t,
-                          "amplitudes_per_s": n / t, "cmac": cmac,
-                          "contraction_tflops": 8 * cmac / t / 1e12}), flush=True)
+        rec = {"workload": name, "prec": args.prec, "amplitudes": n, "seconds": t,
+               "amplitudes_per_s": n / t, "cmac": cmac, "contraction_tflops": 8 * cmac / t / 1e12}
+        key = name.split(",")[0]
+        if key in cpu and "square" not in name:
+            rec["cpu_oracle"] = cpu[key]
+        print(json.dumps(rec), flush=True)
         log(f"{name}: {t * 1e3:.2f} ms")
+
+
+def small_configs_oracle_times():
+    """The oracle on the same small workloads (numpy FP64 on the host): all
+    threads and one thread.  3x3 and 4x5: the state vector (all 512
+    amplitudes; 8 seeds x 64 bitstrings); 5x5: the oracle's PEPS row scheme
+    on a few of the 256 bitstrings plus its builder, extrapolated by count."""
+    from threadpoolctl import threadpool_limits
+    import rqcgen
+    from oracle import peps as op
+    from oracle import statevector as sv
+
+    def sv_job(cases):
+        for c, bits in cases:
+            sv.amplitudes(sv.run(c), bits)
+
+    c3 = [(rqcgen.generate(3, 3, 8, 0), rqcgen.all_bitstrings(9))]
+    c45 = [(rqcgen.generate(4, 5, 24, s), rqcgen.bitstrings(4, 5, s, 64)) for s in range(8)]
+    c5 = rqcgen.generate(5, 5, 32, 0)
+    b5 = rqcgen.bitstrings(5, 5, 0, 256)
+    out = {}
+    for threads in (None, 1):
+        with threadpool_limits(limits=threads):
+            t0 = time.perf_counter()
+            sv_job(c3)
+            t3 = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            sv_job(c45)
+            t45 = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            P = op.build(c5)
+            tb = time.perf_counter() - t0
+            k = 2 if threads is None else 1
+            t0 = time.perf_counter()
+            op.amplitudes(P, b5[:k])
+            t5 = tb + (time.perf_counter() - t0) * 256 / k
+        tag = "seconds" if threads is None else "seconds_1_thread"
+        for key, v in (("3x3 (1+8+1)", t3), ("4x5 (1+24+1)", t45), ("5x5 (1+32+1)", t5)):
+            threads_all = int(os.environ.get("OPENBLAS_NUM_THREADS", os.environ.get("OMP_NUM_THREADS", os.cpu_count())))
+            out.setdefault(key, {"kind": "oracle", "threads": min(threads_all, os.cpu_count() or 1)})[tag] = v
+    out["5x5 (1+32+1)"]["sample"] = "PEPS row scheme on 2 (1 thread: 1) of the 256 bitstrings, extrapolated"
+    log(f"cpu oracle: {out}")
+    return out
 
 
 def main():
