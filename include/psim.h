@@ -26,6 +26,8 @@
  *     the call only.
  *   - functions that take a device (HIP) stream enqueue on it and return
  *     after synchronising that stream.
+ *   - with PSIM_LOG=1 in the environment, psim_amplitudes prints one progress
+ *     line per swept row to stderr (for long runs); nothing else is printed.
  */
 #ifndef PSIM_PUBLIC_H_
 #define PSIM_PUBLIC_H_
