@@ -336,3 +336,24 @@ def test_bench_host_description():
     h = b.host_description()
     assert h["logical_cpus"] == os.cpu_count()
     assert set(h) == {"cpu", "logical_cpus", "blas"}
+
+
+def test_committed_bench_record_keeps_the_contract():
+    """The committed default bench line has every field of the bench
+    contract, with a roofline and a CPU baseline of the stated form."""
+    import json
+    with open(os.path.join(ROOT, "profiles", "bench_6x6_d40_default_3m.json")) as f:
+        d = json.loads(f.read().strip().splitlines()[-1])
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+              "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
+        assert k in d, k
+    assert d["n_gpus"] == 1 and d["higher_is_better"] is False and d["unit"] == "s/amplitude"
+    assert "workload" in d["config"]
+    r = d["roofline"]
+    assert r["bound"] in ("hbm", "mfma", "alu") and r["unit"] in ("GB/s", "TFLOP/s")
+    assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-9 and 0 < r["frac"] < 1
+    assert r["traffic"] is None or r["traffic"] > 0
+    c = d["cpu_baseline"]
+    assert c["kind"] == "oracle" and c["cores"] >= 1 and c["value"] > 0 and c["sample"]
+    # the target: FP32-MFMA within 1e-5 of the FP64 oracle on every amplitude
+    assert d["vs_oracle"]["max_eps_rel"] <= 1e-5 and len(d["vs_oracle"]["eps_rel"]) == d["vs_oracle"]["n"]
