@@ -64,7 +64,7 @@ def run_gpu(args, prec, circuit, bits, sweep=0):
     import paper_1905_08394_amd as ps
     peps = ps.Peps(circuit)
     plan = ps.Plan(peps, prec=prec, mem_budget=args.mem_gib << 30, max_batch=len(bits),
-                   split_acc=args.split_acc and prec == "fp32", sweep=sweep)
+                   split_acc=args.split_acc and prec in ("fp32", "fp32_3m"), sweep=sweep)
     peps.close()
     stats = plan.stats()
     plan.workspace()                               # allocate before timing
@@ -610,7 +610,7 @@ def main():
                     help="skip timing the FP64 path on the same batch")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-tune", dest="tune", action="store_false", help="skip the tile autotuner")
-    ap.add_argument("--split-acc", action="store_true", help="FP32 4M with per-stage partial sums")
+    ap.add_argument("--split-acc", action="store_true", help="FP32 4M / 3M with per-stage partial sums")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-square", dest="square", action="store_false",
                     help="skip timing the square partition on the same batch")
@@ -679,8 +679,9 @@ def main():
         with open(tfile) as f:
             tr = json.load(f)
     per_launch_cmac = hot["cmac"] / max(hot["launches"], 1)
+    # the counters were taken on the default (unsplit) kernel
     if tr is not None and args.prec in KERNEL_SECTIONS and tr.get("kernel_source_sha256") == kernel_source_hash(args.prec) \
-            and "issued_flops_per_launch" in tr:
+            and "issued_flops_per_launch" in tr and not args.split_acc:
         # counters were taken on the largest interior launch; scale to this
         # run's average launch by issued flops (same K and N, M differs)
         traffic = tr["bytes_per_launch"] * issued * per_launch_cmac / tr["issued_flops_per_launch"]
@@ -701,7 +702,7 @@ def main():
                           "8x8 (1+25+1)": "under 1 h per amplitude, 2-core 2.8 GHz PC"},
         "dtype": {"fp64": "f64", "bf16x3": "bf16x3"}.get(args.prec, "f32"),
         "data": "synthetic",
-        "split_accumulation": bool(args.split_acc and args.prec == "fp32"),
+        "split_accumulation": bool(args.split_acc and args.prec in ("fp32", "fp32_3m")),
         "config": {"workload": f"{args.lattice}x{args.lattice} lattice, random circuit depth (1+{args.depth}+1), "
                                f"D={stats['chi']}, exact row-scheme amplitudes of {len(bits)} bitstrings "
                                f"sharing rows 1-{args.lattice - 1} (last-row variants)",

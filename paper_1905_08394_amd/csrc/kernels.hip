@@ -558,7 +558,7 @@ __global__ __launch_bounds__(256) void site_gemm_group(GroupArgs ga) {
 
 __device__ __forceinline__ int dtl_swz(int r) { return (r ^ (r >> 3)) & 7; }
 
-template <int BM, int BN>
+template <int BM, int BN, bool SPLIT = false>
 __device__ __forceinline__ void dtl3m_body(const KArgs& p, const long long t) {
   constexpr int BK = 32;                 // floats per stage row = 8 chunks
   constexpr int MB = 32;
@@ -631,10 +631,28 @@ __device__ __forceinline__ void dtl3m_body(const KArgs& p, const long long t) {
       for (int q = 0; q < 3; ++q)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc3[bi][bj][q][r] = 0;
+  // SPLIT: each stage's products are summed on their own (fresh partial
+  // accumulators) and then added to the running sums, which shortens the
+  // FP32 rounding chains of the K loop
+  f32x16 part[SPLIT ? MBLK : 1][SPLIT ? NBLK3 : 1][SPLIT ? 3 : 1];
 
   const int frow = lane % MB;
   const int fh = (lane / MB) * 2;  // first logical chunk of this lane half within a group of 4
   auto compute = [&](const float* a_s, const float* b_s) {
+    if constexpr (SPLIT) {
+#pragma unroll
+      for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < NBLK3; ++bj)
+#pragma unroll
+          for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) part[bi][bj][q][r] = 0;
+    }
+    auto& dst = [&]() -> auto& {
+      if constexpr (SPLIT) return part;
+      else return acc3;
+    }();
 #pragma unroll
     for (int g = 0; g < BK / 16; ++g) {
       f32x4 ar[MBLK], ai[MBLK], as[MBLK], br[NBLK3], bim[NBLK3], bs[NBLK3];
@@ -664,10 +682,18 @@ __device__ __forceinline__ void dtl3m_body(const KArgs& p, const long long t) {
         for (int bi = 0; bi < MBLK; ++bi)
 #pragma unroll
           for (int bj = 0; bj < NBLK3; ++bj) {
-            acc3[bi][bj][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[bi][s], br[bj][s], acc3[bi][bj][0], 0, 0, 0);
-            acc3[bi][bj][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[bi][s], bim[bj][s], acc3[bi][bj][1], 0, 0, 0);
-            acc3[bi][bj][2] = __builtin_amdgcn_mfma_f32_32x32x2f32(as[bi][s], bs[bj][s], acc3[bi][bj][2], 0, 0, 0);
+            dst[bi][bj][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[bi][s], br[bj][s], dst[bi][bj][0], 0, 0, 0);
+            dst[bi][bj][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[bi][s], bim[bj][s], dst[bi][bj][1], 0, 0, 0);
+            dst[bi][bj][2] = __builtin_amdgcn_mfma_f32_32x32x2f32(as[bi][s], bs[bj][s], dst[bi][bj][2], 0, 0, 0);
           }
+    }
+    if constexpr (SPLIT) {
+#pragma unroll
+      for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < NBLK3; ++bj)
+#pragma unroll
+          for (int q = 0; q < 3; ++q) acc3[bi][bj][q] += part[bi][bj][q];
     }
   };
   // vmcnt(0), other counters unconstrained: the copies into LDS have landed
@@ -711,6 +737,15 @@ __global__ __launch_bounds__(256, 3) void site_gemm_3m_dtl(KArgs p) {
   const long long t = xcd_tile(p.T);
   if (t >= p.T) return;
   dtl3m_body<BM, BN>(p, t);
+}
+
+// split-accumulation form (PSIM_PLAN_SPLIT_ACC): twice the accumulators, two
+// workgroups per CU
+template <int BM, int BN>
+__global__ __launch_bounds__(256, 2) void site_gemm_3m_dtl_split(KArgs p) {
+  const long long t = xcd_tile(p.T);
+  if (t >= p.T) return;
+  dtl3m_body<BM, BN, true>(p, t);
 }
 
 // grouped form (see site_gemm_group)
@@ -1324,7 +1359,7 @@ static int fp32_mode(const GemmLaunch& g) {
 // The direct-to-LDS 3M kernel applies: interior tiles only, every K stage
 // inside one k1 block, an even number of stages, 32-bit copy offsets.
 static bool dtl3m_ok(const GemmLaunch& g, int mode) {
-  return g.prec == PSIM_FP32_3M && !g.trans_out && !g.split && mode == ROWMAJOR && g.M % 128 == 0 &&
+  return g.prec == PSIM_FP32_3M && !g.trans_out && mode == ROWMAJOR && g.M % 128 == 0 &&
          (2 * g.K2) % 32 == 0 && (2 * g.K1 * g.K2) % 64 == 0 && g.K2 < (1 << 20) && g.ldw < (1 << 22);
 }
 
@@ -1517,7 +1552,10 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
       // interior tiles, an even number of K stages, 32-bit copy offsets:
       // the direct-to-LDS kernel (same products in the same order as the
       // ROWFAST 3M kernel, so the same results bit for bit)
-      hipLaunchKernelGGL((site_gemm_3m_dtl<128, 128>), dim3((unsigned)blocks), dim3(256), 0, st, b);
+      if (g.split)
+        hipLaunchKernelGGL((site_gemm_3m_dtl_split<128, 128>), dim3((unsigned)blocks), dim3(256), 0, st, b);
+      else
+        hipLaunchKernelGGL((site_gemm_3m_dtl<128, 128>), dim3((unsigned)blocks), dim3(256), 0, st, b);
   } else if (g.prec == PSIM_FP32_3M) {
       if (fast(128, 32))
         g.trans_out ? launch<float, 128, 128, 32, ROWFAST, true, 3>(b, blocks, st)

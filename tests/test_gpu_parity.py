@@ -47,13 +47,14 @@ def _golden(name):
     return g, np.array(g["bits"], dtype=np.uint8), np.array(g["amps_re"]) + 1j * np.array(g["amps_im"])
 
 
-AMP_BAR = {"fp64": 1e-10, "fp32": 1e-5, "fp32s": 1e-5, "fp32_3m": 1e-5, "bf16x3": 1e-3}
-ALL_PREC = ["fp64", "fp32", "fp32s", "fp32_3m", "bf16x3"]   # fp32s: 4M with split accumulation
+AMP_BAR = {"fp64": 1e-10, "fp32": 1e-5, "fp32s": 1e-5, "fp32_3m": 1e-5, "fp32_3ms": 1e-5, "bf16x3": 1e-3}
+# fp32s / fp32_3ms: 4M / 3M with split accumulation
+ALL_PREC = ["fp64", "fp32", "fp32s", "fp32_3m", "fp32_3ms", "bf16x3"]
 
 
 def _plan(ps, peps, prec, **kw):
-    if prec == "fp32s":
-        return ps.Plan(peps, prec="fp32", split_acc=True, **kw)
+    if prec in ("fp32s", "fp32_3ms"):
+        return ps.Plan(peps, prec="fp32" if prec == "fp32s" else "fp32_3m", split_acc=True, **kw)
     return ps.Plan(peps, prec=prec, **kw)
 
 
@@ -316,3 +317,22 @@ def test_tile_candidates(ps, prec, cfg):
     # element, so all candidates agree with the default bit for bit
     a0 = ps.Plan(P, prec=prec, max_batch=256, mem_budget=48 << 30).amplitudes(bits)
     assert np.array_equal(a, a0)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp32_3m"])
+def test_split_accumulation_is_used_and_more_accurate(ps, prec):
+    """PSIM_PLAN_SPLIT_ACC on 5x5 (1+32+1), 256 bitstrings, whose interior
+    sites take the split form of the 4M kernel and of the 3M direct-to-LDS
+    kernel: the amplitudes differ from the unsplit plan's (the other kernel
+    ran) and sit closer to the oracle (median eps_rel over 256 amplitudes)."""
+    g, bits, ref = _golden("rqc_5x5_d32_s0.json")
+    c = rqcgen.generate(5, 5, 32, 0)
+    P = ps.Peps(c)
+    a0 = ps.Plan(P, prec=prec, max_batch=256, mem_budget=48 << 30).amplitudes(bits)
+    a1 = ps.Plan(P, prec=prec, max_batch=256, mem_budget=48 << 30, split_acc=True).amplitudes(bits)
+    e0, _ = _errors(a0, ref, 25)
+    e1, rms1 = _errors(a1, ref, 25)
+    say(f"5x5 {prec}: median eps_rel {np.median(e0):.3e} unsplit, {np.median(e1):.3e} split")
+    assert not np.array_equal(a0, a1)
+    assert np.max(rms1) <= AMP_BAR[prec]
+    assert np.median(e1) < np.median(e0)
