@@ -128,6 +128,8 @@ psim_status psim_build(int32_t lv, int32_t lh, const psim_gate *gates, size_t n_
 psim_status psim_peps_info(const psim_peps_t *peps, int32_t *lv, int32_t *lh, int32_t *chi,
                            int64_t *bond_dims, size_t n_bonds);
 
+/* Frees a PEPS (host memory only); NULL is a no-op.  Plans made from it stay
+ * valid. */
 void psim_peps_free(psim_peps_t *peps);
 
 /* More gates on a built (possibly projected) PEPS, in array order, with the
@@ -184,8 +186,13 @@ psim_status psim_sample(const psim_peps_t *peps, const psim_plan_opts *opts, con
  * build lacks; EDEVICE on HIP failures. */
 psim_status psim_plan(const psim_peps_t *peps, const psim_plan_opts *opts, psim_plan_t **out);
 
+/* The plan's sizes and work counts (psim_plan_stats).  Errors: EINVAL for a
+ * NULL argument. */
 psim_status psim_plan_info(const psim_plan_t *plan, psim_plan_stats *out);
 
+/* Frees the plan's device and pinned host memory and its captured graphs;
+ * NULL is a no-op.  No call on the plan (or on a group holding it) may be
+ * running. */
 void psim_plan_free(psim_plan_t *plan);
 
 /* Amplitudes <tau|psi> (eq. 7) of n_bitstrings bitstrings (bits: host,
@@ -266,6 +273,7 @@ typedef struct {
 
 psim_status psim_group(psim_plan_t *const *plans, int32_t n_plans, psim_group_t **out);
 
+/* Errors: EINVAL for a NULL argument. */
 psim_status psim_group_info(const psim_group_t *group, psim_group_stats *out);
 
 /* Amplitudes for every plan of the group in one interleaved sweep.  Arrays
@@ -288,6 +296,8 @@ psim_status psim_group_amplitudes(psim_group_t *group, const uint8_t *const *bit
                                   void *const *d_workspaces, const size_t *workspace_bytes, void *hip_stream,
                                   double *const *out_amp);
 
+/* Frees the group's descriptors and graphs (not its plans); NULL is a
+ * no-op. */
 void psim_group_free(psim_group_t *group);
 
 /* Message for the last failing call on this thread; valid until the next
