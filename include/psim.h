@@ -190,7 +190,7 @@ psim_status psim_plan(const psim_peps_t *peps, const psim_plan_opts *opts, psim_
  * NULL argument. */
 psim_status psim_plan_info(const psim_plan_t *plan, psim_plan_stats *out);
 
-/* Frees the plan's device and pinned host memory and its captured graphs;
+/* Frees everything the plan holds (device memory, captured graphs);
  * NULL is a no-op.  No call on the plan (or on a group holding it) may be
  * running. */
 void psim_plan_free(psim_plan_t *plan);
