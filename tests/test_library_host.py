@@ -357,3 +357,21 @@ def test_committed_bench_record_keeps_the_contract():
     assert c["kind"] == "oracle" and c["cores"] >= 1 and c["value"] > 0 and c["sample"]
     # the target: FP32-MFMA within 1e-5 of the FP64 oracle on every amplitude
     assert d["vs_oracle"]["max_eps_rel"] <= 1e-5 and len(d["vs_oracle"]["eps_rel"]) == d["vs_oracle"]["n"]
+
+
+def test_committed_split_records_carry_no_traffic():
+    """Bench lines of split-accumulation runs: the counters behind `traffic`
+    were taken on the unsplit kernel, so those lines leave it null; both
+    split forms stay under the 1e-5 target with a wider margin than the
+    default 3M line."""
+    import json
+    recs = {}
+    for name in ("bench_6x6_d40_fp32_3m_split.json", "bench_6x6_d40_fp32_4m_split.json",
+                 "bench_6x6_d40_default_3m.json"):
+        with open(os.path.join(ROOT, "profiles", name)) as f:
+            recs[name] = json.loads(f.read().strip().splitlines()[-1])
+    default = recs.pop("bench_6x6_d40_default_3m.json")
+    for name, d in recs.items():
+        assert d["split_accumulation"] is True, name
+        assert d["roofline"]["traffic"] is None, name
+        assert d["vs_oracle"]["max_eps_rel"] < default["vs_oracle"]["max_eps_rel"] / 2, name
