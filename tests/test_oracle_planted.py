@@ -78,3 +78,39 @@ def test_dropped_site_is_caught(monkeypatch):
     except AssertionError:
         return  # the contraction no longer reduces to a scalar
     assert err > 1e-3
+
+
+def test_sliced_quadrants_dropped_slice_is_caught(monkeypatch):
+    """One slice of the cut loop over the top bond lost from T (the
+    square-partition oracle that wrote the 6x6 golden values)."""
+    import pytest
+    import test_oracle_amplitudes as pins
+    orig = peps._accumulate_matmul
+    calls = []
+
+    def bad(c, a, b, rows=4096):
+        calls.append(1)
+        if len(calls) != 2:
+            orig(c, a, b, rows)
+    monkeypatch.setattr(peps, "_accumulate_matmul", bad)
+    with pytest.raises(AssertionError):
+        pins.test_quadrants_sliced_small()
+    assert len(calls) > 2
+
+
+def test_sliced_quadrants_shifted_bottom_slice_is_caught(monkeypatch):
+    """The lower-left quadrant sliced at z + 1 where the lower-right one is
+    sliced at z (an off-by-one between the two sides of the cut loop)."""
+    import pytest
+    import test_oracle_amplitudes as pins
+    orig = peps.contract_sites
+
+    def bad(sites, order, start=None, fixed=None):
+        order = list(order)
+        if fixed and order and order[0] == (3, 0):          # lower-left quadrant of 4x4
+            (lab, z), = fixed.items()
+            fixed = {lab: (z + 1) % 4}
+        return orig(sites, order, start, fixed)
+    monkeypatch.setattr(peps, "contract_sites", bad)
+    with pytest.raises(AssertionError):
+        pins.test_quadrants_sliced_small()
