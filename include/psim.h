@@ -93,7 +93,8 @@ typedef struct {
                                  together; otherwise bitstrings go one by one (same results) */
   int32_t device;             /* HIP device ordinal */
   int32_t tile_cfg;           /* FP32 interior-site tile candidate: 0 = default, k > 0 = candidate k
-                                 (4M: 1..5, 3M: 1..2); psim_tune may replace it */
+                                 (4M: 1..5, 3M: 1..2; not with PSIM_PLAN_SPLIT_ACC, whose kernels
+                                 have one tile configuration: EINVAL); psim_tune may replace it */
 } psim_plan_opts;
 
 typedef struct {
@@ -226,8 +227,8 @@ psim_status psim_contract_site(int32_t prec, int64_t batch, int64_t M, int64_t K
  * caller's workspace (>= psim_plan_stats.workspace_bytes, contents are
  * overwritten), and keep the fastest for psim_amplitudes.  best_ms
  * (nullable) receives the chosen time of the costliest shape.  Plans in other
- * precisions and square-partition plans keep their single kernel
- * configuration (PSIM_OK, nothing timed).
+ * precisions, split-accumulation plans and square-partition plans keep their
+ * single kernel configuration (PSIM_OK, nothing timed).
  * Errors: EINVAL for a short workspace or reps < 1, EDEVICE. */
 psim_status psim_tune(psim_plan_t *plan, void *d_workspace, size_t workspace_bytes, void *hip_stream,
                       int32_t reps, double *best_ms);

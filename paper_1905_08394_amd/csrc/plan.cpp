@@ -187,6 +187,9 @@ psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o) {
       (opts.tile_cfg > 0 && !((opts.prec == PSIM_FP32_4M && opts.tile_cfg < fp32_config_count()) ||
                               (opts.prec == PSIM_FP32_3M && opts.tile_cfg < fp32_3m_config_count()))))
     fail(PSIM_EINVAL, "tile_cfg " + std::to_string(opts.tile_cfg) + " is not a candidate of this precision");
+  // the split-accumulation kernels come in one tile configuration
+  if (opts.tile_cfg > 0 && (opts.flags & PSIM_PLAN_SPLIT_ACC))
+    fail(PSIM_EINVAL, "tile_cfg > 0 cannot be combined with PSIM_PLAN_SPLIT_ACC");
   int sweep = opts.sweep;
   if (sweep == 0) sweep = (P->lh <= P->lv) ? 1 : 2;
   if (sweep < 1 || sweep > 3) fail(PSIM_EINVAL, "sweep must be 0, 1, 2 or 3");
