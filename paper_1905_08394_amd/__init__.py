@@ -224,14 +224,16 @@ def expectation(peps: Peps, ops: dict, **plan_kw) -> complex:
         dl.close()
 
 
-def _opts(prec="fp64", mem_budget=0, max_batch=1, sweep=0, device=0, graph=False, tile_cfg=0):
-    return PlanOpts(PREC[prec], PLAN_GRAPH if graph else 0, mem_budget, max_batch, sweep, device, tile_cfg)
+def _opts(prec="fp64", mem_budget=0, max_batch=1, sweep=0, device=0, graph=False, tile_cfg=0, split_acc=False):
+    flags = (PLAN_GRAPH if graph else 0) | (PLAN_SPLIT_ACC if split_acc else 0)
+    return PlanOpts(PREC[prec], flags, mem_budget, max_batch, sweep, device, tile_cfg)
 
 
 def sample(peps: Peps, u, stream=None, **plan_kw):
     """Sequential measurement of every qubit (psim_sample) with the uniform
-    numbers u (shape (n_samples, lv*lh), in [0, 1)).  Returns (bits uint8
-    (n_samples, lv*lh), p(bits) per sample)."""
+    numbers u (shape (n_samples, lv*lh), in [0, 1)).  plan_kw as for Plan
+    (without host_only).  Returns (bits uint8 (n_samples, lv*lh), p(bits) per
+    sample)."""
     import torch
     n = peps.lv * peps.lh
     uu = np.ascontiguousarray(np.asarray(u, dtype=np.float64))

@@ -299,6 +299,13 @@ def test_sample_host_errors(ps):
     st = L.psim_sample(P._h, ctypes.byref(o), u.ctypes.data_as(PD), 2, None, 0, None, bits.ctypes.data_as(PU8), None)
     assert st == ps.PSIM_EINVAL and "not in [0, 1)" in L.psim_last_error().decode()
     assert not bits.any()
+    # options reach the double-layer plans: split accumulation is accepted,
+    # a tile candidate with it is not
+    o = ps._opts(prec="fp32_3m", max_batch=8, split_acc=True)
+    assert o.flags == ps.PLAN_SPLIT_ACC
+    assert L.psim_sample_workspace(P._h, ctypes.byref(o), ctypes.byref(need)) == ps.PSIM_OK
+    o = ps._opts(prec="fp32_3m", max_batch=8, split_acc=True, tile_cfg=1)
+    assert L.psim_sample_workspace(P._h, ctypes.byref(o), ctypes.byref(need)) == ps.PSIM_EINVAL
 
 
 def test_apply_and_project_host(ps):
