@@ -70,10 +70,11 @@ typedef enum {
 
 typedef enum {
   PSIM_PLAN_HOST_ONLY = 1,  /* plan the contraction on the host only (no device, cannot run) */
-  PSIM_PLAN_SPLIT_ACC = 2,  /* FP32 4M (every site kernel) and FP32 3M (the direct-to-LDS interior
-                               kernel; its other site kernels are unchanged): accumulate each K stage
-                               separately before adding it to the running sum (smaller rounding
-                               error, same work, slower: twice the accumulator registers) */
+  PSIM_PLAN_SPLIT_ACC = 2,  /* FP32 4M (every site kernel) and FP32 3M (the direct-to-LDS kernel of
+                               interior sites and square-partition joins; its other site kernels are
+                               unchanged), in both schemes: accumulate each K stage separately before
+                               adding it to the running sum (smaller rounding error, same work,
+                               slower: twice the accumulator registers; joins are not grouped) */
   PSIM_PLAN_GRAPH = 4       /* psim_amplitudes captures its row sweep into a HIP graph the first time
                                a (workspace, prefix-trie shape) pair is seen and replays it afterwards;
                                ignored while profiling or when PSIM_LOG=1 */

@@ -305,6 +305,7 @@ struct SqRun {
   hipStream_t st;
   char* base;
   int prec;
+  int split = 0;         // per-stage partial sums in the FP32 site and join kernels
   uint64_t eb;
   int32_t* d_zero;
   uint32_t* d_mx;
@@ -461,6 +462,7 @@ struct SqRun {
         const Shape sh = site_shape(Q, i, j);
         GemmLaunch g;
         g.prec = prec;
+        g.split = split;
         g.A = (i == 0 && j == 0) ? pl->d_ones : (const void*)cur;
         g.C = nxt;
         g.W0 = g.W1 = w.ptr;
@@ -516,6 +518,7 @@ struct SqRun {
         const bool first = i == 0 && j == 0;
         GemmLaunch g;
         g.prec = prec;
+        g.split = split;
         g.A = first ? pl->d_ones : (const void*)cur;
         g.C = nxt;
         g.W0 = st_.w[0].ptr;
@@ -548,10 +551,11 @@ struct SqRun {
     return row_slot;
   }
 
-  static GemmLaunch join_launch(int prec, const void* A, int64_t M, int64_t K, const void* P, int64_t ld, int64_t N,
-                                void* C) {
+  static GemmLaunch join_launch(int prec, int split, const void* A, int64_t M, int64_t K, const void* P, int64_t ld,
+                                int64_t N, void* C) {
     GemmLaunch g;
     g.prec = prec;
+    g.split = split;
     g.A = A;
     g.C = C;
     g.W0 = g.W1 = P;
@@ -608,6 +612,7 @@ struct SqRun {
   void gemm(const void* A, int64_t M, int64_t K, const void* P, int64_t ld, int64_t N, void* C) {
     GemmLaunch g;
     g.prec = prec;
+    g.split = split;
     g.A = A;
     g.C = C;
     g.W0 = g.W1 = P;
@@ -749,7 +754,7 @@ void run_chunks(SqRun& R, const uint8_t* bits, const std::vector<size_t>& order,
       }
       for (size_t t = 0; t < pairs.size(); ++t)
         gl.push_back(SqRun::join_launch(
-            R.prec, qptr(1, pairs[t].second), vUR, hU,
+            R.prec, R.split, qptr(1, pairs[t].second), vUR, hU,
             w_ul(pairs[t].first), sq->pld[0], vUL,
             Tst + (uint64_t)t * vUR * vUL * eb));
       R.joins(gl, R.buf(sq->boff_desc[0]), uploads);
@@ -778,7 +783,7 @@ void run_chunks(SqRun& R, const uint8_t* bits, const std::vector<size_t>& order,
       gl.clear();
       for (size_t t = 0; t < tris.size(); ++t)
         gl.push_back(SqRun::join_launch(
-            R.prec, Tst + (uint64_t)tris[t].first * vUR * vUL * eb, vUR, vUL,
+            R.prec, R.split, Tst + (uint64_t)tris[t].first * vUR * vUL * eb, vUR, vUL,
             w_ll(tris[t].second), sq->pld[1], hL,
             Yst + (uint64_t)t * vUR * hL * eb));
       R.joins(gl, R.buf(sq->boff_desc[1]), uploads);
@@ -815,6 +820,7 @@ void run_square(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, void* 
   R.base = (char*)(((uintptr_t)ws + 255) / 256 * 256);
   R.profile = pl->profile;
   R.prec = pl->opts.prec;
+  R.split = (pl->opts.flags & PSIM_PLAN_SPLIT_ACC) ? 1 : 0;
   R.eb = pl->elem_bytes;
   char* small = R.buf(sq->off_small);
   R.d_zero = (int32_t*)small;

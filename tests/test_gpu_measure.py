@@ -16,7 +16,10 @@ pytestmark = pytest.mark.gpu
 
 X = np.array([[0, 1], [1, 0]], dtype=complex)
 Z = np.diag([1.0, -1.0]).astype(complex)
-BAR = {"fp64": 1e-11, "fp32": 2e-5, "fp32_3m": 2e-5}
+BAR = {"fp64": 1e-11, "fp32": 2e-5, "fp32_3m": 2e-5, "fp32_3ms": 2e-5}
+# fp32_3ms: FP32 3M with split accumulation
+KW = {"fp64": {"prec": "fp64"}, "fp32": {"prec": "fp32"}, "fp32_3m": {"prec": "fp32_3m"},
+      "fp32_3ms": {"prec": "fp32_3m", "split_acc": True}}
 
 
 def say(*a):
@@ -40,7 +43,7 @@ def _circuit(kind, lv, lh, d, seed):
     return rqcgen.generate(lv, lh, d, seed) if kind == "rqc" else rqcgen.generate_general(lv, lh, d, seed, "U2")
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_3m"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_3m", "fp32_3ms"])
 @pytest.mark.parametrize("sweep", [0, 3])
 @pytest.mark.parametrize("case", CIRCUITS)
 def test_expectation_values(ps, case, sweep, prec):
@@ -52,7 +55,7 @@ def test_expectation_values(ps, case, sweep, prec):
     psi = sv.run(c)
     rng = np.random.default_rng(case[4])
     P = ps.Peps(c)
-    kw = dict(prec=prec, sweep=sweep)
+    kw = dict(KW[prec], sweep=sweep)
     qs = rng.choice(n, size=3, replace=False)
     rand = {int(q): rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2)) for q in qs}
     cases = [{}, {0: Z}, {n - 1: X}, {1: Z, n - 2: X}, rand]
