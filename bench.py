@@ -9,11 +9,13 @@ is seconds per amplitude; the line also carries the contraction TFLOP/s
 hot kernel's roofline (interior-site contraction, eq. S4, timed with HIP
 events on its launch stream), and the CPU oracle timed on a bounded sample.
 
-    python bench.py [--steps K] [--warmup W] [--prec fp32_3m|fp32|fp64|bf16x3] [--no-fp64]
+    python bench.py [--steps K] [--warmup W] [--prec fp32_3m|fp32|fp64|bf16x3] [--no-fp64] [--split-acc]
 
 The default path is the FP32-MFMA 3M scheme (the fastest FP32 form that
 meets the 1e-5 relative bar at this workload); the FP64 path is timed on the
-same batch for the comparison the metric names.
+same batch for the comparison the metric names.  --split-acc runs the FP32
+forms with per-stage partial sums (smaller error, slower); its line carries
+no HBM traffic figure, since the counters were taken on the default kernel.
 """
 import argparse
 import hashlib
