@@ -19,7 +19,9 @@ from oracle import statevector as sv
 pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-AMP_BAR = {"fp64": 1e-10, "fp32": 1e-5, "fp32_3m": 1e-5, "bf16x3": 1e-3}
+AMP_BAR = {"fp64": 1e-10, "fp32": 1e-5, "fp32_3m": 1e-5, "bf16x3": 1e-3, "fp32s": 1e-5, "fp32_3ms": 1e-5}
+# fp32s / fp32_3ms: FP32 4M / 3M plans with split accumulation
+SPLIT = {"fp32s": "fp32", "fp32_3ms": "fp32_3m"}
 
 # (lv, lh, depth, seed, bitstrings): uneven lattices, depths and bond sizes
 MIX = [(3, 3, 8, 0, 32), (4, 5, 24, 1, 64), (3, 4, 13, 2, 24), (4, 4, 24, 5, 40),
@@ -67,7 +69,8 @@ def _check(ps, mix, precs, max_batch=None):
     plans = []
     for k, (c, bits) in enumerate(mix):
         mb = len(bits) if max_batch is None else max_batch[k]
-        plans.append(ps.Plan(ps.Peps(c), prec=precs[k], max_batch=mb))
+        p = precs[k]
+        plans.append(ps.Plan(ps.Peps(c), prec=SPLIT.get(p, p), max_batch=mb, split_acc=p in SPLIT))
     single = [p.amplitudes(b) for p, (c, b) in zip(plans, mix)]
     g = ps.Group(plans)
     grouped = g.amplitudes([b for c, b in mix])
@@ -99,6 +102,16 @@ def test_group_mixed_precisions_and_passes(ps):
     mb = [32, 16, 24, 7, 16, 48, 5]
     say("group test mixed precisions / passes")
     st = _check(ps, mix, precs, mb)
+    assert st["grouped_launches"] > 0
+
+
+def test_group_with_split_accumulation_plans(ps):
+    """Split-accumulation plans (launched one by one) in a group with
+    unsplit FP32 plans, whose launches are still merged."""
+    mix = _mix()
+    precs = ["fp32_3ms", "fp32", "fp32s", "fp32_3m", "fp32_3ms", "fp32", "fp32_3m"]
+    say("group test with split-accumulation plans")
+    st = _check(ps, mix, precs)
     assert st["grouped_launches"] > 0
 
 
