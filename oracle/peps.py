@@ -341,3 +341,61 @@ def _accumulate_matmul(c: np.ndarray, a: np.ndarray, b: np.ndarray, rows: int = 
     """c += a @ b, a block of rows at a time to bound the temporary."""
     for s in range(0, c.shape[0], rows):
         c[s:s + rows] += a[s:s + rows] @ b
+
+
+# --------------------------------------------------------------------------
+# row scheme with cut loops, for lattices whose boundary is too large to hold
+# twice with every leg open (supplement S-II, eqs. S2-S6)
+# --------------------------------------------------------------------------
+
+def row_amplitudes_sliced(peps: PEPS, base_bits: Sequence[int], variants: np.ndarray, log=None) -> np.ndarray:
+    """Row-scheme amplitudes of bitstrings that differ only in the last row.
+
+    Rows 0..Lv-2 are contracted once with the bits of `base_bits`; the last
+    row once per row of `variants` (full bitstrings; their other rows must
+    equal the base).  Every row transfer is split by two cut loops: v, the
+    down leg of the previous row at the last column (the leg the last site of
+    the row absorbs), and w, the new down leg at column 0 (the leg the first
+    site creates).  F_out[w] = sum_v row_transfer(F_in at v, w); each term
+    holds tensors of D^(L-1) elements instead of D^(L+1).
+    """
+    lv, lh = peps.lv, peps.lh
+    say = log or (lambda *_: None)
+    variants = np.asarray(variants)
+    for b in variants:
+        if not np.array_equal(np.asarray(b)[: (lv - 1) * lh], np.asarray(base_bits)[: (lv - 1) * lh]):
+            raise ValueError("variants must share rows 0..Lv-2 with the base")
+    dims = bond_dims(peps)
+    sites = projected_sites(peps, base_bits)
+
+    def down(r):
+        return [("v", r, c) for c in range(lh)]
+
+    # row 0, one cut loop over its first down leg
+    w0 = ("v", 0, 0)
+    F = np.zeros([dims[x] for x in down(0)], dtype=np.complex128)
+    for w in range(dims[w0]):
+        part = contract_sites(sites, [(0, c) for c in range(lh)], fixed={w0: w})
+        F[w] = part.ordered(down(0)[1:])
+    say("row 0")
+    for r in range(1, lv - 1):
+        v_lab, w_lab = ("v", r - 1, lh - 1), ("v", r, 0)
+        Fin = LT(F, down(r - 1))
+        F = np.zeros([dims[x] for x in down(r)], dtype=np.complex128)
+        for w in range(dims[w_lab]):
+            for v in range(dims[v_lab]):
+                part = row_transfer(fix(Fin, v_lab, v), sites, r, lh, fixed={v_lab: v, w_lab: w})
+                F[w] += part.ordered(down(r)[1:])
+            say(f"row {r}: w {w + 1}/{dims[w_lab]}")
+        del Fin
+    # last row: one cut loop over v for every variant
+    Fin = LT(F, down(lv - 2))
+    v_lab = ("v", lv - 2, lh - 1)
+    out = np.zeros(len(variants), dtype=np.complex128)
+    for i, b in enumerate(variants):
+        s = projected_sites(peps, b)
+        for v in range(dims[v_lab]):
+            res = row_transfer(fix(Fin, v_lab, v), s, lv - 1, lh, fixed={v_lab: v})
+            out[i] += complex(res.a)
+    say("last row")
+    return out

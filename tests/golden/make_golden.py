@@ -5,6 +5,8 @@ the seeded generator `rqcgen`; nothing is read from the GPU library.
 
   python tests/golden/make_golden.py            # 3x3, 4x5, 5x5 (minutes)
   python tests/golden/make_golden.py --big      # also 6x6 d40 (about an hour, ~34 GiB RAM)
+  python tests/golden/make_golden.py --only-big --base 1   # 6x6 d40, second base bitstring
+  python tests/golden/make_golden.py --rows6    # 6x6 d40 base 0 again, by the row scheme (hours)
 
 Files: rqc_<lv>x<lh>_d<d>_s<seed>.json with the circuit hash, the bitstrings
 and the FP64 amplitudes.
@@ -63,9 +65,11 @@ def small():
     _write("rqc_5x5_d32_s0.json", c, bits, amps, "statevector", {"porter_thomas_full": pt})
 
 
-def big():
+def big(base_index=0):
+    """Base bitstring `base_index` of the seeded stream and its 16 last-row
+    variants (columns 2-5), by the sliced square partition (eqs. S9-S10)."""
     c = rqcgen.generate(6, 6, 40, 0)
-    base = rqcgen.bitstrings(6, 6, 0, 1)[0]
+    base = rqcgen.bitstrings(6, 6, 0, base_index + 1)[base_index]
     cols = [2, 3, 4, 5]
     var = rqcgen.last_row_variants(base, 6, 6, cols)     # variant i: cols bits = bits of i
     left = var[[0, 8]]                                    # column 2 = 0 / 1 (bottom-left quadrant)
@@ -75,9 +79,26 @@ def big():
     res = peps.quadrant_amplitudes_sliced(P, base, left, right,
                                           log=lambda s: print(f"[{time.time() - t:7.0f}s] {s}", flush=True))
     amps = res.reshape(-1)                                # i * 8 + j == variant index
-    _write("rqc_6x6_d40_s0.json", c, var, amps, "peps-square-partition-sliced",
+    name = "rqc_6x6_d40_s0.json" if base_index == 0 else f"rqc_6x6_d40_s0_b{base_index}.json"
+    _write(name, c, var, amps, "peps-square-partition-sliced",
            {"base_index": int(next(i for i in range(16) if np.array_equal(var[i], base))),
-            "variant_cols": cols, "seconds": time.time() - t})
+            "variant_cols": cols, "stream_index": base_index, "seconds": time.time() - t})
+
+
+def rows6():
+    """The 16 amplitudes of the base-0 6x6 (1+40+1) batch again, by the row
+    scheme (supplement S-II) with cut loops: an order independent of the
+    square partition that wrote rqc_6x6_d40_s0.json (several hours on 8 cores,
+    ~34 GiB RAM)."""
+    c = rqcgen.generate(6, 6, 40, 0)
+    base = rqcgen.bitstrings(6, 6, 0, 1)[0]
+    var = rqcgen.last_row_variants(base, 6, 6, [2, 3, 4, 5])
+    t = time.time()
+    P = peps.build(c)
+    amps = peps.row_amplitudes_sliced(P, base, var,
+                                      log=lambda s: print(f"[{time.time() - t:7.0f}s] {s}", flush=True))
+    _write("rqc_6x6_d40_s0_rows.json", c, var, amps, "peps-row-scheme-sliced",
+           {"variant_cols": [2, 3, 4, 5], "seconds": time.time() - t})
 
 
 def fig2():
@@ -103,10 +124,14 @@ if __name__ == "__main__":
     ap.add_argument("--big", action="store_true")
     ap.add_argument("--only-big", action="store_true")
     ap.add_argument("--fig2", action="store_true", help="8x8 (1+25+1) amplitudes")
+    ap.add_argument("--rows6", action="store_true", help="6x6 d40 base-0 batch by the sliced row scheme")
+    ap.add_argument("--base", type=int, default=0, help="--big: index of the base bitstring in the stream")
     a = ap.parse_args()
-    if a.fig2:
+    if a.rows6:
+        rows6()
+    elif a.fig2:
         fig2()
     elif not a.only_big:
         small()
     if a.big or a.only_big:
-        big()
+        big(a.base)

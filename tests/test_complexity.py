@@ -55,3 +55,39 @@ def test_leading_term_6x6():
     # interior row of 6x6 D=32: 4 sites of M = D^5, K = N = D^2 -> 4 * 2^45
     assert cx.generic_time(6, 6, 40) == 16 * 2 ** 45
     assert cx.generic_space(6, 6, 40) == 2 ** 35
+
+
+def _closed_form_rows(L, D, lv):
+    """Per-row multiply-adds of the row scheme on an Lv x L lattice with every
+    bond D, written out from the shapes of eqs. S2-S6 (site by site, left to
+    right): first row D^(c+3) for sites c = 1..L-2 plus D^(L+1) at the last
+    site; an interior row 2 D^(L+2) + (L-2) D^(L+3); the last row D^(L+1) +
+    sum_{c=1}^{L-2} D^(L-c+2) + D^2."""
+    first = sum(D ** (c + 3) for c in range(1, L - 1)) + D ** (L + 1)
+    inner = 2 * D ** (L + 2) + (L - 2) * D ** (L + 3)
+    last = D ** (L + 1) + sum(D ** (L - c + 2) for c in range(1, L - 1)) + D ** 2
+    return [first] + [inner] * (lv - 2) + [last]
+
+
+@pytest.mark.parametrize("lv,L,D", [(3, 3, 2), (5, 5, 16), (6, 6, 32), (7, 7, 32), (5, 4, 8), (4, 6, 4)])
+def test_per_row_counts_closed_form(lv, L, D):
+    """The per-row split the bench extrapolates with equals the closed form of
+    each row, and the rows add up to the whole-scheme count."""
+    dims = cx.uniform_dims(lv, L, D)
+    per_row = cx.row_scheme_cmac_per_row(lv, L, dims)
+    assert per_row == _closed_form_rows(L, D, lv)
+    assert sum(per_row) == cx.row_scheme_cmac(lv, L, dims)
+
+
+@pytest.mark.parametrize("lv,lh,d,seed", [(8, 8, 25, 0), (4, 5, 13, 1), (3, 6, 21, 2), (6, 6, 17, 3)])
+def test_per_row_counts_sum_with_uneven_bonds(lv, lh, d, seed):
+    """Uneven bonds (d not a multiple of 8): the per-row counts of a built
+    PEPS add up to the total, and the first and last rows are the cheapest."""
+    P = peps.build(rqcgen.generate(lv, lh, d, seed))
+    dims = peps.bond_dims(P)
+    assert len(set(dims.values())) > 1
+    per_row = cx.row_scheme_cmac_per_row(lv, lh, dims)
+    assert len(per_row) == lv and all(x > 0 for x in per_row)
+    assert sum(per_row) == cx.row_scheme_cmac(lv, lh, dims)
+    if lv > 2:
+        assert per_row[0] <= max(per_row[1:-1]) and per_row[-1] <= max(per_row[1:-1])

@@ -171,3 +171,21 @@ def test_golden_files_match_oracle(golden_dir):
     bits = np.array(g["bits"], dtype=np.uint8)
     amps = np.array(g["amps_re"]) + 1j * np.array(g["amps_im"])
     assert np.max(np.abs(sv.amplitudes(sv.run(c), bits) - amps)) < 1e-15
+
+
+@pytest.mark.parametrize("lv,lh,d,seed", [(4, 4, 16, 1), (4, 5, 16, 0), (4, 5, 13, 2), (3, 3, 8, 0), (3, 6, 16, 4)])
+def test_row_scheme_with_cut_loops(lv, lh, d, seed):
+    """The row scheme with cut loops over v and w (supplement S-II and the
+    cut technique) gives the amplitudes of bitstrings that share all rows
+    but the last, equal to the state vector (the plain definition)."""
+    c = rqcgen.generate(lv, lh, d, seed)
+    P = peps.build(c)
+    base = rqcgen.bitstrings(lv, lh, seed, 1)[0]
+    var = rqcgen.last_row_variants(base, lv, lh, list(range(max(0, lh - 3), lh)))
+    got = peps.row_amplitudes_sliced(P, base, var)
+    ref = sv.amplitudes(sv.run(c), var)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    bad = var.copy()
+    bad[0, 0] ^= 1                                      # differs from the base in row 0
+    with pytest.raises(ValueError):
+        peps.row_amplitudes_sliced(P, base, bad)

@@ -39,3 +39,34 @@ def test_shallow_circuit_is_not_porter_thomas():
     x = stats.scaled_probabilities(sv.run(c).reshape(-1), 20)
     s = stats.porter_thomas_summary(x)
     assert abs(s["second_moment"] - 2) > 0.1 or s["ks_statistic"] > 0.05
+
+
+def _check_5x5_moments(s):
+    assert s["n"] == 2 ** 25
+    assert abs(s["mean"] - 1) < 1e-10
+    assert abs(s["second_moment"] - 2) < 0.1
+    assert abs(s["mean_neg_log"] - stats.EULER_GAMMA) < 0.05
+
+
+def test_5x5_d32_stored_full_distribution_is_porter_thomas(golden_dir):
+    """The 5x5 (1+32+1) circuit of the parity suite: the moments of all 2^25
+    scaled probabilities, stored by tests/golden/make_golden.py from the state
+    vector, meet the Porter-Thomas closed forms: E[x] = 1 exactly
+    (normalisation), E[x^2] within 0.1 of 2 (2.075 for seed 0), E[-ln x]
+    within 0.05 of Euler's gamma."""
+    import json
+    import os
+    with open(os.path.join(golden_dir, "rqc_5x5_d32_s0.json")) as f:
+        g = json.load(f)
+    assert g["sha256"] == rqcgen.generate(5, 5, 32, 0).sha256()
+    _check_5x5_moments(g["porter_thomas_full"])
+
+
+@pytest.mark.slow
+def test_5x5_d32_full_distribution_is_porter_thomas():
+    """The same moments recomputed from a fresh state-vector run (about two
+    to five minutes on 8 cores; set PSIM_RUN_SLOW=1 to run it)."""
+    import os
+    if os.environ.get("PSIM_RUN_SLOW") != "1":
+        pytest.skip("slow: set PSIM_RUN_SLOW=1")
+    _check_5x5_moments(_summary(5, 5, 32))
