@@ -10,6 +10,15 @@ hot kernel's roofline (interior-site contraction, eq. S4, timed with HIP
 events on its launch stream), and the CPU oracle timed on a bounded sample.
 
     python bench.py [--steps K] [--warmup W] [--prec fp32_3m|fp32|fp64|bf16x3] [--no-fp64] [--split-acc]
+                    [--budget-s S]
+
+Wall-clock budget: a 6x6 step takes tens of seconds, so the whole run is held
+to --budget-s seconds from process start (default 440).  At most one warm-up
+step runs when a step exceeds 10 s, and the timed loop stops early once the
+remaining budget is needed for the legs that follow (FP64 path, single
+amplitude, square partition, plain FP64 GPU, CPU oracle), each of which runs
+one untimed-warmup-free step.  `steps` and `warmup` in the JSON line are the
+steps that actually ran; every timed step is the full 16-bitstring batch.
 
 The default path is the FP32-MFMA 3M scheme (the fastest FP32 form that
 meets the 1e-5 relative bar at this workload); the FP64 path is timed on the
@@ -24,6 +33,7 @@ import os
 import sys
 import time
 
+T_START = time.monotonic()
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -53,6 +63,11 @@ def kernel_source_hash(prec):
     return hashlib.sha256("\n".join(lines[a:b]).encode()).hexdigest()
 
 
+def workload_base(lattice, seed=0):
+    import rqcgen
+    return rqcgen.bitstrings(lattice, lattice, seed, 1)[0]
+
+
 def workload(lattice, depth, seed=0):
     import rqcgen
     c = rqcgen.generate(lattice, lattice, depth, seed)
@@ -61,9 +76,20 @@ def workload(lattice, depth, seed=0):
     return c, rqcgen.last_row_variants(base, lattice, lattice, cols)
 
 
-def run_gpu(args, prec, circuit, bits, sweep=0):
+def since_start():
+    return time.monotonic() - T_START
+
+
+def run_gpu(args, prec, circuit, bits, sweep=0, steps=None, warmup=None, reserve=None):
+    """Plan, warm up and time `steps` full steps of the batch.  `reserve(t)`
+    gives the seconds the legs after this one need when a step takes t
+    seconds; the timed loop stops once another step would eat into them (at
+    least one step always runs).  Returns the amplitudes, the timed seconds,
+    the per-class profile, the plan stats and the (warmup, steps) that ran."""
     import torch
     import paper_1905_08394_amd as ps
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     peps = ps.Peps(circuit)
     plan = ps.Plan(peps, prec=prec, mem_budget=args.mem_gib << 30, max_batch=len(bits),
                    split_acc=args.split_acc and prec in ("fp32", "fp32_3m"), sweep=sweep)
@@ -81,21 +107,38 @@ def run_gpu(args, prec, circuit, bits, sweep=0):
     small = ps.Plan(ps.Peps(rqcgen.generate(3, 3, 8, 0)), prec=prec)
     small.amplitudes(rqcgen.bitstrings(3, 3, 0, 1))
     small.close()
-    for w in range(args.warmup):
-        log(f"warmup {w + 1}/{args.warmup} ({prec})")
-        plan.amplitudes(bits)
+    step_s = None
+    ran_warmup = 0
+    while ran_warmup < warmup:
+        log(f"warmup {ran_warmup + 1}/{warmup} ({prec}) at {since_start():.0f}s")
+        t0 = time.perf_counter()
+        plan.amplitudes(bits, stream=stream.cuda_stream)
+        torch.cuda.synchronize()
+        step_s = time.perf_counter() - t0
+        ran_warmup += 1
+        if step_s > 10.0:                           # long steps: one warm-up is enough
+            break
     plan.profile_start()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    ran = 0
+    while ran < steps:
         amps = plan.amplitudes(bits, stream=stream.cuda_stream)
-        log(f"step {k + 1}/{args.steps} ({prec}) done at {time.perf_counter() - t0:.2f}s")
+        torch.cuda.synchronize()
+        ran += 1
+        el = time.perf_counter() - t0
+        step_s = el / ran
+        log(f"step {ran}/{steps} ({prec}) done at {el:.2f}s ({since_start():.0f}s since start)")
+        if reserve is not None and ran < steps and \
+                since_start() + step_s + reserve(step_s) > args.budget_s:
+            log(f"budget: stopping the timed loop after {ran} of {steps} steps")
+            break
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = plan.profile_read()
     plan.profile_stop()
     plan.close()
-    return amps, elapsed, prof, stats
+    return amps, elapsed, prof, stats, (ran_warmup, ran)
 
 
 def golden_errors(bits, amps, lattice, depth):
@@ -185,8 +228,8 @@ def square_leg(args, circuit, bits, row_value):
     a = argparse.Namespace(**vars(args))
     a.tune = False
     log("square partition ...")
-    amps, el, prof, stats = run_gpu(a, args.prec, circuit, bits, sweep=3)
-    n_amp = args.steps * len(bits)
+    amps, el, prof, stats, (_, ran) = run_gpu(a, args.prec, circuit, bits, sweep=3, steps=1, warmup=0)
+    n_amp = ran * len(bits)
     issued = ISSUED_PER_CMAC[args.prec]
     cmac = sum(v["cmac"] for v in prof.values())
     j = prof["interior_site"]   # class 1 of a square plan: the joins
@@ -200,6 +243,26 @@ def square_leg(args, circuit, bits, row_value):
                      "frac": join_tflops / PEAK_TFLOPS[args.prec] if join_tflops else None,
                      "launches": j["launches"]}}
     err = golden_errors(bits, amps, args.lattice, args.depth)
+    if err:
+        out["vs_oracle"] = err
+    return out
+
+
+def single_leg(args, circuit, bits):
+    """One amplitude on its own: the base bitstring of the batch in a
+    psim_amplitudes call of one bitstring (no sharing), one step."""
+    import numpy as np
+    a = argparse.Namespace(**vars(args))
+    a.tune = False
+    base = bits[:1]
+    for i, b in enumerate(bits):
+        if np.array_equal(b, workload_base(args.lattice)):
+            base = bits[i:i + 1]
+    log("single amplitude ...")
+    amps, el, prof, stats, (_, ran) = run_gpu(a, args.prec, circuit, base, steps=1, warmup=0)
+    out = {"seconds": el / ran, "bitstrings": 1, "cmac": sum(v["cmac"] for v in prof.values()) / ran,
+           "contraction_tflops": 8 * sum(v["cmac"] for v in prof.values()) / el / 1e12}
+    err = golden_errors(base, amps, args.lattice, args.depth)
     if err:
         out["vs_oracle"] = err
     return out
@@ -611,6 +674,10 @@ def main():
     ap.add_argument("--no-fp64", dest="compare_fp64", action="store_false",
                     help="skip timing the FP64 path on the same batch")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--budget-s", type=float, default=440.0,
+                    help="wall-clock budget of the whole run, from process start")
+    ap.add_argument("--no-single", dest="single", action="store_false",
+                    help="skip timing one amplitude on its own")
     ap.add_argument("--no-tune", dest="tune", action="store_false", help="skip the tile autotuner")
     ap.add_argument("--split-acc", action="store_true", help="FP32 4M / 3M with per-stage partial sums")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -666,8 +733,27 @@ def main():
               flush=True)
         return
     log(f"workload {args.lattice}x{args.lattice} (1+{args.depth}+1), {len(bits)} bitstrings, {args.prec}")
-    amps, elapsed, prof, stats = run_gpu(args, args.prec, circuit, bits)
-    n_amp = args.steps * len(bits)
+    compare64 = args.compare_fp64 and args.prec != "fp64"
+    cpu_on = not args.no_cpu_baseline
+    square_on = args.square and args.lattice % 2 == 0 and args.prec in ("fp32", "fp32_3m", "fp64")
+
+    def reserve(t):
+        """Seconds the legs after the timed loop need when a step takes t s
+        (FP64 steps take about 2.6 t, the square partition about 0.25 t)."""
+        r = 15.0
+        if compare64:
+            r += 2.8 * t + 30.0 + 10.0                 # FP64 path (plan, upload, 1 step) + plain FP64
+        if args.single:
+            r += 1.05 * t + 10.0
+        if square_on:
+            r += 0.4 * t + 20.0
+        if cpu_on:
+            r += args.cpu_seconds + 15.0
+        return r
+
+    amps, elapsed, prof, stats, (ran_warmup, ran_steps) = run_gpu(args, args.prec, circuit, bits, reserve=reserve)
+    step_s = elapsed / ran_steps
+    n_amp = ran_steps * len(bits)
     cmac = sum(v["cmac"] for v in prof.values())
     tflops = 8 * cmac / elapsed / 1e12
     hot = prof["interior_site"]
@@ -692,9 +778,9 @@ def main():
         "value": elapsed / n_amp,
         "unit": "s/amplitude",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "steps": ran_steps,
+        "warmup": ran_warmup,
+        "ms_per_step": elapsed / ran_steps * 1e3,
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
@@ -718,7 +804,8 @@ def main():
                    "workspace_gib": round(stats["workspace_bytes"] / 2 ** 30, 2)},
         "contraction_tflops": tflops,
         "pct_mfma_peak": tflops / peak * issued / 8,
-        "s_per_single_amplitude": elapsed / args.steps,
+        "s_per_step_of_16": step_s,
+        "budget": {"budget_s": args.budget_s, "requested_steps": args.steps, "requested_warmup": args.warmup},
         "kernel_ms": {k: round(v["ms"], 3) for k, v in prof.items()},
         # memory-bound classes: algorithmic bytes / their time, against 8 TB/s
         "hbm_kernels": {k: {"gb_per_s": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1),
@@ -737,12 +824,23 @@ def main():
     err = golden_errors(bits, amps, args.lattice, args.depth)
     if err:
         out["vs_oracle"] = err
-    if args.compare_fp64 and args.prec != "fp64":
+    skipped = []
+
+    def fits(seconds, name):
+        if since_start() + seconds <= args.budget_s:
+            return True
+        skipped.append(name)
+        log(f"budget: skipping {name} ({since_start():.0f}s used of {args.budget_s:.0f}s)")
+        return False
+
+    if compare64 and fits(2.8 * step_s + 30.0, "fp64"):
         a64 = argparse.Namespace(**vars(args))
         a64.mem_gib = 128
-        amps64, el64, prof64, _ = run_gpu(a64, "fp64", circuit, bits)
+        a64.tune = False
+        amps64, el64, prof64, _, (_, ran64) = run_gpu(a64, "fp64", circuit, bits, steps=1, warmup=0)
         h64 = prof64["interior_site"]
-        out["fp64"] = {"s_per_amplitude": el64 / n_amp, "speedup_over_fp64": el64 / elapsed,
+        out["fp64"] = {"s_per_amplitude": el64 / (ran64 * len(bits)),
+                       "speedup_over_fp64": (el64 / ran64) / step_s, "steps": ran64, "warmup": 0,
                        "contraction_tflops": 8 * sum(v["cmac"] for v in prof64.values()) / el64 / 1e12,
                        "hot_kernel_tflops": 8 * h64["cmac"] / (h64["ms"] / 1e3) / 1e12,
                        "pct_fp64_mfma_peak": 8 * sum(v["cmac"] for v in prof64.values()) / el64 / 1e12 / 78.6}
@@ -752,17 +850,21 @@ def main():
         import numpy as np
         d = np.abs(amps - amps64)
         out["vs_fp64_gpu"] = {"max_rel": float(np.max(d / np.abs(amps64))),
-                                   "median_rel": float(np.median(d / np.abs(amps64)))}
-    if args.compare_fp64 and args.prec != "fp64" and args.lattice == 6:
+                              "median_rel": float(np.median(d / np.abs(amps64)))}
+    if compare64 and args.lattice == 6 and fits(10.0, "plain_fp64_gpu"):
         log("plain FP64 GPU baseline (torch complex128) ...")
-        out["plain_fp64_gpu"] = plain_fp64_gpu_baseline(stats, cmac, len(bits))
+        out["plain_fp64_gpu"] = plain_fp64_gpu_baseline(stats, cmac / ran_steps, len(bits))
         out["vs_plain_fp64_gpu"] = out["plain_fp64_gpu"]["value"] / out["value"]
-    if args.square and args.lattice % 2 == 0 and args.prec in ("fp32", "fp32_3m", "fp64"):
+    if args.single and fits(1.05 * step_s + 10.0, "single_amplitude"):
+        out["single_amplitude"] = single_leg(args, circuit, bits)
+    if square_on and fits(0.4 * step_s + 20.0, "square_partition"):
         # the paper's square partition (Fig. S2(b), eqs. S9-S10) on the same batch
         out["square_partition"] = square_leg(args, circuit, bits, out["value"])
-    if not args.no_cpu_baseline:
+    if cpu_on and fits(args.cpu_seconds + 10.0, "cpu_baseline"):
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(circuit, bits, args.cpu_seconds)
+    out["budget"]["skipped"] = skipped
+    out["budget"]["wall_s_at_print"] = round(since_start(), 1)
     print(json.dumps(out), flush=True)
 
 
