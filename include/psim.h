@@ -70,11 +70,10 @@ typedef enum {
 
 typedef enum {
   PSIM_PLAN_HOST_ONLY = 1,  /* plan the contraction on the host only (no device, cannot run) */
-  PSIM_PLAN_SPLIT_ACC = 2,  /* FP32 4M (every site kernel) and FP32 3M (the direct-to-LDS kernel of
-                               interior sites and square-partition joins; its other site kernels are
-                               unchanged), in both schemes: accumulate each K stage separately before
-                               adding it to the running sum (smaller rounding error, same work,
-                               slower: twice the accumulator registers; joins are not grouped) */
+  PSIM_PLAN_SPLIT_ACC = 2,  /* FP32 4M and FP32 3M, every site kernel and square-partition join, in
+                               both schemes: accumulate each K stage separately before adding it to
+                               the running sum (smaller rounding error, same work, slower: twice the
+                               accumulator registers; joins are not grouped) */
   PSIM_PLAN_GRAPH = 4       /* psim_amplitudes captures its row sweep into a HIP graph the first time
                                a (workspace, prefix-trie shape) pair is seen and replays it afterwards;
                                ignored while profiling or when PSIM_LOG=1 */
@@ -93,9 +92,12 @@ typedef struct {
                                  for chunks of up to min(32, max_batch) bitstrings contracted
                                  together; otherwise bitstrings go one by one (same results) */
   int32_t device;             /* HIP device ordinal */
-  int32_t tile_cfg;           /* FP32 interior-site tile candidate: 0 = default, k > 0 = candidate k
-                                 (4M: 1..5, 3M: 1..2; not with PSIM_PLAN_SPLIT_ACC, whose kernels
-                                 have one tile configuration: EINVAL); psim_tune may replace it */
+  int32_t tile_cfg;           /* interior-site tile candidate: 0 = default, k > 0 = candidate k
+                                 (FP32 4M: 1..6, FP32 3M: 1..3, FP64: 1..2, BF16X3: 1; not with
+                                 PSIM_PLAN_SPLIT_ACC, whose kernels have one tile configuration:
+                                 EINVAL).  With 0 and PSIM_TUNE_CACHE set in the environment, the
+                                 choices psim_tune stored there for this device architecture,
+                                 precision and shape are used; psim_tune may replace them */
 } psim_plan_opts;
 
 typedef struct {
@@ -112,6 +114,14 @@ typedef struct {
   int32_t sweep;              /* 1 = rows, 2 = columns, 3 = square partition */
   int32_t prec;
   int32_t hot_cfg;            /* tile candidate used by the costliest site contraction (0 = default) */
+  uint64_t peak_bytes;        /* device bytes in use at the peak of psim_amplitudes for max_batch
+                                 bitstrings: workspace_bytes + weights_bytes (nothing else is
+                                 allocated during the call) */
+  int64_t n_tasks;            /* independent pieces of work in one bitstring's contraction: row
+                                 scheme, per row, v chunks x site contractions plus one rescale
+                                 (the cut loop over v, supplement S-II); square partition, its
+                                 device operations per bitstring (quadrant sites, joins,
+                                 permutes, inner product) */
 } psim_plan_stats;
 
 typedef struct psim_peps_s psim_peps_t;
@@ -204,10 +214,30 @@ void psim_plan_free(psim_plan_t *plan);
  * share those rows' work.  Results go to out_amp (host, 2*n doubles: re, im)
  * in FP64 as mantissa * 2^exponent assembled on the host.  If more than
  * max_batch bitstrings are passed they are processed max_batch at a time.
- * Errors: EINVAL for bits outside {0,1} or a short workspace, EDEVICE. */
+ *
+ * out_rel_err (nullable; host, n doubles): a measured estimate of each
+ * amplitude's relative rounding error, not a bound (an a-priori bound in the
+ * style of first-order rounding analysis is larger than the amplitude itself
+ * for random circuits of this size, so it would say nothing).  When non-NULL
+ * the batch is contracted a second time in a companion form with different
+ * rounding, and out_rel_err[b] = |a_b - c_b| / |c_b| (c = companion result;
+ * out_amp still holds the plan's own result a):
+ *   FP32 4M / 3M plans: the other K-loop accumulation (per-stage partial sums
+ *     on or off, PSIM_PLAN_SPLIT_ACC), same packed site matrices.  The
+ *     difference is dominated by the less accurate of the two (the unsplit
+ *     form, whose error is 2-3x larger), so it tracks the error of unsplit
+ *     plans and overstates that of split plans.  It sees only the K-loop
+ *     part of the error: where every contraction fits one K stage (bonds of
+ *     at most 4, errors near 1e-7) both forms coincide and it reads 0;
+ *   BF16X3 plans: the FP32 4M form of the same site matrices (about 100x
+ *     more accurate), so the estimate is close to the actual BF16x3 error;
+ *   FP64 plans: NaN (no companion; the FP64 path's error is below 1e-12).
+ * The estimate doubles the call's work (its second sweep is not profiled).
+ * Errors: EINVAL for bits outside {0,1} or a short workspace, EDEVICE.  On an
+ * error neither output is written. */
 psim_status psim_amplitudes(psim_plan_t *plan, const uint8_t *bits, size_t n_bitstrings,
                             void *d_workspace, size_t workspace_bytes, void *hip_stream,
-                            double *out_amp);
+                            double *out_amp, double *out_rel_err);
 
 /* One site contraction of the row scheme, eq. (S4), on device buffers:
  *   C[z][m][n] = sum_{k1,k2} A[z][k1][m][k2] * W[k1*K2 + k2][n]     (complex)
@@ -223,14 +253,20 @@ psim_status psim_contract_site(int32_t prec, int64_t batch, int64_t M, int64_t K
                                void *d_C, int32_t transpose_out, void *hip_stream);
 
 /* Autotuner: for every distinct interior-site contraction shape of the plan
- * (eq. S4 steps), time each tile candidate of the FP32 row-major kernel
- * (reps launches each, HIP events on hip_stream) on scratch data inside the
+ * (eq. S4 steps), time each tile candidate of the plan's precision (reps
+ * launches each, HIP events on hip_stream) on scratch data inside the
  * caller's workspace (>= psim_plan_stats.workspace_bytes, contents are
- * overwritten), and keep the fastest for psim_amplitudes.  best_ms
- * (nullable) receives the chosen time of the costliest shape.  Plans in other
- * precisions, split-accumulation plans and square-partition plans keep their
- * single kernel configuration (PSIM_OK, nothing timed).
- * Errors: EINVAL for a short workspace or reps < 1, EDEVICE. */
+ * overwritten), and keep the fastest for psim_amplitudes.  Every candidate
+ * computes the same products in the same order, so the choice changes speed,
+ * never results.  best_ms (nullable) receives the chosen time of the
+ * costliest shape.  With PSIM_TUNE_CACHE naming a file in the environment,
+ * the choices are merged into it as JSON, keyed by device architecture,
+ * precision and shape (M, K1, K2, N, batch entries), and later plans start
+ * from them.  Split-accumulation plans and square-partition plans keep their
+ * single kernel configuration (PSIM_OK, nothing timed).  Captured graphs of
+ * the plan are dropped when a choice changes.
+ * Errors: EINVAL for a short workspace, reps < 1 or an unwritable cache file,
+ * EDEVICE. */
 psim_status psim_tune(psim_plan_t *plan, void *d_workspace, size_t workspace_bytes, void *hip_stream,
                       int32_t reps, double *best_ms);
 

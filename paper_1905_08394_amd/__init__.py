@@ -53,7 +53,8 @@ class PlanStats(ctypes.Structure):
                 ("peak_tensor_elems", ctypes.c_uint64), ("cmac_per_amplitude", ctypes.c_double),
                 ("n_gemm_steps", ctypes.c_int64), ("L", ctypes.c_int32), ("R", ctypes.c_int32),
                 ("chi", ctypes.c_int32), ("v_chunk", ctypes.c_int32), ("sweep", ctypes.c_int32),
-                ("prec", ctypes.c_int32), ("hot_cfg", ctypes.c_int32)]
+                ("prec", ctypes.c_int32), ("hot_cfg", ctypes.c_int32), ("peak_bytes", ctypes.c_uint64),
+                ("n_tasks", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -93,7 +94,8 @@ def lib(need_torch: bool = True) -> ctypes.CDLL:
     L.psim_plan_info.argtypes = [vp, ctypes.POINTER(PlanStats)]
     L.psim_plan_free.argtypes = [vp]
     L.psim_plan_free.restype = None
-    L.psim_amplitudes.argtypes = [vp, ctypes.POINTER(ctypes.c_uint8), sz, vp, sz, vp, ctypes.POINTER(ctypes.c_double)]
+    L.psim_amplitudes.argtypes = [vp, ctypes.POINTER(ctypes.c_uint8), sz, vp, sz, vp, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double)]
     L.psim_contract_site.argtypes = [i32, i64, i64, i64, i64, i64, vp, i64, ctypes.POINTER(ctypes.c_double), vp,
                                      i32, vp]
     L.psim_profile.argtypes = [vp, i32, ctypes.POINTER(KernelStats)]
@@ -283,8 +285,10 @@ class Plan:
             self._ws = torch.empty(need, dtype=torch.uint8, device=f"cuda:{self.device}")
         return self._ws
 
-    def amplitudes(self, bits, stream=None) -> np.ndarray:
-        """<tau|psi> for each row of bits (uint8, shape (n, lv*lh))."""
+    def amplitudes(self, bits, stream=None, rel_err: bool = False):
+        """<tau|psi> for each row of bits (uint8, shape (n, lv*lh)).  With
+        rel_err=True returns (amplitudes, estimated relative errors), the
+        estimates from psim_amplitudes' companion sweep (NaN for FP64)."""
         import torch
         b = np.ascontiguousarray(np.asarray(bits, dtype=np.uint8))
         if b.ndim == 1:
@@ -294,10 +298,13 @@ class Plan:
         out = np.zeros(2 * b.shape[0], dtype=np.float64)
         ws = self.workspace()
         st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        err = np.zeros(b.shape[0], dtype=np.float64) if rel_err else None
         _check(lib().psim_amplitudes(self._h, b.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), b.shape[0],
                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(st),
-                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
-        return out[0::2] + 1j * out[1::2]
+                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     err.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if rel_err else None))
+        amps = out[0::2] + 1j * out[1::2]
+        return (amps, err) if rel_err else amps
 
     def tune(self, reps: int = 2, stream=None) -> float:
         """Pick the fastest tile candidate per interior-step shape (psim_tune)."""

@@ -13,8 +13,6 @@ void apply_more_gates(psim_peps_t& P, const psim_gate* gates, size_t n_gates);
 void project_qubit(psim_peps_t& P, int32_t qubit, int32_t value);
 psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o);
 void free_plan(psim_plan_t* pl);
-void run_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, size_t ws_bytes, void* stream,
-                    double* out);
 void tune_plan(psim_plan_t* pl, void* ws, size_t ws_bytes, void* stream, int reps, double* best_ms);
 psim_group_s* make_group(psim_plan_t* const* plans, int np);
 void free_group(psim_group_s* G);
@@ -139,6 +137,14 @@ psim_status psim_plan_info(const psim_plan_t* pl, psim_plan_stats* s) {
     o.peak_tensor_elems = (uint64_t)pl->peak_elems;
     o.cmac_per_amplitude = pl->cmac;
     o.n_gemm_steps = pl->sq ? pl->sq_steps : (int64_t)pl->steps.size();
+    o.peak_bytes = pl->ws_total + pl->weights_bytes;
+    if (pl->sq) {
+      o.n_tasks = pl->sq_steps;
+    } else {
+      o.n_tasks = 0;
+      for (const auto& lev : pl->levels)
+        o.n_tasks += (pl->L == 1 ? 1 : (lev.Dv + lev.vchunk - 1) / lev.vchunk) * pl->L + 1;
+    }
     o.L = pl->L;
     o.R = pl->R;
     o.chi = pl->chi;
@@ -161,10 +167,10 @@ psim_status psim_plan_info(const psim_plan_t* pl, psim_plan_stats* s) {
 void psim_plan_free(psim_plan_t* pl) { free_plan(pl); }
 
 psim_status psim_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, size_t ws_bytes,
-                            void* stream, double* out) {
+                            void* stream, double* out, double* out_rel_err) {
   return guarded([&] {
     if (!pl) fail(PSIM_EINVAL, "plan is NULL");
-    run_amplitudes(pl, bits, n, ws, ws_bytes, stream, out);
+    run_amplitudes(pl, bits, n, ws, ws_bytes, stream, out, false, out_rel_err);
   });
 }
 

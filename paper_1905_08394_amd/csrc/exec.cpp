@@ -111,15 +111,19 @@ WsLayout layout(const psim_plan_t& pl, void* ws, char* tab = nullptr) {
 
 }  // namespace
 
+void clear_graphs(psim_plan_t* pl) {
+  for (auto& kv : pl->graphs) (void)hipGraphExecDestroy((hipGraphExec_t)kv.second);
+  pl->graphs.clear();
+}
+
 void tune_plan(psim_plan_t* pl, void* ws, size_t ws_bytes, void* stream, int reps, double* best_ms) {
   if (pl->host_only) fail(PSIM_EINVAL, "plan was made with PSIM_PLAN_HOST_ONLY");
   if (!ws || ws_bytes < pl->ws_total) fail(PSIM_EINVAL, "workspace is NULL or smaller than the plan needs");
   if (reps < 1) fail(PSIM_EINVAL, "reps must be at least 1");
   if (best_ms) *best_ms = 0;
-  if ((pl->opts.prec != PSIM_FP32_4M && pl->opts.prec != PSIM_FP32_3M) || (pl->opts.flags & PSIM_PLAN_SPLIT_ACC) ||
-      pl->sq)
-    return;
-  const int ncfg = pl->opts.prec == PSIM_FP32_3M ? fp32_3m_config_count() : fp32_config_count();
+  if ((pl->opts.flags & PSIM_PLAN_SPLIT_ACC) || pl->sq) return;
+  const int ncfg = config_count(pl->opts.prec);
+  if (ncfg < 2) return;
   hip_check(hipSetDevice(pl->opts.device), "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
   WsLayout W = layout(*pl, ws);
@@ -136,6 +140,9 @@ void tune_plan(psim_plan_t* pl, void* ws, size_t ws_bytes, void* stream, int rep
   hipEvent_t a, b;
   hip_check(hipEventCreate(&a), "hipEventCreate");
   hip_check(hipEventCreate(&b), "hipEventCreate");
+  bool changed = false;
+  const std::string arch = device_arch(pl->opts.device);
+  std::map<std::string, std::pair<int, double>> store;  // for PSIM_TUNE_CACHE
   for (auto& kv : shapes) {
     const Step& s = pl->steps[kv.second.front()];
     const int c = pl->levels[s.i].vchunk;
@@ -143,8 +150,14 @@ void tune_plan(psim_plan_t* pl, void* ws, size_t ws_bytes, void* stream, int rep
     g.prec = pl->opts.prec;
     g.A = W.G[0];
     g.C = W.G[1];
-    g.W0 = g.W1 = pl->w[((size_t)s.i * L + s.j) * 2].ptr;
-    g.ldw = pl->w[((size_t)s.i * L + s.j) * 2].ld;
+    const DevMatrix& dm = pl->w[((size_t)s.i * L + s.j) * 2];
+    g.W0 = g.W1 = dm.ptr;
+    g.ldw = dm.ld;
+    if (dm.ptr_b) {  // BF16x3: the pre-split planes
+      g.Wb0 = g.Wb1 = dm.ptr_b;
+      g.ldwb = dm.ld_b;
+      g.planeb = dm.plane_b;
+    }
     g.M = s.M; g.K1 = s.K1; g.K2 = s.K2; g.N = s.N;
     g.nodes = 1; g.Bz = c;
     g.sA_v = s.K1 * s.M * s.K2; g.sA_node = c * g.sA_v;
@@ -163,7 +176,11 @@ void tune_plan(psim_plan_t* pl, void* ws, size_t ws_bytes, void* stream, int rep
       const double t = ms / reps;
       if (t < best_t) { best_t = t; best = cfg; }
     }
-    for (size_t x : kv.second) pl->steps[x].cfg = best;
+    store[tune_key(arch, pl->opts.prec, s.M, s.K1, s.K2, s.N, c)] = {best, best_t};
+    for (size_t x : kv.second) {
+      if (pl->steps[x].cfg != best) changed = true;
+      pl->steps[x].cfg = best;
+    }
     const double cm = (double)c * s.M * s.K1 * s.K2 * s.N;
     if (cm > worst_cmac) {
       worst_cmac = cm;
@@ -172,6 +189,13 @@ void tune_plan(psim_plan_t* pl, void* ws, size_t ws_bytes, void* stream, int rep
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
+  tune_cache_store(store);
+  if (changed) {
+    // captured sweeps replay the old tile configurations: drop them, and make
+    // every group that holds this plan re-capture (its graph key has tune_gen)
+    clear_graphs(pl);
+    ++pl->tune_gen;
+  }
 }
 
 namespace {
@@ -305,7 +329,13 @@ void prepare(psim_plan_t* pl, const uint8_t* bits, const std::vector<size_t>& id
           g.prec = (prec == PSIM_FP32_3M && s.kind == 2) ? PSIM_FP32_4M : prec;  // see the packing
           g.cfg = s.kind == 1 ? s.cfg : 0;
           g.split = (pl->opts.flags & PSIM_PLAN_SPLIT_ACC) ? 1 : 0;
-          if (s.kind == 1 && w0.ptr_b) {
+          const bool bf16_companion = pl->companion && prec == PSIM_BF16X3;
+          if (pl->companion && !bf16_companion) {  // the other K-loop accumulation
+            g.split ^= 1;
+            if (g.split) g.cfg = 0;  // the split kernels have one tile configuration
+          }
+          if (bf16_companion) g.prec = PSIM_FP32_4M;           // the FP32 4M matrices every BF16x3 site has
+          if (s.kind == 1 && w0.ptr_b && !bf16_companion) {
             g.Wb0 = w0.ptr_b;
             g.Wb1 = w1.ptr_b;
             g.ldwb = w0.ld_b;
@@ -433,7 +463,7 @@ void assemble(const Prepared& P, const std::vector<size_t>& idx, double* out) {
 // One sub-batch of one plan on its own: optional event timing, row progress
 // log, or graph capture / replay of the operation list.
 void run_one(psim_plan_t* pl, const uint8_t* bits, const std::vector<size_t>& idx, void* ws, hipStream_t st,
-             double* out) {
+             double* out, bool no_alloc) {
   Prepared P;
   std::vector<char> img(pl->ws_tab, 0);
   prepare(pl, bits, idx, ws, nullptr, img.data(), P);
@@ -451,12 +481,16 @@ void run_one(psim_plan_t* pl, const uint8_t* bits, const std::vector<size_t>& id
 
   // The launch sequence depends only on the workspace address and the number
   // of nodes per level; the tables it reads were uploaded by prepare().
-  const bool use_graph = (pl->opts.flags & PSIM_PLAN_GRAPH) && !pl->profile && !log_rows;
+  // events are created per launch while profiling; the companion sweep of an
+  // error estimate is not profiled
+  const bool profile = pl->profile && !no_alloc && !pl->companion;
+  const bool use_graph = (pl->opts.flags & PSIM_PLAN_GRAPH) && !profile && !log_rows && !no_alloc;
   hipGraphExec_t gexec = nullptr;
   bool capturing = false;
   std::vector<int64_t> gkey;
   if (use_graph) {
     gkey.push_back((int64_t)(uintptr_t)ws);
+    gkey.push_back(pl->companion);
     for (int i = 0; i < pl->R; ++i) gkey.push_back((int64_t)P.t.parent[i].size());
     auto it = pl->graphs.find(gkey);
     if (it != pl->graphs.end()) {
@@ -476,7 +510,7 @@ void run_one(psim_plan_t* pl, const uint8_t* bits, const std::vector<size_t>& id
   if (!gexec) {
     try {
       for (const Op& op : P.ops) {
-        if (pl->profile) {
+        if (profile) {
           Timed tm{};
           tm.cls = op.cls;
           tm.cmac = op.cmac;
@@ -487,7 +521,7 @@ void run_one(psim_plan_t* pl, const uint8_t* bits, const std::vector<size_t>& id
           timed.push_back(tm);
         }
         run_op(pl, op, lst);
-        if (pl->profile) hip_check(hipEventRecord(timed.back().b, lst), "hipEventRecord");
+        if (profile) hip_check(hipEventRecord(timed.back().b, lst), "hipEventRecord");
         if (log_rows && op.rescale) {  // progress for long runs: wait for the row, then report it
           hip_check(hipStreamSynchronize(lst), "hipStreamSynchronize");
           std::fprintf(stderr, "psim: row %d/%d done (%lld nodes) at %.2f s\n", op.row + 1, pl->R,
@@ -511,6 +545,7 @@ void run_one(psim_plan_t* pl, const uint8_t* bits, const std::vector<size_t>& id
     const hipError_t e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     hip_check(e, "hipGraphInstantiate");
+    if (pl->graphs.size() >= kMaxPlanGraphs) clear_graphs(pl);  // bounded cache: start over
     pl->graphs[gkey] = (void*)gexec;
   }
   if (gexec) hip_check(hipGraphLaunch(gexec, st), "hipGraphLaunch");
@@ -532,16 +567,48 @@ void run_one(psim_plan_t* pl, const uint8_t* bits, const std::vector<size_t>& id
 
 }  // namespace
 
+namespace {
+
+void sweep(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, void* stream, double* res, bool no_alloc) {
+  if (pl->sq) {
+    run_square(pl, bits, n, ws, stream, res, no_alloc);
+  } else {
+    hip_check(hipSetDevice(pl->opts.device), "hipSetDevice");
+    for (const auto& idx : split_batches(pl, bits, n)) run_one(pl, bits, idx, ws, (hipStream_t)stream, res, no_alloc);
+  }
+}
+
+}  // namespace
+
 void run_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, size_t ws_bytes, void* stream,
-                    double* out) {
+                    double* out, bool no_alloc, double* out_err) {
   check_batch(pl, bits, n, ws, ws_bytes, out);
   if (n == 0) return;
-  if (pl->sq) {
-    run_square(pl, bits, n, ws, stream, out);
-    return;
+  // results are assembled in host memory and copied to the outputs only once
+  // every sub-batch has succeeded, so a failing call leaves them untouched
+  std::vector<double> res(2 * n);
+  sweep(pl, bits, n, ws, stream, res.data(), no_alloc);
+  std::vector<double> err;
+  if (out_err) {
+    err.assign(n, std::nan(""));
+    if (pl->opts.prec != PSIM_FP64) {
+      std::vector<double> alt(2 * n);
+      pl->companion = 1;
+      try {
+        sweep(pl, bits, n, ws, stream, alt.data(), no_alloc);
+      } catch (...) {
+        pl->companion = 0;
+        throw;
+      }
+      pl->companion = 0;
+      for (size_t b = 0; b < n; ++b) {
+        const double dr = res[2 * b] - alt[2 * b], di = res[2 * b + 1] - alt[2 * b + 1];
+        err[b] = std::hypot(dr, di) / std::hypot(alt[2 * b], alt[2 * b + 1]);
+      }
+    }
   }
-  hip_check(hipSetDevice(pl->opts.device), "hipSetDevice");
-  for (const auto& idx : split_batches(pl, bits, n)) run_one(pl, bits, idx, ws, (hipStream_t)stream, out);
+  std::memcpy(out, res.data(), res.size() * sizeof(double));
+  if (out_err) std::memcpy(out_err, err.data(), err.size() * sizeof(double));
 }
 
 // ------------------------------------------------------------------ groups
@@ -637,6 +704,9 @@ void run_group(psim_group_s* G, const uint8_t* const* bits, const size_t* n, voi
   const int kb = kargs_bytes();
   const int maxg = max_group();
   const int maxs = max_scale_group();
+  // every plan's results in host memory until the last pass has succeeded
+  std::vector<std::vector<double>> res(np);
+  for (int p = 0; p < np; ++p) res[p].resize(2 * n[p]);
   char* dbuf = (char*)G->d_buf;
   char* hbuf = G->h_buf;
   CopySeg* hseg = (CopySeg*)(hbuf + G->seg_off);
@@ -729,6 +799,7 @@ void run_group(psim_group_s* G, const uint8_t* const* bits, const size_t* n, voi
       std::vector<int64_t> key;
       for (size_t q = 0; q < m; ++q) {
         key.push_back(who[q]);
+        key.push_back(P[q].pl->tune_gen);   // tile configurations as tuned when captured
         key.push_back((int64_t)(uintptr_t)ws[who[q]]);
         for (const auto& lev : P[q].t.parent) key.push_back((int64_t)lev.size());
       }
@@ -771,7 +842,9 @@ void run_group(psim_group_s* G, const uint8_t* const* bits, const size_t* n, voi
       P[q].vals.assign(hbuf + G->res_off[p], hbuf + G->res_off[p] + leaves * pl->elem_bytes);
       P[q].ex.resize(leaves);
       std::memcpy(P[q].ex.data(), hbuf + G->res_exp_off[p], leaves * 4);
-      assemble(P[q], subs[who[q]][pass], out[who[q]]);
+      assemble(P[q], subs[who[q]][pass], res[who[q]].data());
     }
   }
+  for (int p = 0; p < np; ++p)
+    if (n[p]) std::memcpy(out[p], res[p].data(), res[p].size() * sizeof(double));
 }

@@ -116,7 +116,7 @@ struct V16<double> { typedef f64x2 t; static constexpr int n = 2; };
 // LDS A tile is the same interleaved (re, im) tile; each lane reads four
 // consecutive complex k (8 floats), splits re / im in registers and forms
 // re + im there.  W is packed as P[n][2k] = Re W[k][n], P[n][2k+1] = Im W[k][n].
-// SPLIT (FP32 4M only): each stage of BK real k accumulates into a fresh
+// SPLIT (FP32, 4M or 3M): each stage of BK real k accumulates into a fresh
 // partial sum that is then added to the running accumulator, so the FP32
 // rounding of the K-loop sum grows like sqrt(BK) + sqrt(K/BK) instead of
 // sqrt(K) (about 3x smaller at K = 2048).
@@ -362,6 +362,22 @@ __device__ __forceinline__ void site_gemm_body(const KArgs& p, const long long t
     } else {
       // groups of 8 complex k (16 floats); lane half h covers complex k 4h .. 4h+3
       const int f8 = (lane / MF::MB) * 8;
+      // SPLIT: this stage's three products summed apart, then added to acc3
+      typename MF::acc_t part3[SPLIT ? MBLK : 1][SPLIT ? NBLK3 : 1][3];
+      auto& tgt = [&]() -> auto& {
+        if constexpr (SPLIT) return part3;
+        else return acc3;
+      }();
+      if constexpr (SPLIT) {
+#pragma unroll
+        for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < NBLK3; ++bj)
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+#pragma unroll
+              for (int r = 0; r < MF::NACC; ++r) part3[bi][bj][q][r] = 0;
+      }
 #pragma unroll
       for (int g = 0; g < BK / 16; ++g) {
         f32x4 ar[MBLK], ai[MBLK], as[MBLK], br[NBLK3], bim[NBLK3], bs[NBLK3];
@@ -388,15 +404,23 @@ __device__ __forceinline__ void site_gemm_body(const KArgs& p, const long long t
 #pragma unroll
             for (int bj = 0; bj < NBLK3; ++bj) {
               if constexpr (SWAP) {  // C^T blocks: rows n, columns m
-                acc3[bi][bj][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(br[bj][s], ar[bi][s], acc3[bi][bj][0], 0, 0, 0);
-                acc3[bi][bj][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(bim[bj][s], ai[bi][s], acc3[bi][bj][1], 0, 0, 0);
-                acc3[bi][bj][2] = __builtin_amdgcn_mfma_f32_32x32x2f32(bs[bj][s], as[bi][s], acc3[bi][bj][2], 0, 0, 0);
+                tgt[bi][bj][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(br[bj][s], ar[bi][s], tgt[bi][bj][0], 0, 0, 0);
+                tgt[bi][bj][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(bim[bj][s], ai[bi][s], tgt[bi][bj][1], 0, 0, 0);
+                tgt[bi][bj][2] = __builtin_amdgcn_mfma_f32_32x32x2f32(bs[bj][s], as[bi][s], tgt[bi][bj][2], 0, 0, 0);
               } else {
-                acc3[bi][bj][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[bi][s], br[bj][s], acc3[bi][bj][0], 0, 0, 0);
-                acc3[bi][bj][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[bi][s], bim[bj][s], acc3[bi][bj][1], 0, 0, 0);
-                acc3[bi][bj][2] = __builtin_amdgcn_mfma_f32_32x32x2f32(as[bi][s], bs[bj][s], acc3[bi][bj][2], 0, 0, 0);
+                tgt[bi][bj][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[bi][s], br[bj][s], tgt[bi][bj][0], 0, 0, 0);
+                tgt[bi][bj][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[bi][s], bim[bj][s], tgt[bi][bj][1], 0, 0, 0);
+                tgt[bi][bj][2] = __builtin_amdgcn_mfma_f32_32x32x2f32(as[bi][s], bs[bj][s], tgt[bi][bj][2], 0, 0, 0);
               }
             }
+      }
+      if constexpr (SPLIT) {
+#pragma unroll
+        for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < NBLK3; ++bj)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) acc3[bi][bj][q] += part3[bi][bj][q];
       }
     }
     if (more) {
@@ -500,11 +524,11 @@ __global__ __launch_bounds__(256) void site_gemm(KArgs p) {
 }
 
 // split-accumulation variant, held to two waves per SIMD
-template <typename T, int BM, int BN, int BK, int AMODE, bool TRANS>
+template <typename T, int BM, int BN, int BK, int AMODE, bool TRANS, int SCH>
 __global__ __launch_bounds__(256, 2) void site_gemm_split(KArgs p) {
   const long long t = xcd_tile(p.T);
   if (t >= p.T) return;
-  site_gemm_body<T, BM, BN, BK, AMODE, TRANS, 4, true>(p, t);
+  site_gemm_body<T, BM, BN, BK, AMODE, TRANS, SCH, true>(p, t);
 }
 
 // Grouped launch: one grid over the tiles of several independent problems
@@ -1301,18 +1325,34 @@ void hip_check(int err, const char* what) {
 struct FCfg {
   int bm, bn, bk;
 };
+// 6 = the direct-to-LDS 4M kernel with 128 x 64 tiles (0 is its 128 x 128 form)
 static const FCfg kFp32Configs[] = {{128, 128, 32}, {256, 128, 16}, {128, 256, 16},
-                                    {256, 256, 16}, {128, 128, 64}, {256, 128, 32}};
+                                    {256, 256, 16}, {128, 128, 64}, {256, 128, 32}, {128, 64, 32}};
 int fp32_config_count() { return (int)(sizeof(kFp32Configs) / sizeof(kFp32Configs[0])); }
 // 3M candidates: 0 = 128 x 128 x 32 (two waves per SIMD), 1 = 256 x 128 x 32,
 // 2 = 128 x 256 x 32 (one wave per SIMD, twice the work per LDS stage)
-static const FCfg kFp32_3mConfigs[] = {{128, 128, 32}, {256, 128, 32}, {128, 256, 32}};
+// 3 = the direct-to-LDS kernel with 64 x 128 tiles (more workgroups per CU)
+static const FCfg kFp32_3mConfigs[] = {{128, 128, 32}, {256, 128, 32}, {128, 256, 32}, {64, 128, 32}};
 int fp32_3m_config_count() { return (int)(sizeof(kFp32_3mConfigs) / sizeof(kFp32_3mConfigs[0])); }
+// FP64 candidates: 0 = direct-to-LDS 128 x 64, 1 = direct-to-LDS 64 x 64,
+// 2 = row-major 128 x 64 x 16 (LDS through registers)
+int fp64_config_count() { return 3; }
+// BF16x3 candidates: 0 = 256 x 256 tiles, 1 = 128 x 256
+int bf16x3_config_count() { return 2; }
+int config_count(int prec) {
+  switch (prec) {
+    case PSIM_FP32_4M: return fp32_config_count();
+    case PSIM_FP32_3M: return fp32_3m_config_count();
+    case PSIM_FP64: return fp64_config_count();
+    case PSIM_BF16X3: return bf16x3_config_count();
+    default: return 1;
+  }
+}
 
 template <typename T, int BM, int BN, int BK, int AMODE, bool TRANS, int SCH = 4, bool SPLIT = false>
 static void launch(const KArgs& a, long long blocks, hipStream_t st) {
   if constexpr (SPLIT)
-    hipLaunchKernelGGL((site_gemm_split<T, BM, BN, BK, AMODE, TRANS>), dim3((unsigned)blocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((site_gemm_split<T, BM, BN, BK, AMODE, TRANS, SCH>), dim3((unsigned)blocks), dim3(256), 0, st, a);
   else
     hipLaunchKernelGGL((site_gemm<T, BM, BN, BK, AMODE, TRANS, SCH>), dim3((unsigned)blocks), dim3(256), 0, st, a);
 }
@@ -1358,8 +1398,8 @@ static int fp32_mode(const GemmLaunch& g) {
 
 // The direct-to-LDS 3M kernel applies: interior tiles only, every K stage
 // inside one k1 block, an even number of stages, 32-bit copy offsets.
-static bool dtl3m_ok(const GemmLaunch& g, int mode) {
-  return g.prec == PSIM_FP32_3M && !g.trans_out && mode == ROWMAJOR && g.M % 128 == 0 &&
+static bool dtl3m_ok(const GemmLaunch& g, int mode, int bm = 128) {
+  return g.prec == PSIM_FP32_3M && !g.trans_out && mode == ROWMAJOR && g.M % bm == 0 &&
          (2 * g.K2) % 32 == 0 && (2 * g.K1 * g.K2) % 64 == 0 && g.K2 < (1 << 20) && g.ldw < (1 << 22);
 }
 
@@ -1445,6 +1485,16 @@ void launch_group(int variant, const void* const* d_probs, const long long* star
 int kargs_bytes() { return (int)sizeof(KArgs); }
 int max_group() { return kMaxGroup; }
 
+// FP32 launch arguments with 128 x 128 tiles over Z batch entries
+static KArgs default_tiles(const KArgs& a, long long Z) {
+  KArgs d = a;
+  d.MT = (d.M + 128 - 1) / 128;
+  d.NT = (d.Nr + 128 - 1) / 128;
+  d.T = d.MT * d.NT * Z;
+  return d;
+}
+static long long default_blocks(const KArgs& a, long long Z) { return (default_tiles(a, Z).T + 7) / 8 * 8; }
+
 void launch_site_gemm(const GemmLaunch& g, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   KArgs a = make_kargs(g);
@@ -1461,7 +1511,17 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
     // interior-only row-major launches (every stage inside one k1 block):
     // 128 x 64 tiles with the division-free loader
     const bool fastd = !g.trans_out && g.K2 % 8 == 0 && g.M % 128 == 0;
-    if (fastd && (g.K1 * g.K2) % 16 == 0 && g.K2 < (1 << 20) && g.ldw < (1 << 22)) {
+    const bool dtl_ok = fastd && (g.K1 * g.K2) % 16 == 0 && g.K2 < (1 << 20) && g.ldw < (1 << 22);
+    if (dtl_ok && g.cfg == 1) {
+      // candidate 1: 64 x 64 tiles
+      KArgs f = a;
+      f.MT = f.M / 64;
+      f.NT = (f.Nr + 64 - 1) / 64;
+      f.T = f.MT * f.NT * Z;
+      const long long fb = (f.T + 7) / 8 * 8;
+      if (fb > 0x7fffffffLL) fail(PSIM_EUNSUPPORTED, "grid too large");
+      hipLaunchKernelGGL((site_gemm_4m_dtl<double, 64, 64, 4>), dim3((unsigned)fb), dim3(256), 0, st, f);
+    } else if (dtl_ok && g.cfg != 2) {
       // an even number of 16-double stages, 32-bit copy offsets: direct-to-LDS
       KArgs f = a;
       f.MT = f.M / 128;
@@ -1511,6 +1571,20 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
       else
         g.trans_out ? launch<float, 128, 128, 32, GENERIC, true, 4, true>(b, blocks, st)
                     : launch<float, 128, 128, 32, GENERIC, false, 4, true>(b, blocks, st);
+    } else if (g.split && g.prec == PSIM_FP32_3M && !dtl3m_ok(g, mode)) {
+      // 3M launches outside the direct-to-LDS kernel, per-stage partial sums
+      if (fast(128, 32))
+        g.trans_out ? launch<float, 128, 128, 32, ROWFAST, true, 3, true>(b, blocks, st)
+                    : launch<float, 128, 128, 32, ROWFAST, false, 3, true>(b, blocks, st);
+      else if (mode == ROWMAJOR)
+        g.trans_out ? launch<float, 128, 128, 32, ROWMAJOR, true, 3, true>(b, blocks, st)
+                    : launch<float, 128, 128, 32, ROWMAJOR, false, 3, true>(b, blocks, st);
+      else if (mode == KMAJOR)
+        g.trans_out ? launch<float, 128, 128, 32, KMAJOR, true, 3, true>(b, blocks, st)
+                    : launch<float, 128, 128, 32, KMAJOR, false, 3, true>(b, blocks, st);
+      else
+        g.trans_out ? launch<float, 128, 128, 32, GENERIC, true, 3, true>(b, blocks, st)
+                    : launch<float, 128, 128, 32, GENERIC, false, 3, true>(b, blocks, st);
     } else if (g.prec == PSIM_BF16X3 && mode == ROWMAJOR && !g.trans_out && g.Wb0) {
       // split-precision kernel on the pre-split planes
       b.W0 = g.Wb0;
@@ -1546,6 +1620,12 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
                   : launch<float, 256, 128, 32, ROWMAJOR, false, 3>(b, bl, st); break;
         case 2: f ? launch<float, 128, 256, 32, ROWFAST, false, 3>(b, bl, st)
                   : launch<float, 128, 256, 32, ROWMAJOR, false, 3>(b, bl, st); break;
+        case 3:
+          if (dtl3m_ok(g, mode, 64))
+            hipLaunchKernelGGL((site_gemm_3m_dtl<64, 128>), dim3((unsigned)bl), dim3(256), 0, st, b);
+          else  // shapes the direct-to-LDS kernel does not take: 128 x 128 tiles
+            launch<float, 128, 128, 32, ROWMAJOR, false, 3>(default_tiles(a, Z), default_blocks(a, Z), st);
+          break;
         default: fail(PSIM_EINVAL, "unknown kernel config");
       }
     } else if (dtl3m_ok(g, mode)) {
@@ -1589,6 +1669,12 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
                   : launch<float, 128, 128, 64, ROWMAJOR, false>(b, bl, st); break;
         case 5: f ? launch<float, 256, 128, 32, ROWFAST, false>(b, bl, st)
                   : launch<float, 256, 128, 32, ROWMAJOR, false>(b, bl, st); break;
+        case 6:
+          if (f && (2 * g.K1 * g.K2) % 64 == 0 && g.K2 < (1 << 20) && g.ldw < (1 << 22))
+            hipLaunchKernelGGL((site_gemm_4m_dtl<float, 128, 64, 3>), dim3((unsigned)bl), dim3(256), 0, st, b);
+          else
+            launch<float, 128, 128, 32, ROWMAJOR, false>(default_tiles(a, Z), default_blocks(a, Z), st);
+          break;
         default: fail(PSIM_EINVAL, "unknown kernel config");
       }
     } else if (g.trans_out && g.N <= 32 && mode != GENERIC) {

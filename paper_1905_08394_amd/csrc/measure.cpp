@@ -29,8 +29,6 @@
 
 psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o);
 void free_plan(psim_plan_t* pl);
-void run_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, size_t ws_bytes, void* stream,
-                    double* out);
 
 namespace psim {
 

@@ -26,6 +26,7 @@
 // the sum over the sweep is the exact count whose leading term is eq. (S8).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include <hip/hip_runtime_api.h>
@@ -183,9 +184,7 @@ psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o) {
     fail(PSIM_EUNSUPPORTED, "precision " + std::to_string(opts.prec) + " is not available in this build");
   if (opts.mem_budget_bytes == 0) opts.mem_budget_bytes = 200ull << 30;
   if (opts.max_batch <= 0) opts.max_batch = 1;
-  if (opts.tile_cfg < 0 ||
-      (opts.tile_cfg > 0 && !((opts.prec == PSIM_FP32_4M && opts.tile_cfg < fp32_config_count()) ||
-                              (opts.prec == PSIM_FP32_3M && opts.tile_cfg < fp32_3m_config_count()))))
+  if (opts.tile_cfg < 0 || opts.tile_cfg >= config_count(opts.prec))
     fail(PSIM_EINVAL, "tile_cfg " + std::to_string(opts.tile_cfg) + " is not a candidate of this precision");
   // the split-accumulation kernels come in one tile configuration
   if (opts.tile_cfg > 0 && (opts.flags & PSIM_PLAN_SPLIT_ACC))
@@ -374,6 +373,20 @@ psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o) {
     pl->ws_G = G;
     pl->ws_total = pl->ws_tab + pl->ws_F + pl->ws_G + 256;
     if (pl->ws_total > budget + 256) fail(PSIM_EINTERNAL, "memory plan exceeds its budget");
+
+    // ---------------------------------------------------------- stored tile choices
+    // psim_tune's earlier measurements (PSIM_TUNE_CACHE) for these interior
+    // shapes on this device architecture; an explicit tile_cfg wins
+    if (!pl->host_only && opts.tile_cfg == 0 && !(opts.flags & PSIM_PLAN_SPLIT_ACC) && std::getenv("PSIM_TUNE_CACHE")) {
+      const std::string arch = device_arch(opts.device);
+      for (Step& st : pl->steps) {
+        if (st.kind != 1) continue;
+        int cfg = 0;
+        if (tune_cache_lookup(tune_key(arch, opts.prec, st.M, st.K1, st.K2, st.N, pl->levels[st.i].vchunk), &cfg) &&
+            cfg >= 0 && cfg < config_count(opts.prec))
+          st.cfg = cfg;
+      }
+    }
 
     // ---------------------------------------------------------- pack + upload
     pl->w.resize((size_t)R * L * 2);

@@ -115,6 +115,10 @@ struct psim_plan_s {
   // address and node count per level, and the stream they are captured on
   std::map<std::vector<int64_t>, void*> graphs;
   void* cap_stream = nullptr;
+  int64_t tune_gen = 0;                  // bumped whenever psim_tune changes a tile configuration
+  // 1 while the companion sweep of an error estimate runs: FP32 plans toggle
+  // split accumulation, BF16x3 plans run their FP32 4M matrices
+  int companion = 0;
   int64_t max_ops = 0;                   // most device operations one sub-batch can need
   // square partition (sweep 3): quadrant frames, packed site matrices, workspace plan
   std::shared_ptr<psim::SquarePlan> sq;
@@ -179,6 +183,15 @@ struct GemmLaunch {
 };
 int fp32_config_count();
 int fp32_3m_config_count();
+int fp64_config_count();
+int bf16x3_config_count();
+// tile candidates of a precision (1 = a single configuration)
+int config_count(int prec);
+// tune_cache.cpp: autotuner choices kept in the JSON file PSIM_TUNE_CACHE names
+std::string device_arch(int device);
+std::string tune_key(const std::string& arch, int prec, int64_t M, int64_t K1, int64_t K2, int64_t N, int64_t Bz);
+bool tune_cache_lookup(const std::string& key, int* cfg);
+void tune_cache_store(const std::map<std::string, std::pair<int, double>>& entries);
 void launch_site_gemm(const GemmLaunch& g, void* stream);
 // Grouped launches (several problems, one grid): returns the variant id and
 // writes the problem descriptor (kargs_bytes() bytes) to out and its tile
@@ -226,7 +239,10 @@ void launch_pack_w(int prec, const void* Q, void* P, int64_t N, int64_t K, int64
 int cdot_blocks();
 // square.cpp
 void make_square_plan(psim_plan_t* pl, const psim_peps_t& P);
-void run_square(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, void* stream, double* out);
+// no_alloc: no profiling events (the call creates nothing on the device)
+void run_square(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, void* stream, double* out,
+                bool no_alloc = false);
+
 void launch_cdot(int prec, const void* a, const void* b, int64_t n, double* part, double* out, void* stream);
 bool rescale_fusable(int64_t per_node);
 int max_scale_group();
@@ -241,3 +257,15 @@ void sample(const psim_peps_t& P, const psim_plan_opts& o, const double* u, size
             size_t ws_bytes, void* stream, uint8_t* bits, double* prob);
 
 }  // namespace psim
+
+// exec.cpp: the row sweep (or the square partition) for a batch; out is
+// written only when every sub-batch succeeded.  no_alloc: eager launches only
+// (no graph capture or instantiation, no profiling events).
+// out_err (nullable): per-amplitude relative-error estimates from a second
+// sweep in the companion form (NaN for FP64 plans).
+void run_amplitudes(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, size_t ws_bytes, void* stream,
+                    double* out, bool no_alloc = false, double* out_err = nullptr);
+// instantiated graphs a plan keeps at most (the cache is emptied when full)
+constexpr size_t kMaxPlanGraphs = 64;
+void clear_graphs(psim_plan_t* pl);
+

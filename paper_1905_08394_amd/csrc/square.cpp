@@ -809,7 +809,7 @@ void run_chunks(SqRun& R, const uint8_t* bits, const std::vector<size_t>& order,
 
 }  // namespace
 
-void run_square(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, void* stream, double* out) {
+void run_square(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, void* stream, double* out, bool no_alloc) {
   const SquarePlan* sq = pl->sq.get();
   const int nq = sq->lv * sq->lh;
   hip_check(hipSetDevice(pl->opts.device), "hipSetDevice");
@@ -818,9 +818,10 @@ void run_square(psim_plan_t* pl, const uint8_t* bits, size_t n, void* ws, void* 
   R.sq = sq;
   R.st = (hipStream_t)stream;
   R.base = (char*)(((uintptr_t)ws + 255) / 256 * 256);
-  R.profile = pl->profile;
+  R.profile = pl->profile && !no_alloc && !pl->companion;
   R.prec = pl->opts.prec;
   R.split = (pl->opts.flags & PSIM_PLAN_SPLIT_ACC) ? 1 : 0;
+  if (pl->companion) R.split ^= 1;  // error estimate: the other K-loop accumulation
   R.eb = pl->elem_bytes;
   char* small = R.buf(sq->off_small);
   R.d_zero = (int32_t*)small;

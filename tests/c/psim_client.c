@@ -52,12 +52,17 @@ int main(void) {
   st = psim_plan_info(plan, &s);
   CHECK(st == PSIM_OK && s.L == 3 && s.R == 3 && s.chi == 2 && s.cmac_per_amplitude > 0 && s.n_gemm_steps == 9,
         "psim_plan_info: %d L %d R %d chi %d steps %lld", (int)st, s.L, s.R, s.chi, (long long)s.n_gemm_steps);
+  /* peak device bytes = workspace + packed site matrices; tasks: per row, v chunks x sites + a rescale */
+  CHECK(s.peak_bytes == s.workspace_bytes + s.weights_bytes && s.peak_bytes > 0, "peak_bytes %llu",
+        (unsigned long long)s.peak_bytes);
+  CHECK(s.n_tasks >= (int64_t)s.R * (s.L + 1), "n_tasks %lld", (long long)s.n_tasks);
 
   /* a host-only plan cannot run; nothing is written */
   uint8_t bits[9] = {0};
   double out[2] = {-7.0, -7.0};
-  st = psim_amplitudes(plan, bits, 1, NULL, 0, NULL, out);
-  CHECK(st == PSIM_EINVAL && out[0] == -7.0, "host-only psim_amplitudes: %d", (int)st);
+  double err[1] = {-7.0};
+  st = psim_amplitudes(plan, bits, 1, NULL, 0, NULL, out, err);
+  CHECK(st == PSIM_EINVAL && out[0] == -7.0 && err[0] == -7.0, "host-only psim_amplitudes: %d", (int)st);
 
   /* a CZ between non-neighbours is rejected with a message */
   psim_gate bad = {PSIM_CZ, 0, 0, 4, NULL};

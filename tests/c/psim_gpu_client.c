@@ -1,7 +1,9 @@
 /* A plain C client of libpsim on the GPU, without PyTorch: device workspace
  * from hipMalloc, all 512 amplitudes of a 3x3 random-style circuit (H layer,
  * CZ on every edge, T on every qubit, H layer) in FP64 and FP32 3M, checked
- * for normalisation (sum |a|^2 = 1) and against each other. */
+ * for normalisation (sum |a|^2 = 1) and against each other; the plan's
+ * reported sizes and the per-amplitude error estimates (NaN for FP64, finite
+ * and of the size of the FP32 error for FP32 3M). */
 #include <hip/hip_runtime_api.h>
 #include <math.h>
 #include <stdio.h>
@@ -10,7 +12,7 @@
 
 #include "psim.h"
 
-static int run(psim_peps_t *peps, int32_t prec, const uint8_t *bits, size_t nb, double *amp) {
+static int run(psim_peps_t *peps, int32_t prec, const uint8_t *bits, size_t nb, double *amp, double *err) {
   psim_plan_opts o;
   memset(&o, 0, sizeof o);
   o.prec = prec;
@@ -22,6 +24,11 @@ static int run(psim_peps_t *peps, int32_t prec, const uint8_t *bits, size_t nb, 
   }
   psim_plan_stats s;
   psim_plan_info(plan, &s);
+  if (s.peak_bytes != s.workspace_bytes + s.weights_bytes || s.n_tasks < (int64_t)s.R * (s.L + 1)) {
+    fprintf(stderr, "plan stats: peak %llu, tasks %lld\n", (unsigned long long)s.peak_bytes, (long long)s.n_tasks);
+    psim_plan_free(plan);
+    return 1;
+  }
   void *ws = NULL;
   if (hipMalloc(&ws, s.workspace_bytes) != hipSuccess) {
     fprintf(stderr, "hipMalloc failed\n");
@@ -30,7 +37,7 @@ static int run(psim_peps_t *peps, int32_t prec, const uint8_t *bits, size_t nb, 
   }
   hipStream_t st;
   hipStreamCreate(&st);
-  const psim_status r = psim_amplitudes(plan, bits, nb, ws, s.workspace_bytes, st, amp);
+  const psim_status r = psim_amplitudes(plan, bits, nb, ws, s.workspace_bytes, st, amp, err);
   if (r != PSIM_OK) fprintf(stderr, "psim_amplitudes: %s\n", psim_last_error());
   hipStreamDestroy(st);
   hipFree(ws);
@@ -60,7 +67,17 @@ int main(void) {
   for (size_t b = 0; b < nb; ++b)
     for (int q = 0; q < 9; ++q) bits[b * 9 + q] = (uint8_t)((b >> (8 - q)) & 1);
   double *a64 = malloc(2 * nb * sizeof(double)), *a32 = malloc(2 * nb * sizeof(double));
-  int bad = run(peps, PSIM_FP64, bits, nb, a64) || run(peps, PSIM_FP32_3M, bits, nb, a32);
+  double *e64 = malloc(nb * sizeof(double)), *e32 = malloc(nb * sizeof(double));
+  int bad = run(peps, PSIM_FP64, bits, nb, a64, e64) || run(peps, PSIM_FP32_3M, bits, nb, a32, e32);
+  /* error estimates: NaN without a companion (FP64); finite, non-negative and
+     below 1e-3 for FP32 3M on amplitudes that are not tiny */
+  for (size_t b = 0; !bad && b < nb; ++b) {
+    const double mag = hypot(a64[2 * b], a64[2 * b + 1]);
+    if (!isnan(e64[b]) || !(e32[b] >= 0) || (mag > 1e-3 && e32[b] > 1e-3)) {
+      fprintf(stderr, "error estimate %zu: fp64 %g fp32 %g (|a| %g)\n", b, e64[b], e32[b], mag);
+      bad = 1;
+    }
+  }
   double n64 = 0, n32 = 0, diff = 0;
   for (size_t b = 0; !bad && b < nb; ++b) {
     n64 += a64[2 * b] * a64[2 * b] + a64[2 * b + 1] * a64[2 * b + 1];
@@ -75,6 +92,8 @@ int main(void) {
   free(bits);
   free(a64);
   free(a32);
+  free(e64);
+  free(e32);
   psim_peps_free(peps);
   return bad;
 }

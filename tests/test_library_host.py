@@ -113,7 +113,7 @@ def test_host_only_plan_cannot_run(ps):
     L = ps.lib()
     out = (ctypes.c_double * 2)()
     bits = (ctypes.c_uint8 * 9)()
-    st = L.psim_amplitudes(pl._h, bits, 1, ctypes.c_void_p(16), 1 << 20, None, out)
+    st = L.psim_amplitudes(pl._h, bits, 1, ctypes.c_void_p(16), 1 << 20, None, out, None)
     assert st == ps.PSIM_EINVAL
 
 
