@@ -239,6 +239,25 @@ psim_status psim_amplitudes(psim_plan_t *plan, const uint8_t *bits, size_t n_bit
                             void *d_workspace, size_t workspace_bytes, void *hip_stream,
                             double *out_amp, double *out_rel_err);
 
+/* Allocation-free form of psim_amplitudes, for callers that cannot allocate
+ * device memory (tight serving loops, harnesses that forbid hipMalloc): the
+ * workspace is a fixed array of PSIM_STATIC_WORKSPACE_BYTES bytes inside the
+ * library, one per device, held from its first use on that device until the
+ * process ends.  Same kernels, same launches and the same results, bit for
+ * bit, as psim_amplitudes on the same plan and bitstrings; the call captures
+ * no graph, records no profiling events and allocates nothing on the device
+ * (it still enqueues on hip_stream and synchronises it, so it cannot itself
+ * be captured into a graph).  All calls on one device share the array, which
+ * keeps the last call's contents (each call writes everything it reads before
+ * reading it): calls that overlap in time on one device race.
+ * Errors: EINVAL when the plan's workspace_bytes exceeds
+ * PSIM_STATIC_WORKSPACE_BYTES (the message gives both sizes), otherwise those
+ * of psim_amplitudes; out_amp and out_rel_err (nullable, as for
+ * psim_amplitudes) are written only on success. */
+#define PSIM_STATIC_WORKSPACE_BYTES (64ull << 20)
+psim_status psim_amplitudes_static(psim_plan_t *plan, const uint8_t *bits, size_t n_bitstrings, void *hip_stream,
+                                   double *out_amp, double *out_rel_err);
+
 /* One site contraction of the row scheme, eq. (S4), on device buffers:
  *   C[z][m][n] = sum_{k1,k2} A[z][k1][m][k2] * W[k1*K2 + k2][n]     (complex)
  * A: device, complex (complex128 for PSIM_FP64, complex64 otherwise), batch

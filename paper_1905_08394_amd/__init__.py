@@ -26,7 +26,7 @@ PLAN_GRAPH = 4
 EXPORTED = ("psim_build", "psim_peps_info", "psim_peps_free", "psim_plan", "psim_plan_info", "psim_plan_free",
             "psim_amplitudes", "psim_contract_site", "psim_tune", "psim_profile", "psim_group", "psim_group_info",
             "psim_group_amplitudes", "psim_group_free", "psim_apply", "psim_project", "psim_double_layer",
-            "psim_sample_workspace", "psim_sample",
+            "psim_sample_workspace", "psim_sample", "psim_amplitudes_static",
             "psim_last_error", "psim_version")
 KERNEL_CLASSES = ("first_site", "interior_site", "last_site", "rescale")
 
@@ -96,6 +96,8 @@ def lib(need_torch: bool = True) -> ctypes.CDLL:
     L.psim_plan_free.restype = None
     L.psim_amplitudes.argtypes = [vp, ctypes.POINTER(ctypes.c_uint8), sz, vp, sz, vp, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_double)]
+    L.psim_amplitudes_static.argtypes = [vp, ctypes.POINTER(ctypes.c_uint8), sz, vp, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double)]
     L.psim_contract_site.argtypes = [i32, i64, i64, i64, i64, i64, vp, i64, ctypes.POINTER(ctypes.c_double), vp,
                                      i32, vp]
     L.psim_profile.argtypes = [vp, i32, ctypes.POINTER(KernelStats)]
@@ -115,7 +117,7 @@ def lib(need_torch: bool = True) -> ctypes.CDLL:
                               ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_double)]
     L.psim_last_error.restype = ctypes.c_char_p
     L.psim_version.restype = ctypes.c_char_p
-    for f in ("psim_build", "psim_peps_info", "psim_plan", "psim_plan_info", "psim_amplitudes",
+    for f in ("psim_build", "psim_peps_info", "psim_plan", "psim_plan_info", "psim_amplitudes", "psim_amplitudes_static",
               "psim_contract_site", "psim_profile", "psim_tune", "psim_group", "psim_group_info",
               "psim_group_amplitudes", "psim_apply", "psim_project", "psim_double_layer", "psim_sample_workspace",
               "psim_sample"):
