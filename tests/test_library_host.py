@@ -120,7 +120,9 @@ def test_host_only_plan_cannot_run(ps):
 def test_tile_cfg_validation(ps):
     P = ps.Peps(rqcgen.generate(3, 3, 8, 0))
     assert ps.Plan(P, prec="fp32", host_only=True, tile_cfg=5).stats()["hot_cfg"] in (0, 5)
-    for prec, bad in (("fp32", 6), ("fp32_3m", 3), ("fp64", 1), ("fp32", -1)):
+    for prec, good in (("fp32", 6), ("fp32_3m", 3), ("fp64", 2), ("bf16x3", 1)):
+        assert ps.Plan(P, prec=prec, host_only=True, tile_cfg=good).stats()["hot_cfg"] in (0, good)
+    for prec, bad in (("fp32", 7), ("fp32_3m", 4), ("fp64", 3), ("bf16x3", 2), ("fp32", -1)):
         with pytest.raises(ps.PsimError) as e:
             ps.Plan(P, prec=prec, host_only=True, tile_cfg=bad)
         assert e.value.status == ps.PSIM_EINVAL
