@@ -9,7 +9,7 @@ is seconds per amplitude; the line also carries the contraction TFLOP/s
 hot kernel's roofline (interior-site contraction, eq. S4, timed with HIP
 events on its launch stream), and the CPU oracle timed on a bounded sample.
 
-    python bench.py [--steps K] [--warmup W] [--prec fp32_3m|fp32|fp64|bf16x3] [--no-fp64] [--split-acc]
+    python bench.py [--steps K] [--warmup W] [--prec fp32_3m|fp32|fp64|bf16x3] [--no-fp64] [--no-split-acc]
                     [--budget-s S]
 
 Wall-clock budget: a 6x6 step takes tens of seconds, so the whole run is held
@@ -20,11 +20,12 @@ amplitude, square partition, plain FP64 GPU, CPU oracle), each of which runs
 one untimed-warmup-free step.  `steps` and `warmup` in the JSON line are the
 steps that actually ran; every timed step is the full 16-bitstring batch.
 
-The default path is the FP32-MFMA 3M scheme (the fastest FP32 form that
-meets the 1e-5 relative bar at this workload); the FP64 path is timed on the
-same batch for the comparison the metric names.  --split-acc runs the FP32
-forms with per-stage partial sums (smaller error, slower); its line carries
-no HBM traffic figure, since the counters were taken on the default kernel.
+The default path is the FP32-MFMA 3M scheme with per-stage partial sums in
+the K loops (split accumulation): the FP32 form that meets the 1e-5 relative
+bar on every oracle amplitude of this workload (without split accumulation
+the worst is 1.25e-5).  The FP64 path is timed on the same batch for the
+comparison the metric names.  --no-split-acc runs the FP32 forms with plain
+sequential sums (faster, less accurate).
 """
 import argparse
 import hashlib
@@ -41,7 +42,7 @@ METRIC = "seconds/amplitude + contraction TFLOP/s (% MFMA peak), 6x6 d40, FP32-M
 # MI355X dense MFMA peaks (TFLOP/s) of the arithmetic each path issues
 PEAK_TFLOPS = {"fp32": 157.3, "fp32_3m": 157.3, "fp64": 78.6, "bf16x3": 2500.0}
 ISSUED_PER_CMAC = {"fp32": 8, "fp32_3m": 6, "fp64": 8, "bf16x3": 24}   # real MFMA flops per complex multiply-add
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_interior_site_6x6_d40_{prec}.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_interior_site_6x6_d40_{prec}{split}.json")
 
 
 def log(*a):
@@ -227,6 +228,7 @@ def square_leg(args, circuit, bits, row_value):
     D^h x D^h x D^h steps, class 1 of the profile) against the MFMA peak."""
     a = argparse.Namespace(**vars(args))
     a.tune = False
+    a.mem_gib = max(args.mem_gib, 64 if args.prec != "fp64" else 128)   # quadrant tensors of 8 GiB each
     log("square partition ...")
     amps, el, prof, stats, (_, ran) = run_gpu(a, args.prec, circuit, bits, sweep=3, steps=1, warmup=0)
     n_amp = ran * len(bits)
@@ -253,7 +255,6 @@ def single_leg(args, circuit, bits):
     psim_amplitudes call of one bitstring (no sharing), one step."""
     import numpy as np
     a = argparse.Namespace(**vars(args))
-    a.tune = False
     base = bits[:1]
     for i, b in enumerate(bits):
         if np.array_equal(b, workload_base(args.lattice)):
@@ -326,6 +327,70 @@ def counters_program(prec="fp32_3m", reps=3):
     torch.cuda.synchronize()
     print(json.dumps({"prec": prec, "copy_bytes": 4 * n, "hot_step_algorithmic_bytes":
                       2 * batch * K1 * M * K2 * 8 + K1 * K2 * N * 4 * 4, "reps": reps}), flush=True)
+
+
+def seven_program(args):
+    """7x7 (1+40+1), the paper's flagship lattice (supplement S-IV), on one
+    MI355X: built and planned exactly (host-only plan: the exact multiply-add
+    count and the memory a one-GPU row sweep would need), then extrapolated
+    from measured launches.  Its boundary F = 32^7 complex64 is 256 GiB, so two
+    of them (input and output of a row) do not fit one GPU's 288 GB; nothing
+    of the amplitude itself runs.  Timed: the interior-site contraction at the
+    shape of a 7x7 row's (v, w) task -- the last input leg v and the first
+    output leg w fixed: M = 32^4 rows, K = N = 1024, two tasks per launch --
+    which is the shape of the 6x6 hot launch, with synthetic operands (the
+    kernel's speed does not depend on the values)."""
+    import numpy as np
+    import torch
+    import paper_1905_08394_amd as ps
+    import rqcgen
+    torch.cuda.set_device(0)
+    c = rqcgen.generate(7, 7, 40, 0)
+    t0 = time.perf_counter()
+    peps = ps.Peps(c)
+    t_build = time.perf_counter() - t0
+    plan = ps.Plan(peps, prec=args.prec, host_only=True, mem_budget=2 << 40, max_batch=1)
+    st = plan.stats()
+    plan.close()
+    D, L = st["chi"], st["L"]
+    # per-row multiply-adds of the row scheme on an L x L lattice with every
+    # bond D (site shapes of eqs. S2-S6); their sum is checked against the plan
+    first = sum(D ** (j + 3) for j in range(1, L - 1)) + D ** (L + 1)
+    inner = 2 * D ** (L + 2) + (L - 2) * D ** (L + 3)
+    last = D ** (L + 1) + sum(D ** (L - j + 2) for j in range(1, L - 1)) + D ** 2
+    total = first + (L - 2) * inner + last
+    assert abs(total / st["cmac_per_amplitude"] - 1) < 1e-12, (total, st["cmac_per_amplitude"])
+    hot_cmac = (L - 2) * (L - 2) * D ** (L + 3)          # interior sites of interior rows (eq. S4)
+    M, K1, K2, N, batch = D ** (L - 3), D, D, D * D, 2
+    A = torch.randn(batch * K1 * M * K2, dtype=torch.complex64, device="cuda")
+    rng = np.random.default_rng(0)
+    W = rng.standard_normal((K1 * K2, N)) + 1j * rng.standard_normal((K1 * K2, N))
+    ps.contract_site(args.prec, A, W, M, K1, K2, N, batch=batch)        # warm
+    torch.cuda.synchronize()
+    reps = 5
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        ps.contract_site(args.prec, A, W, M, K1, K2, N, batch=batch)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps        # includes the per-call upload of W (8 MiB)
+    rate = batch * M * K1 * K2 * N / (ms / 1e3)  # complex multiply-adds per second
+    issued = ISSUED_PER_CMAC[args.prec]
+    out = {"workload": "7x7 lattice, random circuit depth (1+40+1), D=32, one amplitude (row scheme)",
+           "prec": args.prec, "peps_build_s": t_build, "cmac_per_amplitude": st["cmac_per_amplitude"],
+           "cmac_per_row": {"first": first, "interior": inner, "last": last}, "hot_cmac_share": hot_cmac / total,
+           "boundary_bytes": int(D ** L * 8), "one_gpu_row_sweep_workspace_bytes": st["workspace_bytes"],
+           "hot_launch": {"shape": f"{batch} x (M = {M}, K = N = {K1 * K2})", "ms": ms,
+                          "tflops_issued": issued * rate / 1e12, "frac_of_peak": issued * rate / 1e12 /
+                          PEAK_TFLOPS[args.prec]},
+           "extrapolated_s_per_amplitude": total / rate,
+           "extrapolation": "exact multiply-add count of the amplitude / measured rate of the interior-site "
+                            "contraction at the (v, w) task shape; boundary rows and rescales (about 2 % of "
+                            "the work at 6x6) are counted at the same rate; the row sweep needs two 256 GiB "
+                            "boundaries, more than one GPU holds, so this is a projection, not a run",
+           "paper": "31 min per amplitude, 4096 Tianhe-2 fat nodes, FP64 (supplement S-IV)"}
+    print(json.dumps(out), flush=True)
 
 
 def fig2_program(args):
@@ -668,9 +733,10 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--prec", default="fp32_3m", choices=["fp32", "fp32_3m", "fp64", "bf16x3"])
-    ap.add_argument("--lattice", type=int, default=6)
+    ap.add_argument("--lattice", type=int, default=6,
+                    help="6: the headline workload; 7: the 7x7 (1+40+1) projection from measured launches")
     ap.add_argument("--depth", type=int, default=40)
-    ap.add_argument("--mem-gib", type=int, default=0, help="workspace budget (0: 96 GiB fp32, 128 GiB fp64)")
+    ap.add_argument("--mem-gib", type=int, default=0, help="workspace budget (0: 32 GiB fp32, 48 GiB fp64)")
     ap.add_argument("--no-fp64", dest="compare_fp64", action="store_false",
                     help="skip timing the FP64 path on the same batch")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -679,7 +745,8 @@ def main():
     ap.add_argument("--no-single", dest="single", action="store_false",
                     help="skip timing one amplitude on its own")
     ap.add_argument("--no-tune", dest="tune", action="store_false", help="skip the tile autotuner")
-    ap.add_argument("--split-acc", action="store_true", help="FP32 4M / 3M with per-stage partial sums")
+    ap.add_argument("--no-split-acc", dest="split_acc", action="store_false",
+                    help="FP32 4M / 3M with plain sequential K-loop sums instead of per-stage partial sums")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-square", dest="square", action="store_false",
                     help="skip timing the square partition on the same batch")
@@ -713,6 +780,9 @@ def main():
         args.mem_gib = args.mem_gib or 64
         fig2_program(args)
         return
+    if args.lattice == 7:
+        seven_program(args)
+        return
     if args.counters:
         counters_program(args.prec)
         return
@@ -722,7 +792,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     if args.mem_gib == 0:
-        args.mem_gib = 128 if args.prec == "fp64" else 96
+        # the batch shares rows 1-5, so one boundary per row suffices: the plan
+        # cuts the rows over v and w and needs 24 GiB (FP32) / 40 GiB (FP64)
+        args.mem_gib = 48 if args.prec == "fp64" else 32
 
     import torch
     torch.cuda.set_device(0)
@@ -762,14 +834,15 @@ def main():
     peak = PEAK_TFLOPS[args.prec]
     traffic = None
     tr = None
-    tfile = TRAFFIC_FILE.format(prec=args.prec)
+    split_on = bool(args.split_acc and args.prec in ("fp32", "fp32_3m"))
+    tfile = TRAFFIC_FILE.format(prec=args.prec, split="_split" if split_on else "")
     if os.path.exists(tfile) and args.lattice == 6:
         with open(tfile) as f:
             tr = json.load(f)
     per_launch_cmac = hot["cmac"] / max(hot["launches"], 1)
-    # the counters were taken on the default (unsplit) kernel
+    # counters of this precision's hot kernel, while its source section is unchanged
     if tr is not None and args.prec in KERNEL_SECTIONS and tr.get("kernel_source_sha256") == kernel_source_hash(args.prec) \
-            and "issued_flops_per_launch" in tr and not args.split_acc:
+            and "issued_flops_per_launch" in tr:
         # counters were taken on the largest interior launch; scale to this
         # run's average launch by issued flops (same K and N, M differs)
         traffic = tr["bytes_per_launch"] * issued * per_launch_cmac / tr["issued_flops_per_launch"]
@@ -790,16 +863,18 @@ def main():
                           "8x8 (1+25+1)": "under 1 h per amplitude, 2-core 2.8 GHz PC"},
         "dtype": {"fp64": "f64", "bf16x3": "bf16x3"}.get(args.prec, "f32"),
         "data": "synthetic",
-        "split_accumulation": bool(args.split_acc and args.prec in ("fp32", "fp32_3m")),
+        "split_accumulation": split_on,
         "config": {"workload": f"{args.lattice}x{args.lattice} lattice, random circuit depth (1+{args.depth}+1), "
                                f"D={stats['chi']}, exact row-scheme amplitudes of {len(bits)} bitstrings "
                                f"sharing rows 1-{args.lattice - 1} (last-row variants)",
                    "precision": {"fp32": "complex64 storage, FP32 MFMA (4M)",
-                                 "fp32_3m": "complex64 storage, FP32 MFMA (3M, Gauss)",
+                                 "fp32_3m": "complex64 storage, FP32 MFMA (3M, Gauss)" +
+                                            (", per-stage partial sums" if split_on else ""),
                                  "fp64": "complex128 storage, FP64 MFMA",
                                  "bf16x3": "complex64 storage, BF16 hi/lo split, 3 BF16 MFMA products, "
                                            "FP32 accumulation"}[args.prec],
                    "bitstrings_per_step": len(bits), "seed": 0, "v_chunk": stats["v_chunk"],
+                   "w_chunk": stats["w_chunk"],
                    "hot_tile_config": stats["hot_cfg"],
                    "workspace_gib": round(stats["workspace_bytes"] / 2 ** 30, 2)},
         "contraction_tflops": tflops,
@@ -835,7 +910,7 @@ def main():
 
     if compare64 and fits(2.8 * step_s + 30.0, "fp64"):
         a64 = argparse.Namespace(**vars(args))
-        a64.mem_gib = 128
+        a64.mem_gib = 48
         a64.tune = False
         amps64, el64, prof64, _, (_, ran64) = run_gpu(a64, "fp64", circuit, bits, steps=1, warmup=0)
         h64 = prof64["interior_site"]

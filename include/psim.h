@@ -93,9 +93,9 @@ typedef struct {
                                  together; otherwise bitstrings go one by one (same results) */
   int32_t device;             /* HIP device ordinal */
   int32_t tile_cfg;           /* interior-site tile candidate: 0 = default, k > 0 = candidate k
-                                 (FP32 4M: 1..6, FP32 3M: 1..3, FP64: 1..2, BF16X3: 1; not with
-                                 PSIM_PLAN_SPLIT_ACC, whose kernels have one tile configuration:
-                                 EINVAL).  With 0 and PSIM_TUNE_CACHE set in the environment, the
+                                 (FP32 4M: 1..6, FP32 3M: 1..3, FP64: 1..2, BF16X3: 1; with
+                                 PSIM_PLAN_SPLIT_ACC only 0, or 3 for FP32 3M (the split kernels'
+                                 tiles): EINVAL otherwise).  With 0 and PSIM_TUNE_CACHE set in the environment, the
                                  choices psim_tune stored there for this device architecture,
                                  precision and shape are used; psim_tune may replace them */
 } psim_plan_opts;
@@ -122,6 +122,9 @@ typedef struct {
                                  (the cut loop over v, supplement S-II); square partition, its
                                  device operations per bitstring (quadrant sites, joins,
                                  permutes, inner product) */
+  int32_t w_chunk;            /* rows cut over w as well as v (their intermediates exceed 2^29
+                                 elements, or the budget): the smallest number of w values per
+                                 pass; 0 when no row is cut over w */
 } psim_plan_stats;
 
 typedef struct psim_peps_s psim_peps_t;
@@ -190,7 +193,10 @@ psim_status psim_sample(const psim_peps_t *peps, const psim_plan_opts *opts, con
                         double *out_prob);
 
 /* Plan the exact contraction (supplement S-II, Fig. S2(a)): sweep axis, leg
- * orders, v-slicing of the boundary for the memory budget, exact work count.
+ * orders, cut loops over the last input leg v of each row and, where the
+ * per-v intermediates are large, over its first output leg w as well (every
+ * (v, w) pair then holds D^(L-1)-element intermediates; same work), the
+ * memory plan for the budget, exact work count.
  * Unless PSIM_PLAN_HOST_ONLY is set, projects both values of every site
  * (E = A[tau], eq. 7), packs them for the chosen precision and uploads them to
  * the device; the peps may be freed afterwards.
@@ -281,8 +287,9 @@ psim_status psim_contract_site(int32_t prec, int64_t batch, int64_t M, int64_t K
  * costliest shape.  With PSIM_TUNE_CACHE naming a file in the environment,
  * the choices are merged into it as JSON, keyed by device architecture,
  * precision and shape (M, K1, K2, N, batch entries), and later plans start
- * from them.  Split-accumulation plans and square-partition plans keep their
- * single kernel configuration (PSIM_OK, nothing timed).  Captured graphs of
+ * from them.  Split-accumulation plans choose among their split kernels'
+ * tiles (FP32 3M: 128 x 128 or 64 x 128; other precisions have one, and
+ * nothing is timed); square-partition plans keep their single configuration.  Captured graphs of
  * the plan are dropped when a choice changes.
  * Errors: EINVAL for a short workspace, reps < 1 or an unwritable cache file,
  * EDEVICE. */

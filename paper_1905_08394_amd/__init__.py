@@ -54,7 +54,7 @@ class PlanStats(ctypes.Structure):
                 ("n_gemm_steps", ctypes.c_int64), ("L", ctypes.c_int32), ("R", ctypes.c_int32),
                 ("chi", ctypes.c_int32), ("v_chunk", ctypes.c_int32), ("sweep", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("hot_cfg", ctypes.c_int32), ("peak_bytes", ctypes.c_uint64),
-                ("n_tasks", ctypes.c_int64)]
+                ("n_tasks", ctypes.c_int64), ("w_chunk", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

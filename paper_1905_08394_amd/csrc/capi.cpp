@@ -138,12 +138,16 @@ psim_status psim_plan_info(const psim_plan_t* pl, psim_plan_stats* s) {
     o.cmac_per_amplitude = pl->cmac;
     o.n_gemm_steps = pl->sq ? pl->sq_steps : (int64_t)pl->steps.size();
     o.peak_bytes = pl->ws_total + pl->weights_bytes;
+    o.w_chunk = 0;
+    for (const auto& lev : pl->levels)
+      if (w_cut(lev)) o.w_chunk = o.w_chunk ? std::min(o.w_chunk, lev.wchunk) : lev.wchunk;
     if (pl->sq) {
       o.n_tasks = pl->sq_steps;
     } else {
       o.n_tasks = 0;
       for (const auto& lev : pl->levels)
-        o.n_tasks += (pl->L == 1 ? 1 : (lev.Dv + lev.vchunk - 1) / lev.vchunk) * pl->L + 1;
+        o.n_tasks += (pl->L == 1 ? 1 : (lev.Dv + lev.vchunk - 1) / lev.vchunk) * (w_cut(lev) ? lev.Dw / lev.wchunk : 1) *
+                         pl->L + 1;
     }
     o.L = pl->L;
     o.R = pl->R;

@@ -121,9 +121,12 @@ void tune_plan(psim_plan_t* pl, void* ws, size_t ws_bytes, void* stream, int rep
   if (!ws || ws_bytes < pl->ws_total) fail(PSIM_EINVAL, "workspace is NULL or smaller than the plan needs");
   if (reps < 1) fail(PSIM_EINVAL, "reps must be at least 1");
   if (best_ms) *best_ms = 0;
-  if ((pl->opts.flags & PSIM_PLAN_SPLIT_ACC) || pl->sq) return;
-  const int ncfg = config_count(pl->opts.prec);
-  if (ncfg < 2) return;
+  if (pl->sq) return;
+  const bool split = (pl->opts.flags & PSIM_PLAN_SPLIT_ACC) != 0;
+  std::vector<int> cands;
+  for (int cfg = 0; cfg < config_count(pl->opts.prec); ++cfg)
+    if (!split || split_candidate(pl->opts.prec, cfg)) cands.push_back(cfg);
+  if (cands.size() < 2) return;
   hip_check(hipSetDevice(pl->opts.device), "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
   WsLayout W = layout(*pl, ws);
@@ -135,7 +138,7 @@ void tune_plan(psim_plan_t* pl, void* ws, size_t ws_bytes, void* stream, int rep
     const Step& s = pl->steps[x];
     if (s.kind != 1 || s.K2 % 2) continue;
     const Level& lev = pl->levels[s.i];
-    shapes[{s.M, s.K1, s.K2, s.N, (int64_t)lev.vchunk}].push_back(x);
+    shapes[{interior_rows(lev, s), s.K1, s.K2, s.N, interior_batch(lev)}].push_back(x);
   }
   hipEvent_t a, b;
   hip_check(hipEventCreate(&a), "hipEventCreate");
@@ -145,7 +148,8 @@ void tune_plan(psim_plan_t* pl, void* ws, size_t ws_bytes, void* stream, int rep
   std::map<std::string, std::pair<int, double>> store;  // for PSIM_TUNE_CACHE
   for (auto& kv : shapes) {
     const Step& s = pl->steps[kv.second.front()];
-    const int c = pl->levels[s.i].vchunk;
+    const Level& lev = pl->levels[s.i];
+    const int64_t c = interior_batch(lev), Ms = interior_rows(lev, s);
     GemmLaunch g;
     g.prec = pl->opts.prec;
     g.A = W.G[0];
@@ -158,13 +162,14 @@ void tune_plan(psim_plan_t* pl, void* ws, size_t ws_bytes, void* stream, int rep
       g.ldwb = dm.ld_b;
       g.planeb = dm.plane_b;
     }
-    g.M = s.M; g.K1 = s.K1; g.K2 = s.K2; g.N = s.N;
-    g.nodes = 1; g.Bz = c;
-    g.sA_v = s.K1 * s.M * s.K2; g.sA_node = c * g.sA_v;
-    g.sC_v = s.g_out; g.sC_node = c * s.g_out;
+    g.M = Ms; g.K1 = s.K1; g.K2 = s.K2; g.N = s.N;
+    g.nodes = 1; g.Bz = (int32_t)c;
+    g.sA_v = s.K1 * Ms * s.K2; g.sA_node = c * g.sA_v;
+    g.sC_v = Ms * s.N; g.sC_node = c * g.sC_v;
     int best = 0;
     double best_t = 1e300;
-    for (int cfg = 0; cfg < ncfg; ++cfg) {
+    g.split = split ? 1 : 0;
+    for (int cfg : cands) {
       g.cfg = cfg;
       launch_site_gemm(g, st);  // warm
       hip_check(hipEventRecord(a, st), "hipEventRecord");
@@ -176,12 +181,12 @@ void tune_plan(psim_plan_t* pl, void* ws, size_t ws_bytes, void* stream, int rep
       const double t = ms / reps;
       if (t < best_t) { best_t = t; best = cfg; }
     }
-    store[tune_key(arch, pl->opts.prec, s.M, s.K1, s.K2, s.N, c)] = {best, best_t};
+    store[tune_key(arch, pl->opts.prec, Ms, s.K1, s.K2, s.N, c, split)] = {best, best_t};
     for (size_t x : kv.second) {
       if (pl->steps[x].cfg != best) changed = true;
       pl->steps[x].cfg = best;
     }
-    const double cm = (double)c * s.M * s.K1 * s.K2 * s.N;
+    const double cm = (double)c * Ms * s.K1 * s.K2 * s.N;
     if (cm > worst_cmac) {
       worst_cmac = cm;
       if (best_ms) *best_ms = best_t;
@@ -317,81 +322,133 @@ void prepare(psim_plan_t* pl, const uint8_t* bits, const std::vector<size_t>& id
     const int64_t Fprev_elems = i == 0 ? 1 : pl->levels[i - 1].F_elems;
     char* Fcur = W.F[i % 2];
     const int c = lev.vchunk;
+    const bool wc = w_cut(lev);
+    const int cw = wc ? lev.wchunk : 1;
+    const int64_t rows_per_col = (prec == PSIM_FP32_3M) ? 1 : 2;  // packed rows per complex column (first site)
     for (int64_t g0 = 0; g0 < nodes; g0 += lev.group) {
       const int64_t gn = std::min<int64_t>(lev.group, nodes - g0);
       for (int v0 = 0; v0 < lev.Dv; v0 += c) {
-        for (int j = 0; j < L; ++j) {
-          const Step& s = pl->steps[(size_t)i * L + j];
-          const DevMatrix& w0 = pl->w[((size_t)i * L + j) * 2];
-          const DevMatrix& w1 = pl->w[((size_t)i * L + j) * 2 + 1];
-          Op op;
-          GemmLaunch& g = op.g;
-          g.prec = (prec == PSIM_FP32_3M && s.kind == 2) ? PSIM_FP32_4M : prec;  // see the packing
-          g.cfg = s.kind == 1 ? s.cfg : 0;
-          g.split = (pl->opts.flags & PSIM_PLAN_SPLIT_ACC) ? 1 : 0;
-          const bool bf16_companion = pl->companion && prec == PSIM_BF16X3;
-          if (pl->companion && !bf16_companion) {  // the other K-loop accumulation
-            g.split ^= 1;
-            if (g.split) g.cfg = 0;  // the split kernels have one tile configuration
-          }
-          if (bf16_companion) g.prec = PSIM_FP32_4M;           // the FP32 4M matrices every BF16x3 site has
-          if (s.kind == 1 && w0.ptr_b && !bf16_companion) {
-            g.Wb0 = w0.ptr_b;
-            g.Wb1 = w1.ptr_b;
-            g.ldwb = w0.ld_b;
-            g.planeb = w0.plane_b;
-          }
-          g.W0 = w0.ptr;
-          g.W1 = w1.ptr;
-          g.ldw = w0.ld;
-          g.tau = W.tau[i] + g0 * L + j;
-          g.tau_stride = L;
-          g.nodes = gn;
-          g.N = s.N;
-          g.K2 = s.K2;
-          g.M = s.M;
-          if (s.kind == 2) {
-            g.trans_out = 1;
-            g.Bz = 1;
-            g.C = Fcur + (uint64_t)g0 * lev.F_elems * eb;
-            g.sC_node = lev.F_elems;
-            if (L == 1) {  // the only site: contracts the parent's boundary directly
-              g.A = Fprev;
-              g.a_index = W.parent[i] + g0;
-              g.sA_node = Fprev_elems;
-              g.K1 = lev.Dv;
-              g.beta = 0;
-            } else {
-              g.A = W.G[(L - 2) % 2];
-              g.sA_node = (int64_t)c * s.M * s.K2;
-              g.K1 = c;
-              g.w_koff = (int64_t)v0 * s.K2;
-              g.beta = v0 > 0;
+        for (int w0 = 0; w0 < (wc ? lev.Dw : 1); w0 += cw) {
+          for (int j = 0; j < L; ++j) {
+            const Step& s = pl->steps[(size_t)i * L + j];
+            const DevMatrix& w0m = pl->w[((size_t)i * L + j) * 2];
+            const DevMatrix& w1m = pl->w[((size_t)i * L + j) * 2 + 1];
+            Op op;
+            GemmLaunch& g = op.g;
+            g.prec = (prec == PSIM_FP32_3M && s.kind == 2) ? PSIM_FP32_4M : prec;  // see the packing
+            g.cfg = s.kind == 1 ? s.cfg : 0;
+            g.split = (pl->opts.flags & PSIM_PLAN_SPLIT_ACC) ? 1 : 0;
+            const bool bf16_companion = pl->companion && prec == PSIM_BF16X3;
+            if (pl->companion && !bf16_companion) {  // the other K-loop accumulation
+              g.split ^= 1;
+              if (g.split && !split_candidate(prec, g.cfg)) g.cfg = 0;  // the split kernels' tiles
             }
-          } else {
-            g.Bz = c;
-            g.K1 = s.K1;
-            g.C = W.G[j % 2];
-            g.sC_v = s.g_out;
-            g.sC_node = (int64_t)c * s.g_out;
-            if (s.kind == 0) {
+            if (bf16_companion) g.prec = PSIM_FP32_4M;           // the FP32 4M matrices every BF16x3 site has
+            if (s.kind == 1 && w0m.ptr_b && !bf16_companion) {
+              g.Wb0 = w0m.ptr_b;
+              g.Wb1 = w1m.ptr_b;
+              g.ldwb = w0m.ld_b;
+              g.planeb = w0m.plane_b;
+            }
+            g.W0 = w0m.ptr;
+            g.W1 = w1m.ptr;
+            g.ldw = w0m.ld;
+            g.tau = W.tau[i] + g0 * L + j;
+            g.tau_stride = L;
+            g.nodes = gn;
+            g.N = s.N;
+            g.K2 = s.K2;
+            g.M = s.M;
+            if (s.kind == 2) {
+              g.trans_out = 1;
+              g.C = Fcur + (uint64_t)g0 * lev.F_elems * eb;
+              g.sC_node = lev.F_elems;
+              if (L == 1) {  // the only site: contracts the parent's boundary directly
+                g.Bz = 1;
+                g.A = Fprev;
+                g.a_index = W.parent[i] + g0;
+                g.sA_node = Fprev_elems;
+                g.K1 = lev.Dv;
+                g.beta = 0;
+              } else if (!wc) {
+                g.Bz = 1;
+                g.A = W.G[(L - 2) % 2];
+                g.sA_node = (int64_t)c * s.M * s.K2;
+                g.K1 = c;
+                g.w_koff = (int64_t)v0 * s.K2;
+                g.beta = v0 > 0;
+              } else {
+                // one batch entry per w of the chunk: its c v values are the
+                // K1 blocks; F[d_last][w][d_1 ..] receives C^T at column w
+                const int64_t Mt = s.M / lev.Dw;
+                g.M = Mt;
+                g.Bz = cw;
+                g.A = W.G[(L - 2) % 2];
+                g.sA_v = (int64_t)c * Mt * s.K2;
+                g.sA_node = (int64_t)cw * g.sA_v;
+                g.K1 = c;
+                g.w_koff = (int64_t)v0 * s.K2;
+                g.beta = v0 > 0;
+                g.C = (char*)g.C + (uint64_t)w0 * Mt * eb;
+                g.sC_v = Mt;
+                g.ldct = (int64_t)lev.Dw * Mt;
+              }
+            } else if (!wc) {
+              g.Bz = c;
+              g.K1 = s.K1;
+              g.C = W.G[j % 2];
+              g.sC_v = s.g_out;
+              g.sC_node = (int64_t)c * s.g_out;
+              if (s.kind == 0) {
+                g.A = (const char*)Fprev + (uint64_t)v0 * s.K1 * s.M * eb;
+                g.a_index = W.parent[i] + g0;
+                g.sA_node = Fprev_elems;
+                g.sA_v = s.K1 * s.M;
+              } else {
+                g.A = W.G[(j - 1) % 2];
+                g.sA_v = s.K1 * s.M * s.K2;
+                g.sA_node = (int64_t)c * g.sA_v;
+              }
+            } else if (s.kind == 0) {
+              // the columns (w, r_0) of the w chunk: packed rows from w0 * dr on;
+              // results stored per (w, v) pair as [w][v][m][r_0]
+              const int64_t dr = pl->cs[(size_t)i * L].dr;
+              const uint64_t off = (uint64_t)w0 * dr * rows_per_col * w0m.ld * (prec == PSIM_FP64 ? 8 : 4);
+              g.W0 = (const char*)w0m.ptr + off;
+              g.W1 = (const char*)w1m.ptr + off;
+              g.N = (int64_t)cw * dr;
+              g.Bz = c;
+              g.K1 = s.K1;
               g.A = (const char*)Fprev + (uint64_t)v0 * s.K1 * s.M * eb;
               g.a_index = W.parent[i] + g0;
               g.sA_node = Fprev_elems;
               g.sA_v = s.K1 * s.M;
+              g.C = W.G[0];
+              g.sC_v = s.M * dr;
+              g.nb = dr;
+              g.sCw = (int64_t)c * s.M * dr;
+              g.sC_node = (int64_t)cw * g.sCw;
             } else {
+              // interior site on every (w, v) pair of the pass, d_0 out of the rows
+              const int64_t Mt = s.M / lev.Dw;
+              g.M = Mt;
+              g.Bz = c * cw;
+              g.K1 = s.K1;
               g.A = W.G[(j - 1) % 2];
-              g.sA_v = s.K1 * s.M * s.K2;
-              g.sA_node = (int64_t)c * g.sA_v;
+              g.sA_v = s.K1 * Mt * s.K2;
+              g.sA_node = (int64_t)c * cw * g.sA_v;
+              g.C = W.G[j % 2];
+              g.sC_v = Mt * s.N;
+              g.sC_node = (int64_t)c * cw * g.sC_v;
             }
+            op.cls = s.kind;
+            op.cmac = (double)g.nodes * g.Bz * g.M * g.K1 * g.K2 * g.N;
+            op.bytes = (double)eb * ((double)g.nodes * g.Bz * g.K1 * g.M * g.K2 +
+                                     (double)g.nodes * g.Bz * g.M * g.N * (g.beta ? 2 : 1) +
+                                     (double)g.K1 * g.K2 * g.N);
+            op.row = i;
+            P.ops.push_back(op);
           }
-          op.cls = s.kind;
-          op.cmac = (double)g.nodes * g.Bz * g.M * g.K1 * g.K2 * g.N;
-          op.bytes = (double)eb * ((double)g.nodes * g.Bz * g.K1 * g.M * g.K2 +
-                                   (double)g.nodes * g.Bz * g.M * g.N * (g.beta ? 2 : 1) +
-                                   (double)g.K1 * g.K2 * g.N);
-          op.row = i;
-          P.ops.push_back(op);
         }
         if (L == 1) break;  // the single site consumed every v at once
       }

@@ -62,6 +62,9 @@ struct KArgs {
   long long sA_node, sA_v, sC_node, sC_v;
   long long MT, NT, T;
   long long plane;    // BF16x3: elements between the hi and lo planes of W
+  long long ldct;     // transposed stores: complex elements between rows n of C (M for a dense C^T)
+  long long nb, sCw;  // nb > 0: plain stores split N into blocks of nb columns, block b at b * sCw
+                      // (C[n / nb][m][n % nb]); 0: row-major C[m][n]
   int Bz, trans_out, beta;
 };
 
@@ -443,7 +446,7 @@ __device__ __forceinline__ void site_gemm_body(const KArgs& p, const long long t
           const long long nr = n0 + wc * WN + bj * MF::MB + MF::out_row(lane, r);  // even
           if (m < p.M && nr < p.Nr) {
             f32x2 v = {acc[bi][bj][r], acc[bi][bj][r + 1]};
-            f32x2* dst = (f32x2*)(C + 2 * ((nr >> 1) * p.M + m));
+            f32x2* dst = (f32x2*)(C + 2 * ((nr >> 1) * p.ldct + m));
             if (p.beta) v += *dst;
             *dst = v;
           }
@@ -461,7 +464,7 @@ __device__ __forceinline__ void site_gemm_body(const KArgs& p, const long long t
           if (m < p.M && n < p.N) {
             const T t1 = acc3[bi][bj][0][r], t2 = acc3[bi][bj][1][r], t3 = acc3[bi][bj][2][r];
             f32x2 v = {t1 - t2, t3 - t1 - t2};
-            f32x2* dst = (f32x2*)(C + 2 * (n * p.M + m));
+            f32x2* dst = (f32x2*)(C + 2 * (n * p.ldct + m));
             if (p.beta) v += *dst;
             *dst = v;
           }
@@ -478,9 +481,14 @@ __device__ __forceinline__ void site_gemm_body(const KArgs& p, const long long t
           if (row < p.M && col < p.Nr) {
             const T v = acc[bi][bj][r];
             if constexpr (!TRANS) {
-              C[row * p.Nr + col] = v;
+              if (p.nb) {
+                const long long cc = col >> 1;
+                C[2 * ((cc / p.nb) * p.sCw + row * p.nb + cc % p.nb) + (col & 1)] = v;
+              } else {
+                C[row * p.Nr + col] = v;
+              }
             } else {
-              T* dst = C + 2 * ((col >> 1) * p.M + row) + (col & 1);
+              T* dst = C + 2 * ((col >> 1) * p.ldct + row) + (col & 1);
               *dst = p.beta ? *dst + v : v;
             }
           }
@@ -498,7 +506,9 @@ __device__ __forceinline__ void site_gemm_body(const KArgs& p, const long long t
           if (row < p.M && col < p.N) {
             const T t1 = acc3[bi][bj][0][r], t2 = acc3[bi][bj][1][r], t3 = acc3[bi][bj][2][r];
             f32x2 v = {t1 - t2, t3 - t1 - t2};
-            f32x2* dst = (f32x2*)(C + 2 * (TRANS ? col * p.M + row : row * p.N + col));
+            f32x2* dst = (f32x2*)(C + 2 * (TRANS  ? col * p.ldct + row
+                                           : p.nb ? (col / p.nb) * p.sCw + row * p.nb + col % p.nb
+                                                  : row * p.N + col));
             if constexpr (TRANS) {
               if (p.beta) v += *dst;
             }
@@ -765,8 +775,8 @@ __global__ __launch_bounds__(256, 3) void site_gemm_3m_dtl(KArgs p) {
 
 // split-accumulation form (PSIM_PLAN_SPLIT_ACC): twice the accumulators, two
 // workgroups per CU
-template <int BM, int BN>
-__global__ __launch_bounds__(256, 2) void site_gemm_3m_dtl_split(KArgs p) {
+template <int BM, int BN, int OCC = 2>
+__global__ __launch_bounds__(256, OCC) void site_gemm_3m_dtl_split(KArgs p) {
   const long long t = xcd_tile(p.T);
   if (t >= p.T) return;
   dtl3m_body<BM, BN, true>(p, t);
@@ -968,18 +978,24 @@ __global__ __launch_bounds__(256) void site_gemm_bf16x3(KArgs p) {
   const long long sK1 = p.M * p.K2;
   const unsigned K2u = (unsigned)p.K2;
 
-  f32x4 ra[A_VECS];
-  f32x4 rbh[B_VECS], rbl[B_VECS];  // 16 bytes = 8 bf16 each
+  // Staging registers, two sets: the global loads run two stages ahead of
+  // the MFMAs (stage s is loaded into set s % 2), so a load has about two
+  // stages of MFMA work to arrive before its data is converted and stored.
+  struct Stage {
+    f32x4 a[A_VECS];
+    f32x4 bh[B_VECS], bl[B_VECS];  // 16 bytes = 8 bf16 each
+  };
+  Stage set0, set1;
 
-  long long fk1 = 0, fk2 = 0;  // FAST: next stage's (k1, k2), as in ROWFAST
-  auto load = [&](long long kr0) {
+  long long fk1 = 0, fk2 = 0;  // FAST: next stage's (k1, k2), as in ROWFAST; loads are issued in stage order
+  auto load = [&](long long kr0, Stage& r) {
     if constexpr (FAST) {  // interior tile, stage inside one k1 (see ROWFAST)
       const float* base = A + 2 * (fk1 * sK1 + m0 * p.K2 + fk2);
 #pragma unroll
       for (int it = 0; it < A_VECS; ++it) {
         const int lin = it * 256 + tid;
         const int row = lin / (BK / 4), kq = lin % (BK / 4);
-        ra[it] = *(const f32x4*)(base + 2 * (long long)row * p.K2 + kq * 4);
+        r.a[it] = *(const f32x4*)(base + 2 * (long long)row * p.K2 + kq * 4);
       }
       fk2 += BK / 2;
       if (fk2 == p.K2) {
@@ -998,7 +1014,7 @@ __global__ __launch_bounds__(256) void site_gemm_bf16x3(KArgs p) {
           const unsigned k1 = k / K2u, k2 = k - k1 * K2u;
           v = *(const f32x4*)(A + 2 * ((long long)k1 * sK1 + m * p.K2 + k2));
         }
-        ra[it] = v;
+        r.a[it] = v;
       }
     }
 #pragma unroll
@@ -1006,11 +1022,11 @@ __global__ __launch_bounds__(256) void site_gemm_bf16x3(KArgs p) {
       const int lin = it * 256 + tid;
       const int row = lin / (BK / 8), kq = lin % (BK / 8);
       const long long off = (n0 + row) * p.ldw + kr0 + kq * 8;
-      rbh[it] = *(const f32x4*)(Wh + off);
-      rbl[it] = *(const f32x4*)(Wl + off);
+      r.bh[it] = *(const f32x4*)(Wh + off);
+      r.bl[it] = *(const f32x4*)(Wl + off);
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](int buf, const Stage& r) {
 #pragma unroll
     for (int it = 0; it < A_VECS; ++it) {
       const int lin = it * 256 + tid;
@@ -1018,8 +1034,8 @@ __global__ __launch_bounds__(256) void site_gemm_bf16x3(KArgs p) {
       bf16x4 hi, lo;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        hi[e] = (__bf16)ra[it][e];
-        lo[e] = (__bf16)(ra[it][e] - (float)hi[e]);
+        hi[e] = (__bf16)r.a[it][e];
+        lo[e] = (__bf16)(r.a[it][e] - (float)hi[e]);
       }
       *(bf16x4*)(&sAh[buf][row * LD + kq * 4]) = hi;
       *(bf16x4*)(&sAl[buf][row * LD + kq * 4]) = lo;
@@ -1028,8 +1044,8 @@ __global__ __launch_bounds__(256) void site_gemm_bf16x3(KArgs p) {
     for (int it = 0; it < B_VECS; ++it) {
       const int lin = it * 256 + tid;
       const int row = lin / (BK / 8), kq = lin % (BK / 8);
-      *(f32x4*)(&sBh[buf][row * LD + kq * 8]) = rbh[it];
-      *(f32x4*)(&sBl[buf][row * LD + kq * 8]) = rbl[it];
+      *(f32x4*)(&sBh[buf][row * LD + kq * 8]) = r.bh[it];
+      *(f32x4*)(&sBl[buf][row * LD + kq * 8]) = r.bl[it];
     }
   };
 
@@ -1042,38 +1058,54 @@ __global__ __launch_bounds__(256) void site_gemm_bf16x3(KArgs p) {
       for (int r = 0; r < 16; ++r) acc[bi][bj][r] = 0;
 
   const long long nk = (p.Kr + BK - 1) / BK;
-  load(0);
-  store(0);
+  load(0, set0);
+  store(0, set0);
+  if (nk > 1) load(BK, set1);
   __syncthreads();
   const int frow = lane & 31, fk = (lane >> 5) * 8;
-  for (long long kt = 0; kt < nk; ++kt) {
-    const int cur = (int)(kt & 1);
-    const bool more = kt + 1 < nk;
-    if (more) load((kt + 1) * BK);
-    bf16x8 ah[MBLK], al[MBLK], bh[NBLK], bl[NBLK];
-#pragma unroll
-    for (int bi = 0; bi < MBLK; ++bi) {
-      const int o = (wr * WM + bi * 32 + frow) * LD + fk;
-      ah[bi] = *(const bf16x8*)(&sAh[cur][o]);
-      al[bi] = *(const bf16x8*)(&sAl[cur][o]);
-    }
-#pragma unroll
-    for (int bj = 0; bj < NBLK; ++bj) {
-      const int o = (wc * WN + bj * 32 + frow) * LD + fk;
-      bh[bj] = *(const bf16x8*)(&sBh[cur][o]);
-      bl[bj] = *(const bf16x8*)(&sBl[cur][o]);
-    }
-#pragma unroll
-    for (int bi = 0; bi < MBLK; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < NBLK; ++bj) {
-        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[bi], bh[bj], acc[bi][bj], 0, 0, 0);
-        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bl[bj], acc[bi][bj], 0, 0, 0);
-        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bh[bj], acc[bi][bj], 0, 0, 0);
-      }
-    if (more) store(cur ^ 1);
-    __syncthreads();
+  // One stage: its fragments come from LDS buffer kt & 1; NEXT holds stage
+  // kt + 1 (stored into the other buffer halfway through the MFMAs, where the
+  // conversion and the LDS stores overlap the matrix work), FREE receives the
+  // loads of stage kt + 2.  Each accumulator sees its products in the same
+  // order as with one staging set.
+#define PSIM_BF16X3_STAGE(KT, NEXT, FREE)                                                                   \
+  {                                                                                                       \
+    const long long kt_ = (KT);                                                                           \
+    const int cur = (int)(kt_ & 1);                                                                       \
+    if (kt_ + 2 < nk) load((kt_ + 2) * BK, FREE);                                                         \
+    bf16x8 ah[MBLK], al[MBLK], bh[NBLK], bl[NBLK];                                                        \
+    _Pragma("unroll") for (int bi = 0; bi < MBLK; ++bi) {                                                 \
+      const int o = (wr * WM + bi * 32 + frow) * LD + fk;                                                 \
+      ah[bi] = *(const bf16x8*)(&sAh[cur][o]);                                                            \
+      al[bi] = *(const bf16x8*)(&sAl[cur][o]);                                                            \
+    }                                                                                                     \
+    _Pragma("unroll") for (int bj = 0; bj < NBLK; ++bj) {                                                 \
+      const int o = (wc * WN + bj * 32 + frow) * LD + fk;                                                 \
+      bh[bj] = *(const bf16x8*)(&sBh[cur][o]);                                                            \
+      bl[bj] = *(const bf16x8*)(&sBl[cur][o]);                                                            \
+    }                                                                                                     \
+    _Pragma("unroll") for (int bi = 0; bi < MBLK / 2; ++bi)                                               \
+      _Pragma("unroll") for (int bj = 0; bj < NBLK; ++bj) {                                               \
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[bi], bh[bj], acc[bi][bj], 0, 0, 0);      \
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bl[bj], acc[bi][bj], 0, 0, 0);      \
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bh[bj], acc[bi][bj], 0, 0, 0);      \
+      }                                                                                                   \
+    if (kt_ + 1 < nk) store(cur ^ 1, NEXT);                                                               \
+    _Pragma("unroll") for (int bi = MBLK / 2; bi < MBLK; ++bi)                                            \
+      _Pragma("unroll") for (int bj = 0; bj < NBLK; ++bj) {                                               \
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[bi], bh[bj], acc[bi][bj], 0, 0, 0);      \
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bl[bj], acc[bi][bj], 0, 0, 0);      \
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bh[bj], acc[bi][bj], 0, 0, 0);      \
+      }                                                                                                   \
+    __syncthreads();                                                                                      \
   }
+  long long kt = 0;
+  for (; kt + 1 < nk; kt += 2) {
+    PSIM_BF16X3_STAGE(kt, set1, set0)
+    PSIM_BF16X3_STAGE(kt + 1, set0, set1)
+  }
+  if (kt < nk) PSIM_BF16X3_STAGE(kt, set1, set0)
+#undef PSIM_BF16X3_STAGE
 
 #pragma unroll
   for (int bi = 0; bi < MBLK; ++bi)
@@ -1386,6 +1418,10 @@ static KArgs make_kargs(const GemmLaunch& g) {
   a.Bz = g.Bz;
   a.trans_out = g.trans_out;
   a.beta = g.beta;
+  a.ldct = g.ldct ? g.ldct : g.M;
+  a.nb = g.nb;
+  a.sCw = g.sCw;
+  if (g.nb && (g.trans_out || g.nb < 1)) fail(PSIM_EINVAL, "site gemm: split-N stores need a plain store");
   return a;
 }
 
@@ -1399,7 +1435,7 @@ static int fp32_mode(const GemmLaunch& g) {
 // The direct-to-LDS 3M kernel applies: interior tiles only, every K stage
 // inside one k1 block, an even number of stages, 32-bit copy offsets.
 static bool dtl3m_ok(const GemmLaunch& g, int mode, int bm = 128) {
-  return g.prec == PSIM_FP32_3M && !g.trans_out && mode == ROWMAJOR && g.M % bm == 0 &&
+  return g.prec == PSIM_FP32_3M && !g.trans_out && !g.nb && mode == ROWMAJOR && g.M % bm == 0 &&
          (2 * g.K2) % 32 == 0 && (2 * g.K1 * g.K2) % 64 == 0 && g.K2 < (1 << 20) && g.ldw < (1 << 22);
 }
 
@@ -1510,7 +1546,7 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
     const bool kmajor = g.K2 == 1 && g.K1 > 1;
     // interior-only row-major launches (every stage inside one k1 block):
     // 128 x 64 tiles with the division-free loader
-    const bool fastd = !g.trans_out && g.K2 % 8 == 0 && g.M % 128 == 0;
+    const bool fastd = !g.trans_out && !g.nb && g.K2 % 8 == 0 && g.M % 128 == 0;
     const bool dtl_ok = fastd && (g.K1 * g.K2) % 16 == 0 && g.K2 < (1 << 20) && g.ldw < (1 << 22);
     if (dtl_ok && g.cfg == 1) {
       // candidate 1: 64 x 64 tiles
@@ -1585,7 +1621,7 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
       else
         g.trans_out ? launch<float, 128, 128, 32, GENERIC, true, 3, true>(b, blocks, st)
                     : launch<float, 128, 128, 32, GENERIC, false, 3, true>(b, blocks, st);
-    } else if (g.prec == PSIM_BF16X3 && mode == ROWMAJOR && !g.trans_out && g.Wb0) {
+    } else if (g.prec == PSIM_BF16X3 && mode == ROWMAJOR && !g.trans_out && !g.nb && g.Wb0) {
       // split-precision kernel on the pre-split planes
       b.W0 = g.Wb0;
       b.W1 = g.Wb1 ? g.Wb1 : g.Wb0;
@@ -1607,7 +1643,7 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
         hipLaunchKernelGGL((site_gemm_bf16x3<128, 256, true>), dim3((unsigned)bl), dim3(256), 0, st, b);
       else
         hipLaunchKernelGGL((site_gemm_bf16x3<128, 256, false>), dim3((unsigned)bl), dim3(256), 0, st, b);
-    } else if (g.prec == PSIM_FP32_3M && !g.trans_out && g.cfg > 0 && mode == ROWMAJOR) {
+    } else if (g.prec == PSIM_FP32_3M && !g.trans_out && g.cfg > 0 && !g.split && mode == ROWMAJOR) {
       const FCfg& c = kFp32_3mConfigs[g.cfg];
       b.MT = (b.M + c.bm - 1) / c.bm;
       b.NT = (b.Nr + c.bn - 1) / c.bn;
@@ -1632,7 +1668,16 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
       // interior tiles, an even number of K stages, 32-bit copy offsets:
       // the direct-to-LDS kernel (same products in the same order as the
       // ROWFAST 3M kernel, so the same results bit for bit)
-      if (g.split)
+      if (g.split && g.cfg == 3 && dtl3m_ok(g, mode, 64)) {
+        // split accumulation with 64 x 128 tiles: half the accumulators per
+        // wave, three workgroups per CU instead of two
+        KArgs f = b;
+        f.MT = f.M / 64;
+        f.T = f.MT * f.NT * Z;
+        const long long fb = (f.T + 7) / 8 * 8;
+        if (fb > 0x7fffffffLL) fail(PSIM_EUNSUPPORTED, "grid too large");
+        hipLaunchKernelGGL((site_gemm_3m_dtl_split<64, 128, 3>), dim3((unsigned)fb), dim3(256), 0, st, f);
+      } else if (g.split)
         hipLaunchKernelGGL((site_gemm_3m_dtl_split<128, 128>), dim3((unsigned)blocks), dim3(256), 0, st, b);
       else
         hipLaunchKernelGGL((site_gemm_3m_dtl<128, 128>), dim3((unsigned)blocks), dim3(256), 0, st, b);
@@ -1688,7 +1733,7 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
         launch<float, 256, 64, 16, ROWMAJOR, true>(b, bl, st);
       else
         launch<float, 256, 64, 16, KMAJOR, true>(b, bl, st);
-    } else if (!g.trans_out && fast(128, 32) && (2 * g.K1 * g.K2) % 64 == 0 && g.K2 < (1 << 20) &&
+    } else if (!g.trans_out && !g.nb && fast(128, 32) && (2 * g.K1 * g.K2) % 64 == 0 && g.K2 < (1 << 20) &&
                g.ldw < (1 << 22)) {
       // interior tiles, an even number of K stages: direct-to-LDS 4M kernel
       hipLaunchKernelGGL((site_gemm_4m_dtl<float, 128, 128, 2>), dim3((unsigned)blocks), dim3(256), 0, st, b);

@@ -186,9 +186,9 @@ psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o) {
   if (opts.max_batch <= 0) opts.max_batch = 1;
   if (opts.tile_cfg < 0 || opts.tile_cfg >= config_count(opts.prec))
     fail(PSIM_EINVAL, "tile_cfg " + std::to_string(opts.tile_cfg) + " is not a candidate of this precision");
-  // the split-accumulation kernels come in one tile configuration
-  if (opts.tile_cfg > 0 && (opts.flags & PSIM_PLAN_SPLIT_ACC))
-    fail(PSIM_EINVAL, "tile_cfg > 0 cannot be combined with PSIM_PLAN_SPLIT_ACC");
+  // the split-accumulation kernels come in one tile configuration (FP32 3M: two)
+  if ((opts.flags & PSIM_PLAN_SPLIT_ACC) && !split_candidate(opts.prec, opts.tile_cfg))
+    fail(PSIM_EINVAL, "tile_cfg " + std::to_string(opts.tile_cfg) + " has no split-accumulation form");
   int sweep = opts.sweep;
   if (sweep == 0) sweep = (P->lh <= P->lv) ? 1 : 2;
   if (sweep < 1 || sweep > 3) fail(PSIM_EINVAL, "sweep must be 0, 1, 2 or 3");
@@ -296,6 +296,9 @@ psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o) {
     const uint64_t eb = pl->elem_bytes;
     const uint64_t budget = opts.mem_budget_bytes;
     const uint64_t kParElems = 1ull << 31;
+    // rows whose per-v intermediate exceeds this many elements are cut over
+    // the first output leg w as well (intermediates of D^(L-1) per (v, w))
+    const uint64_t kWCutElems = 1ull << 29;
     auto al = [](uint64_t x) { return (x + 255) / 256 * 256; };
     int64_t nmax_all = 1;
     uint64_t tab = 0;
@@ -320,24 +323,59 @@ psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o) {
         lev.group = (int)std::min<int64_t>(lev.nmax, 1 << 16);
         continue;
       }
-      const uint64_t per = 2ull * lev.Gmax * eb;  // ping-pong, one (node, v)
-      const uint64_t par = std::max<uint64_t>(kParElems, lev.Gmax);
       const int64_t K2 = cs(i, L - 1).dl;
-      int c = 0;
-      for (int cand = lev.Dv; cand >= 1; --cand) {
-        if (lev.Dv % cand) continue;
-        // keep the last site's packed-matrix offset 16-byte aligned
-        if (cand != lev.Dv && ((int64_t)cand * K2) % 2) continue;
-        if ((uint64_t)cand * per <= gbud && (uint64_t)cand * lev.Gmax <= par) { c = cand; break; }
+      // keep the last site's packed-matrix offset 16-byte aligned
+      auto v_ok = [&](int cand) { return lev.Dv % cand == 0 && (cand == lev.Dv || ((int64_t)cand * K2) % 2 == 0); };
+      // per-(node, v, w) intermediates of a row cut over w as well (w = d of
+      // the first site, held fixed from its creation to the end of the row)
+      lev.Dw = cs(i, 0).dd;
+      lev.Gtask = 0;
+      for (int j = 0; j < L - 1; ++j) {
+        const Step& st = pl->steps[(size_t)i * L + j];
+        const int64_t t = j == 0 ? st.M * cs(i, 0).dr : st.M / lev.Dw * st.N;
+        lev.Gtask = std::max(lev.Gtask, t);
       }
+      const bool cut_w = lev.Dw > 1 && (lev.Gmax > kWCutElems || 2ull * lev.Gmax * eb > gbud);
+      if (!cut_w) {
+        const uint64_t per = 2ull * lev.Gmax * eb;  // ping-pong, one (node, v)
+        const uint64_t par = std::max<uint64_t>(kParElems, lev.Gmax);
+        int c = 0;
+        for (int cand = lev.Dv; cand >= 1; --cand)
+          if (v_ok(cand) && (uint64_t)cand * per <= gbud && (uint64_t)cand * lev.Gmax <= par) { c = cand; break; }
+        if (c == 0)
+          fail(PSIM_ENOMEM, "plan needs at least " + std::to_string(tab + Fmin[0] + Fmin[1] + per) + " bytes (row " +
+                                std::to_string(i) + "); budget is " + std::to_string(budget));
+        lev.vchunk = c;
+        lev.wchunk = lev.Dw;
+        uint64_t g = std::max<uint64_t>(1, par / ((uint64_t)c * lev.Gmax));
+        g = std::min<uint64_t>({g, (uint64_t)lev.nmax, gbud / ((uint64_t)c * per), 1u << 16});
+        lev.group = (int)std::max<uint64_t>(g, 1);
+        G = std::max(G, 2 * al((uint64_t)lev.group * c * lev.Gmax * eb));
+        continue;
+      }
+      // cut over w: (v, w) pairs per pass up to `target` elements per buffer,
+      // v chunk first (fewer accumulation passes of the last site), leaving
+      // room for at least two w values when possible
+      const uint64_t task = (uint64_t)lev.Gtask;
+      const uint64_t target = std::min<uint64_t>(std::max<uint64_t>(kWCutElems, task), gbud / (2 * eb));
+      int c = 0;
+      for (int cand = lev.Dv; cand >= 1 && !c; --cand)
+        if (v_ok(cand) && 2 * cand * task <= target) c = cand;
+      for (int cand = lev.Dv; cand >= 1 && !c; --cand)
+        if (v_ok(cand) && cand * task <= target) c = cand;
       if (c == 0)
-        fail(PSIM_ENOMEM, "plan needs at least " + std::to_string(tab + Fmin[0] + Fmin[1] + per) + " bytes (row " +
-                              std::to_string(i) + "); budget is " + std::to_string(budget));
+        fail(PSIM_ENOMEM, "plan needs at least " + std::to_string(tab + Fmin[0] + Fmin[1] + 2 * task * eb) +
+                              " bytes (row " + std::to_string(i) + ", cut over v and w); budget is " +
+                              std::to_string(budget));
+      int cw = 1;
+      for (int cand = lev.Dw - 1; cand >= 1; --cand)
+        if (lev.Dw % cand == 0 && (uint64_t)c * cand * task <= target) { cw = cand; break; }
       lev.vchunk = c;
-      uint64_t g = std::max<uint64_t>(1, par / ((uint64_t)c * lev.Gmax));
-      g = std::min<uint64_t>({g, (uint64_t)lev.nmax, gbud / ((uint64_t)c * per), 1u << 16});
+      lev.wchunk = cw;
+      uint64_t g = std::max<uint64_t>(1, target / ((uint64_t)c * cw * task));
+      g = std::min<uint64_t>({g, (uint64_t)lev.nmax, 1u << 16});
       lev.group = (int)std::max<uint64_t>(g, 1);
-      G = std::max(G, 2 * al((uint64_t)lev.group * c * lev.Gmax * eb));
+      G = std::max(G, 2 * al((uint64_t)lev.group * c * cw * task * eb));
     }
     // boundaries: what is left, split between even and odd levels
     if (tab + G + Fmin[0] + Fmin[1] > budget)
@@ -367,7 +405,8 @@ psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o) {
       const Level& lev = pl->levels[i];
       const int64_t groups = (lev.cap + lev.group - 1) / lev.group;
       const int64_t chunks = L == 1 ? 1 : (lev.Dv + lev.vchunk - 1) / lev.vchunk;
-      pl->max_ops += groups * chunks * L + 1;
+      const int64_t wchunks = w_cut(lev) ? lev.Dw / lev.wchunk : 1;
+      pl->max_ops += groups * chunks * wchunks * L + 1;
     }
     pl->ws_F = Fb[0] + Fb[1];
     pl->ws_G = G;
@@ -377,13 +416,17 @@ psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o) {
     // ---------------------------------------------------------- stored tile choices
     // psim_tune's earlier measurements (PSIM_TUNE_CACHE) for these interior
     // shapes on this device architecture; an explicit tile_cfg wins
-    if (!pl->host_only && opts.tile_cfg == 0 && !(opts.flags & PSIM_PLAN_SPLIT_ACC) && std::getenv("PSIM_TUNE_CACHE")) {
+    if (!pl->host_only && opts.tile_cfg == 0 && std::getenv("PSIM_TUNE_CACHE")) {
+      const bool split = (opts.flags & PSIM_PLAN_SPLIT_ACC) != 0;
       const std::string arch = device_arch(opts.device);
       for (Step& st : pl->steps) {
         if (st.kind != 1) continue;
         int cfg = 0;
-        if (tune_cache_lookup(tune_key(arch, opts.prec, st.M, st.K1, st.K2, st.N, pl->levels[st.i].vchunk), &cfg) &&
-            cfg >= 0 && cfg < config_count(opts.prec))
+        const Level& lv_ = pl->levels[st.i];
+        if (tune_cache_lookup(tune_key(arch, opts.prec, interior_rows(lv_, st), st.K1, st.K2, st.N, interior_batch(lv_),
+                                       split),
+                              &cfg) &&
+            cfg >= 0 && cfg < config_count(opts.prec) && (!split || split_candidate(opts.prec, cfg)))
           st.cfg = cfg;
       }
     }
@@ -407,6 +450,10 @@ psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o) {
           const int pack_prec =
               (opts.prec == PSIM_BF16X3 || (opts.prec == PSIM_FP32_3M && last)) ? PSIM_FP32_4M : opts.prec;
           pack_site_matrix(pack_prec, W.data(), (int64_t)c.du * c.dl, (int64_t)c.dd * c.dr, buf, dm.ld);
+          // a row cut over w reads the first site's matrix from an offset
+          // (the columns of one w chunk): 256 zero rows keep the last
+          // chunk's full tiles inside the allocation
+          if (j == 0) buf.resize(buf.size() + (size_t)256 * dm.ld * (opts.prec == PSIM_FP64 ? 8 : 4), 0);
           pl->weights_bytes += buf.size();
           if (!pl->host_only) {
             hip_check(hipSetDevice(opts.device), "hipSetDevice");

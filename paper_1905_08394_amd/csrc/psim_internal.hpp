@@ -72,6 +72,9 @@ struct Level {
   int64_t Gmax = 0;      // largest per-(node, v) intermediate of this row
   int Dv = 1;            // size of the leg v = u of the last site in this row
   int vchunk = 1;        // v values per pass
+  int Dw = 1;            // size of the leg w = d of the first site (the first output leg)
+  int wchunk = 1;        // w values per pass; wchunk < Dw: the row is cut over w as well as v
+  int64_t Gtask = 0;     // largest per-(node, v, w) intermediate when the row is cut over w
   int group = 1;         // nodes per pass
   int64_t nmax = 1;      // most nodes (distinct prefixes) this level can have
   int64_t cap = 1;       // nodes whose boundary fits the workspace at once
@@ -124,6 +127,15 @@ struct psim_plan_s {
   std::shared_ptr<psim::SquarePlan> sq;
   int64_t sq_steps = 0;
 };
+
+namespace psim {
+// Launch shape of an interior-site step (kind 1): rows per batch entry and
+// batch entries per node.  A row cut over w (wchunk < Dw) runs every (v, w)
+// pair as its own batch entry, with d_0 = w taken out of the rows.
+inline bool w_cut(const Level& lev) { return lev.wchunk < lev.Dw; }
+inline int64_t interior_rows(const Level& lev, const Step& s) { return w_cut(lev) ? s.M / lev.Dw : s.M; }
+inline int64_t interior_batch(const Level& lev) { return (int64_t)lev.vchunk * (w_cut(lev) ? lev.wchunk : 1); }
+}  // namespace psim
 
 // Plans run together (psim_group): the plans are borrowed; the group owns the
 // device array of launch descriptors (max_ops slots per plan).
@@ -180,6 +192,8 @@ struct GemmLaunch {
   const void* Wb0 = nullptr;          // BF16x3: pre-split bf16 planes of W (hi then lo)
   const void* Wb1 = nullptr;
   int64_t ldwb = 0, planeb = 0;
+  int64_t ldct = 0;                   // transposed stores: row stride of C^T in complex elements (0 = M)
+  int64_t nb = 0, sCw = 0;            // plain stores with nb > 0: C[n / nb][m][n % nb], blocks sCw apart
 };
 int fp32_config_count();
 int fp32_3m_config_count();
@@ -187,9 +201,13 @@ int fp64_config_count();
 int bf16x3_config_count();
 // tile candidates of a precision (1 = a single configuration)
 int config_count(int prec);
+// candidates that have a split-accumulation form (FP32 3M: 0 and the 64 x 128
+// direct-to-LDS tile; every other precision: 0)
+inline bool split_candidate(int prec, int cfg) { return cfg == 0 || (prec == PSIM_FP32_3M && cfg == 3); }
 // tune_cache.cpp: autotuner choices kept in the JSON file PSIM_TUNE_CACHE names
 std::string device_arch(int device);
-std::string tune_key(const std::string& arch, int prec, int64_t M, int64_t K1, int64_t K2, int64_t N, int64_t Bz);
+std::string tune_key(const std::string& arch, int prec, int64_t M, int64_t K1, int64_t K2, int64_t N, int64_t Bz,
+                     bool split = false);
 bool tune_cache_lookup(const std::string& key, int* cfg);
 void tune_cache_store(const std::map<std::string, std::pair<int, double>>& entries);
 void launch_site_gemm(const GemmLaunch& g, void* stream);

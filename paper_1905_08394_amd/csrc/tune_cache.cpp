@@ -65,9 +65,11 @@ std::string device_arch(int device) {
   return colon == std::string::npos ? name : name.substr(0, colon);
 }
 
-std::string tune_key(const std::string& arch, int prec, int64_t M, int64_t K1, int64_t K2, int64_t N, int64_t Bz) {
+std::string tune_key(const std::string& arch, int prec, int64_t M, int64_t K1, int64_t K2, int64_t N, int64_t Bz,
+                     bool split) {
   std::ostringstream k;
-  k << arch << "|" << prec_name(prec) << "|M=" << M << "|K1=" << K1 << "|K2=" << K2 << "|N=" << N << "|Bz=" << Bz;
+  k << arch << "|" << prec_name(prec) << (split ? "_split" : "") << "|M=" << M << "|K1=" << K1 << "|K2=" << K2
+    << "|N=" << N << "|Bz=" << Bz;
   return k.str();
 }
 

@@ -24,6 +24,15 @@ import numpy as np
 X_MIN = 0.1
 BAR = {"fp64": 1e-10, "fp32": 1e-5, "fp32s": 1e-5, "fp32_3m": 1e-5, "fp32_3ms": 1e-5, "bf16x3": 1e-3}
 
+# Measured against that bar on the 32 amplitudes of 6x6 (1+40+1): the FP32
+# forms WITHOUT split accumulation miss it (worst eps_rel 1.16e-5 for 4M,
+# 1.25e-5 for 3M, both at x >= 0.1; the sequential FP32 sums over K = 1024
+# and over the v values of a pass grow with the lattice), the split forms meet
+# it (3.4e-6 4M, 5.5e-6 3M), so the split 3M form is the default and the one
+# the 1e-5 target is claimed for.  The unsplit forms are held at 6x6 to the
+# regression bar below, which is not the target.
+BAR_C4_UNSPLIT = 2e-5
+
 
 def measures(a, r, n):
     """(eps_rel, eps_rms, eps_floor, x) of every amplitude."""
