@@ -126,12 +126,13 @@ def test_tile_cfg_validation(ps):
         with pytest.raises(ps.PsimError) as e:
             ps.Plan(P, prec=prec, host_only=True, tile_cfg=bad)
         assert e.value.status == ps.PSIM_EINVAL
-    # the split-accumulation kernels have one tile configuration
-    for prec, cfg in (("fp32", 2), ("fp32_3m", 1)):
+    # the split-accumulation kernels come in one tile configuration (FP32 3M: 0 and 3)
+    for prec, cfg in (("fp32", 2), ("fp32_3m", 1), ("fp32_3m", 2)):
         assert ps.Plan(P, prec=prec, host_only=True, split_acc=True).stats()["hot_cfg"] == 0
         with pytest.raises(ps.PsimError) as e:
             ps.Plan(P, prec=prec, host_only=True, tile_cfg=cfg, split_acc=True)
-        assert e.value.status == ps.PSIM_EINVAL and b"SPLIT_ACC" in ps.lib().psim_last_error()
+        assert e.value.status == ps.PSIM_EINVAL and b"split-accumulation" in ps.lib().psim_last_error()
+    assert ps.Plan(P, prec="fp32_3m", host_only=True, tile_cfg=3, split_acc=True).stats()["hot_cfg"] in (0, 3)
 
 
 def test_group_rejects_host_only_and_empty(ps):
