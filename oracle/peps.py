@@ -399,3 +399,48 @@ def row_amplitudes_sliced(peps: PEPS, base_bits: Sequence[int], variants: np.nda
             out[i] += complex(res.a)
     say("last row")
     return out
+
+
+def halves_amplitude_sliced(peps: PEPS, bits: Sequence[int], log=None) -> complex:
+    """One amplitude of an even L x L lattice by the square partition grouped
+    into left and right halves (the four blocks of eqs. S9-S10 paired the
+    other way): with e, a, b, c the bond groups ul|ur, ul|bl, ur|br, bl|br,
+        amp = sum_{e,c} Lft[e,c] Rgt[e,c],  Lft = ul . bl (over a),  Rgt = ur . br (over b),
+    cut over the first bond x of e and the last bond z of c, so each term
+    holds D^(L-1)-element slices:
+        amp = sum_{x,z} sum_{e',c'} (ul_x bl_z)[e',c'] (ur_x br_z)[e',c'].
+    The lower quadrants' slices are kept, the upper ones made once per x."""
+    L = peps.lv
+    m = L // 2
+    if peps.lh != L or L % 2:
+        raise ValueError("needs an even square lattice")
+    e_lab = [("h", r, m - 1) for r in range(m)]
+    a_lab = [("v", m - 1, c) for c in range(m)]
+    b_lab = [("v", m - 1, c) for c in range(m, L)]
+    c_lab = [("h", r, m - 1) for r in range(m, L)]
+    dims = bond_dims(peps)
+    de = int(np.prod([dims[x] for x in e_lab]))
+    da = int(np.prod([dims[x] for x in a_lab]))
+    db = int(np.prod([dims[x] for x in b_lab]))
+    dc = int(np.prod([dims[x] for x in c_lab]))
+    say = log or (lambda *_: None)
+    sites = projected_sites(peps, bits)
+    x_lab, z_lab = e_lab[0], c_lab[-1]
+    bl, br = [], []
+    for z in range(dims[z_lab]):
+        bl.append(contract_sites(sites, quadrant_sites(L, "bl"), fixed={z_lab: z})
+                  .ordered(a_lab + c_lab[:-1]).reshape(da, dc // dims[z_lab]))
+        br.append(contract_sites(sites, quadrant_sites(L, "br"), fixed={z_lab: z})
+                  .ordered(b_lab + c_lab[:-1]).reshape(db, dc // dims[z_lab]))
+    say("lower quadrant slices")
+    amp = 0j
+    for x in range(dims[x_lab]):
+        ul = contract_sites(sites, quadrant_sites(L, "ul"), fixed={x_lab: x}) \
+            .ordered(e_lab[1:] + a_lab).reshape(de // dims[x_lab], da)
+        ur = contract_sites(sites, quadrant_sites(L, "ur"), fixed={x_lab: x}) \
+            .ordered(e_lab[1:] + b_lab).reshape(de // dims[x_lab], db)
+        for z in range(dims[z_lab]):
+            amp += np.sum((ul @ bl[z]) * (ur @ br[z]))
+        del ul, ur
+        say(f"x {x + 1}/{dims[x_lab]}")
+    return complex(amp)

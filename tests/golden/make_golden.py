@@ -6,7 +6,8 @@ the seeded generator `rqcgen`; nothing is read from the GPU library.
   python tests/golden/make_golden.py            # 3x3, 4x5, 5x5 (minutes)
   python tests/golden/make_golden.py --big      # also 6x6 d40 (about an hour, ~34 GiB RAM)
   python tests/golden/make_golden.py --only-big --base 1   # 6x6 d40, second base bitstring
-  python tests/golden/make_golden.py --rows6    # 6x6 d40 base 0 again, by the row scheme (hours)
+  python tests/golden/make_golden.py --rows6    # 6x6 d40 base 0 again, by the row scheme (about 11 h here)
+  python tests/golden/make_golden.py --halves6  # 6x6 d40 base amplitude by the left/right halves (about 1 h)
 
 Files: rqc_<lv>x<lh>_d<d>_s<seed>.json with the circuit hash, the bitstrings
 and the FP64 amplitudes.
@@ -101,6 +102,20 @@ def rows6():
            {"variant_cols": [2, 3, 4, 5], "seconds": time.time() - t})
 
 
+def halves6():
+    """The base amplitude of the base-0 6x6 (1+40+1) batch again, by the
+    square partition grouped into left and right halves (a contraction order
+    and cut loops other than those that wrote rqc_6x6_d40_s0.json; about an
+    hour on 8 cores, ~34 GiB RAM)."""
+    c = rqcgen.generate(6, 6, 40, 0)
+    base = rqcgen.bitstrings(6, 6, 0, 1)[0]
+    t = time.time()
+    P = peps.build(c)
+    amp = peps.halves_amplitude_sliced(P, base, log=lambda s: print(f"[{time.time() - t:7.0f}s] {s}", flush=True))
+    _write("rqc_6x6_d40_s0_halves.json", c, base[None, :], np.array([amp]), "peps-square-partition-halves-sliced",
+           {"seconds": time.time() - t})
+
+
 def fig2():
     """8x8 (1+25+1), the lattice of the paper's Porter-Thomas figure: eight
     amplitudes by the oracle's row scheme (largest tensor 8^8 x 16 elements)."""
@@ -125,9 +140,12 @@ if __name__ == "__main__":
     ap.add_argument("--only-big", action="store_true")
     ap.add_argument("--fig2", action="store_true", help="8x8 (1+25+1) amplitudes")
     ap.add_argument("--rows6", action="store_true", help="6x6 d40 base-0 batch by the sliced row scheme")
+    ap.add_argument("--halves6", action="store_true", help="6x6 d40 base amplitude by the left/right halves")
     ap.add_argument("--base", type=int, default=0, help="--big: index of the base bitstring in the stream")
     a = ap.parse_args()
-    if a.rows6:
+    if a.halves6:
+        halves6()
+    elif a.rows6:
         rows6()
     elif a.fig2:
         fig2()

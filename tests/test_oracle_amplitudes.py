@@ -189,3 +189,34 @@ def test_row_scheme_with_cut_loops(lv, lh, d, seed):
     bad[0, 0] ^= 1                                      # differs from the base in row 0
     with pytest.raises(ValueError):
         peps.row_amplitudes_sliced(P, base, bad)
+
+
+@pytest.mark.parametrize("L,d,seed", [(4, 16, 0), (4, 24, 1), (2, 8, 2)])
+def test_square_partition_left_right_halves(L, d, seed):
+    """The square partition grouped into left and right halves with cut loops
+    over one bond between the upper and one between the lower quadrants (the
+    second order of the 6x6 (1+40+1) golden) equals the state vector."""
+    c = rqcgen.generate(L, L, d, seed)
+    P = peps.build(c)
+    bits = rqcgen.bitstrings(L, L, seed, 4)
+    got = np.array([peps.halves_amplitude_sliced(P, b) for b in bits])
+    ref = sv.amplitudes(sv.run(c), bits)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_6x6_golden_two_orders(golden_dir):
+    """The base amplitude of the 6x6 (1+40+1) golden batch from two
+    contraction orders of the oracle: the square partition paired top and
+    bottom with cut loops over the top e-bond and the last c-bond (eqs.
+    S9-S10, rqc_6x6_d40_s0.json) and paired left and right
+    (rqc_6x6_d40_s0_halves.json) agree to 1e-12 relative."""
+    with open(os.path.join(golden_dir, "rqc_6x6_d40_s0.json")) as f:
+        a = json.load(f)
+    with open(os.path.join(golden_dir, "rqc_6x6_d40_s0_halves.json")) as f:
+        b = json.load(f)
+    assert a["sha256"] == b["sha256"] == rqcgen.generate(6, 6, 40, 0).sha256()
+    i = a["base_index"]
+    assert a["bits"][i] == b["bits"][0] == rqcgen.bitstrings(6, 6, 0, 1)[0].tolist()
+    x = complex(a["amps_re"][i], a["amps_im"][i])
+    y = complex(b["amps_re"][0], b["amps_im"][0])
+    assert abs(x - y) <= 1e-12 * abs(x)
