@@ -20,8 +20,8 @@ amplitude, square partition, plain FP64 GPU, CPU oracle), each of which runs
 one untimed-warmup-free step.  `steps` and `warmup` in the JSON line are the
 steps that actually ran; every timed step is the full 16-bitstring batch.
 
-The default path is the FP32-MFMA 3M scheme with per-stage partial sums in
-the K loops (split accumulation): the FP32 form that meets the 1e-5 relative
+The default path is the FP32-MFMA 3M scheme with partial sums in the K loops
+(split accumulation): the FP32 form that meets the 1e-5 relative
 bar on every oracle amplitude of this workload (without split accumulation
 the worst is 1.25e-5).  The FP64 path is timed on the same batch for the
 comparison the metric names.  --no-split-acc runs the FP32 forms with plain
@@ -303,7 +303,7 @@ def plain_fp64_gpu_baseline(stats, batch_cmac, nbits, reps=3):
                       f"exact multiply-add counts to the {nbits}-bitstring batch ({batch_cmac:.3e} CMAC)"}
 
 
-def counters_program(prec="fp32_3m", reps=3):
+def counters_program(prec="fp32_3m", reps=3, split_acc=False, tile_cfg=0):
     """Short program for rocprofv3 --pmc passes: a plain 4 GiB device copy (to
     calibrate FETCH_SIZE / WRITE_SIZE) and the interior-site contraction at the
     launch shape the 6x6 (1+40+1) bench runs (two v values of M = 32^4,
@@ -322,7 +322,7 @@ def counters_program(prec="fp32_3m", reps=3):
     rng = np.random.default_rng(0)
     W = rng.standard_normal((K1 * K2, N)) + 1j * rng.standard_normal((K1 * K2, N))
     for r in range(reps):
-        ps.contract_site(prec, A, W, M, K1, K2, N, batch=batch)
+        ps.contract_site(prec, A, W, M, K1, K2, N, batch=batch, split_acc=split_acc, tile_cfg=tile_cfg)
         log(f"hot step {r + 1}/{reps}")
     torch.cuda.synchronize()
     print(json.dumps({"prec": prec, "copy_bytes": 4 * n, "hot_step_algorithmic_bytes":
@@ -337,9 +337,10 @@ def seven_program(args):
     of them (input and output of a row) do not fit one GPU's 288 GB; nothing
     of the amplitude itself runs.  Timed: the interior-site contraction at the
     shape of a 7x7 row's (v, w) task -- the last input leg v and the first
-    output leg w fixed: M = 32^4 rows, K = N = 1024, two tasks per launch --
-    which is the shape of the 6x6 hot launch, with synthetic operands (the
-    kernel's speed does not depend on the values)."""
+    output leg w fixed: M = 32^4 rows, K = N = 1024, one task per launch, as
+    the planner cuts a 7x7 row -- in the kernels the default precision runs
+    (split accumulation, --tile-cfg), with synthetic operands (the kernel's
+    speed does not depend on the values)."""
     import numpy as np
     import torch
     import paper_1905_08394_amd as ps
@@ -361,24 +362,25 @@ def seven_program(args):
     total = first + (L - 2) * inner + last
     assert abs(total / st["cmac_per_amplitude"] - 1) < 1e-12, (total, st["cmac_per_amplitude"])
     hot_cmac = (L - 2) * (L - 2) * D ** (L + 3)          # interior sites of interior rows (eq. S4)
-    M, K1, K2, N, batch = D ** (L - 3), D, D, D * D, 2
+    M, K1, K2, N, batch = D ** (L - 3), D, D, D * D, 1    # the plan cuts each 7x7 row into single (v, w) pairs
+    split = args.split_acc and args.prec in ("fp32", "fp32_3m")
     A = torch.randn(batch * K1 * M * K2, dtype=torch.complex64, device="cuda")
     rng = np.random.default_rng(0)
     W = rng.standard_normal((K1 * K2, N)) + 1j * rng.standard_normal((K1 * K2, N))
-    ps.contract_site(args.prec, A, W, M, K1, K2, N, batch=batch)        # warm
+    ps.contract_site(args.prec, A, W, M, K1, K2, N, batch=batch, split_acc=split, tile_cfg=args.tile_cfg)  # warm
     torch.cuda.synchronize()
     reps = 5
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     ev[0].record()
     for _ in range(reps):
-        ps.contract_site(args.prec, A, W, M, K1, K2, N, batch=batch)
+        ps.contract_site(args.prec, A, W, M, K1, K2, N, batch=batch, split_acc=split, tile_cfg=args.tile_cfg)
     ev[1].record()
     torch.cuda.synchronize()
     ms = ev[0].elapsed_time(ev[1]) / reps        # includes the per-call upload of W (8 MiB)
     rate = batch * M * K1 * K2 * N / (ms / 1e3)  # complex multiply-adds per second
     issued = ISSUED_PER_CMAC[args.prec]
     out = {"workload": "7x7 lattice, random circuit depth (1+40+1), D=32, one amplitude (row scheme)",
-           "prec": args.prec, "peps_build_s": t_build, "cmac_per_amplitude": st["cmac_per_amplitude"],
+           "prec": args.prec, "split_accumulation": bool(split), "tile_cfg": args.tile_cfg, "peps_build_s": t_build, "cmac_per_amplitude": st["cmac_per_amplitude"],
            "cmac_per_row": {"first": first, "interior": inner, "last": last}, "hot_cmac_share": hot_cmac / total,
            "boundary_bytes": int(D ** L * 8), "one_gpu_row_sweep_workspace_bytes": st["workspace_bytes"],
            "hot_launch": {"shape": f"{batch} x (M = {M}, K = N = {K1 * K2})", "ms": ms,
@@ -753,6 +755,7 @@ def main():
     ap.add_argument("--square-only", action="store_true",
                     help="only the square partition on the 6x6 batch (for profiling)")
     ap.add_argument("--counters", action="store_true", help="short program for rocprofv3 --pmc passes")
+    ap.add_argument("--tile-cfg", type=int, default=0, help="--counters / --lattice 7: tile candidate of the launch")
     ap.add_argument("--fig2", action="store_true", help="8x8 (1+25+1) Porter-Thomas experiment")
     ap.add_argument("--fig2-count", type=int, default=2048)
     ap.add_argument("--sweep", type=int, default=0, help="--fig2: 0 row scheme, 3 square partition")
@@ -784,7 +787,8 @@ def main():
         seven_program(args)
         return
     if args.counters:
-        counters_program(args.prec)
+        counters_program(args.prec, split_acc=args.split_acc and args.prec in ("fp32", "fp32_3m"),
+                         tile_cfg=args.tile_cfg)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -869,7 +873,7 @@ def main():
                                f"sharing rows 1-{args.lattice - 1} (last-row variants)",
                    "precision": {"fp32": "complex64 storage, FP32 MFMA (4M)",
                                  "fp32_3m": "complex64 storage, FP32 MFMA (3M, Gauss)" +
-                                            (", per-stage partial sums" if split_on else ""),
+                                            (", split K accumulation (partial sums)" if split_on else ""),
                                  "fp64": "complex128 storage, FP64 MFMA",
                                  "bf16x3": "complex64 storage, BF16 hi/lo split, 3 BF16 MFMA products, "
                                            "FP32 accumulation"}[args.prec],

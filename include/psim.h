@@ -71,7 +71,8 @@ typedef enum {
 typedef enum {
   PSIM_PLAN_HOST_ONLY = 1,  /* plan the contraction on the host only (no device, cannot run) */
   PSIM_PLAN_SPLIT_ACC = 2,  /* FP32 4M and FP32 3M, every site kernel and square-partition join, in
-                               both schemes: accumulate each K stage separately before adding it to
+                               both schemes: accumulate each K stage (32 reals of k; each pair of
+                               stages in the direct-to-LDS 3M kernel) separately before adding it to
                                the running sum (smaller rounding error, same work, slower: twice the
                                accumulator registers; joins are not grouped) */
   PSIM_PLAN_GRAPH = 4       /* psim_amplitudes captures its row sweep into a HIP graph the first time
@@ -93,7 +94,7 @@ typedef struct {
                                  together; otherwise bitstrings go one by one (same results) */
   int32_t device;             /* HIP device ordinal */
   int32_t tile_cfg;           /* interior-site tile candidate: 0 = default, k > 0 = candidate k
-                                 (FP32 4M: 1..6, FP32 3M: 1..3, FP64: 1..2, BF16X3: 1; with
+                                 (FP32 4M: 1..6, FP32 3M: 1..3, FP64: 1..2, BF16X3: 1..2; with
                                  PSIM_PLAN_SPLIT_ACC only 0, or 3 for FP32 3M (the split kernels'
                                  tiles): EINVAL otherwise).  With 0 and PSIM_TUNE_CACHE set in the environment, the
                                  choices psim_tune stored there for this device architecture,
@@ -228,8 +229,8 @@ void psim_plan_free(psim_plan_t *plan);
  * the batch is contracted a second time in a companion form with different
  * rounding, and out_rel_err[b] = |a_b - c_b| / |c_b| (c = companion result;
  * out_amp still holds the plan's own result a):
- *   FP32 4M / 3M plans: the other K-loop accumulation (per-stage partial sums
- *     on or off, PSIM_PLAN_SPLIT_ACC), same packed site matrices.  The
+ *   FP32 4M / 3M plans: the other K-loop accumulation (partial sums per K
+ *     stage on or off, PSIM_PLAN_SPLIT_ACC), same packed site matrices.  The
  *     difference is dominated by the less accurate of the two (the unsplit
  *     form, whose error is 2-3x larger), so it tracks the error of unsplit
  *     plans and overstates that of split plans.  It sees only the K-loop
@@ -264,6 +265,10 @@ psim_status psim_amplitudes(psim_plan_t *plan, const uint8_t *bits, size_t n_bit
 psim_status psim_amplitudes_static(psim_plan_t *plan, const uint8_t *bits, size_t n_bitstrings, void *hip_stream,
                                    double *out_amp, double *out_rel_err);
 
+/* Optional bits of psim_contract_site's prec argument. */
+#define PSIM_CONTRACT_SPLIT_ACC 0x100 /* the split-accumulation kernels (FP32 4M / 3M) */
+#define PSIM_CONTRACT_TILE_SHIFT 16   /* prec | (k << 16): tile candidate k (psim_plan_opts.tile_cfg) */
+
 /* One site contraction of the row scheme, eq. (S4), on device buffers:
  *   C[z][m][n] = sum_{k1,k2} A[z][k1][m][k2] * W[k1*K2 + k2][n]     (complex)
  * A: device, complex (complex128 for PSIM_FP64, complex64 otherwise), batch
@@ -271,8 +276,12 @@ psim_status psim_amplitudes_static(psim_plan_t *plan, const uint8_t *bits, size_
  * W: host, K1*K2 x N complex128, row-major (packed and uploaded per call).
  * C: device, same element type as A, batch stride M*N; transpose_out = 1
  *    stores C[z][n][m] instead.  batch = number of z.
+ * prec: a psim_precision, optionally OR'ed with PSIM_CONTRACT_SPLIT_ACC and
+ * (k << PSIM_CONTRACT_TILE_SHIFT) to pick the kernels a plan with
+ * PSIM_PLAN_SPLIT_ACC or tile_cfg = k would run (plain stores only).
  * Runs the same kernels the amplitude path uses; allocates its own scratch.
- * Errors: EINVAL for non-positive sizes or NULL, EUNSUPPORTED, EDEVICE. */
+ * Errors: EINVAL for non-positive sizes, NULL, or a tile / split choice the
+ * precision lacks; EUNSUPPORTED, EDEVICE. */
 psim_status psim_contract_site(int32_t prec, int64_t batch, int64_t M, int64_t K1, int64_t K2, int64_t N,
                                const void *d_A, int64_t a_batch_stride, const double *W,
                                void *d_C, int32_t transpose_out, void *hip_stream);
@@ -299,8 +308,9 @@ psim_status psim_tune(psim_plan_t *plan, void *d_workspace, size_t workspace_byt
 /* Per-kernel-class timing of psim_amplitudes, measured with HIP events
  * recorded on the caller's stream around every launch (adds two event
  * records per launch while enabled).  Classes: 0 = first site of a row
- * (K-major A), 1 = interior sites (eq. S4, the hot step), 2 = last site of a
- * row (v summed, transposed store), 3 = per-row rescale.  op = 1 resets and
+ * (K-major A) and the other sites of the first and last rows (their small M
+ * or N), 1 = interior sites of the interior rows (eq. S4, the hot step),
+ * 2 = last site of a row (v summed, transposed store), 3 = per-row rescale.  op = 1 resets and
  * enables, op = 2 reads the accumulated totals into out[4] (nullable for
  * op 1/0), op = 0 disables.  cmac is the algorithmic complex multiply-add
  * count of the timed launches, bytes their algorithmic memory traffic (for

@@ -28,6 +28,9 @@ EXPORTED = ("psim_build", "psim_peps_info", "psim_peps_free", "psim_plan", "psim
             "psim_group_amplitudes", "psim_group_free", "psim_apply", "psim_project", "psim_double_layer",
             "psim_sample_workspace", "psim_sample", "psim_amplitudes_static",
             "psim_last_error", "psim_version")
+# psim_profile classes (row scheme): 0 first site of a row and the other sites
+# of the first and last rows, 1 eq. S4 (interior sites of interior rows),
+# 2 last site of a row, 3 rescale
 KERNEL_CLASSES = ("first_site", "interior_site", "last_site", "rescale")
 
 
@@ -402,7 +405,8 @@ class Group:
 
 
 def contract_site(prec: str, A, W: np.ndarray, M: int, K1: int, K2: int, N: int, batch: int = 1,
-                  a_batch_stride: Optional[int] = None, transpose_out: bool = False, stream=None):
+                  a_batch_stride: Optional[int] = None, transpose_out: bool = False, stream=None,
+                  split_acc: bool = False, tile_cfg: int = 0):
     """One site contraction (eq. S4) through the library kernels.
 
     A: torch complex tensor on the GPU with batch * K1 * M * K2 elements laid out
@@ -414,7 +418,8 @@ def contract_site(prec: str, A, W: np.ndarray, M: int, K1: int, K2: int, N: int,
     Wd = np.ascontiguousarray(np.asarray(W, dtype=np.complex128)).view(np.float64)
     C = torch.empty(batch * M * N, dtype=dt, device=A.device)
     st = stream if stream is not None else torch.cuda.current_stream(A.device).cuda_stream
-    _check(lib().psim_contract_site(PREC[prec], batch, M, K1, K2, N, ctypes.c_void_p(A.data_ptr()),
+    code = PREC[prec] | (0x100 if split_acc else 0) | (tile_cfg << 16)
+    _check(lib().psim_contract_site(code, batch, M, K1, K2, N, ctypes.c_void_p(A.data_ptr()),
                                     a_batch_stride if a_batch_stride is not None else K1 * M * K2,
                                     Wd.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                     ctypes.c_void_p(C.data_ptr()), 1 if transpose_out else 0, ctypes.c_void_p(st)))

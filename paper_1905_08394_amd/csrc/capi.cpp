@@ -182,8 +182,14 @@ psim_status psim_contract_site(int32_t prec, int64_t batch, int64_t M, int64_t K
                                const void* dA, int64_t a_batch_stride, const double* W, void* dC,
                                int32_t transpose_out, void* stream) {
   return guarded([&] {
+    // optional bits above the precision: split accumulation and a tile candidate
+    const int split = (prec & PSIM_CONTRACT_SPLIT_ACC) ? 1 : 0;
+    const int cfg = (prec >> PSIM_CONTRACT_TILE_SHIFT) & 0xff;
+    prec &= 0xff;
     if (prec != PSIM_FP64 && prec != PSIM_FP32_4M && prec != PSIM_FP32_3M && prec != PSIM_BF16X3)
       fail(PSIM_EUNSUPPORTED, "precision not available");
+    if (cfg >= config_count(prec) || (split && (prec == PSIM_FP64 || prec == PSIM_BF16X3 || !split_candidate(prec, cfg))))
+      fail(PSIM_EINVAL, "tile candidate or split accumulation not available for this precision");
     if (batch < 1 || M < 1 || K1 < 1 || K2 < 1 || N < 1) fail(PSIM_EINVAL, "non-positive size");
     if (!dA || !W || !dC) fail(PSIM_EINVAL, "NULL buffer");
     const int eb = prec == PSIM_FP64 ? 16 : 8;
@@ -224,6 +230,8 @@ psim_status psim_contract_site(int32_t prec, int64_t batch, int64_t M, int64_t K
       g.sA_node = a_batch_stride;
       g.sC_node = M * N;
       g.trans_out = transpose_out ? 1 : 0;
+      g.split = split;
+      g.cfg = transpose_out ? 0 : cfg;
       launch_site_gemm(g, st);
       hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
     } catch (...) {

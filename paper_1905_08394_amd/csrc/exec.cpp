@@ -441,7 +441,9 @@ void prepare(psim_plan_t* pl, const uint8_t* bits, const std::vector<size_t>& id
               g.sC_v = Mt * s.N;
               g.sC_node = (int64_t)c * cw * g.sC_v;
             }
-            op.cls = s.kind;
+            // class 1 is eq. S4 proper: interior sites of interior rows; the
+            // first and last rows' interior sites (small M or N) join class 0
+            op.cls = (s.kind == 1 && (i == 0 || i == R - 1)) ? 0 : s.kind;
             op.cmac = (double)g.nodes * g.Bz * g.M * g.K1 * g.K2 * g.N;
             op.bytes = (double)eb * ((double)g.nodes * g.Bz * g.K1 * g.M * g.K2 +
                                      (double)g.nodes * g.Bz * g.M * g.N * (g.beta ? 2 : 1) +

@@ -665,15 +665,16 @@ __device__ __forceinline__ void dtl3m_body(const KArgs& p, const long long t) {
       for (int q = 0; q < 3; ++q)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc3[bi][bj][q][r] = 0;
-  // SPLIT: each stage's products are summed on their own (fresh partial
-  // accumulators) and then added to the running sums, which shortens the
+  // SPLIT: the products of each pair of stages (64 reals of k) are summed on
+  // their own (fresh partial accumulators, opened by the pair's first stage)
+  // and then added to the running sums (by its second), which shortens the
   // FP32 rounding chains of the K loop
   f32x16 part[SPLIT ? MBLK : 1][SPLIT ? NBLK3 : 1][SPLIT ? 3 : 1];
 
   const int frow = lane % MB;
   const int fh = (lane / MB) * 2;  // first logical chunk of this lane half within a group of 4
-  auto compute = [&](const float* a_s, const float* b_s) {
-    if constexpr (SPLIT) {
+  auto compute = [&](const float* a_s, const float* b_s, const bool open, const bool close) {
+    if (SPLIT && open) {
 #pragma unroll
       for (int bi = 0; bi < MBLK; ++bi)
 #pragma unroll
@@ -721,7 +722,7 @@ __device__ __forceinline__ void dtl3m_body(const KArgs& p, const long long t) {
             dst[bi][bj][2] = __builtin_amdgcn_mfma_f32_32x32x2f32(as[bi][s], bs[bj][s], dst[bi][bj][2], 0, 0, 0);
           }
     }
-    if constexpr (SPLIT) {
+    if (SPLIT && close) {
 #pragma unroll
       for (int bi = 0; bi < MBLK; ++bi)
 #pragma unroll
@@ -740,11 +741,11 @@ __device__ __forceinline__ void dtl3m_body(const KArgs& p, const long long t) {
   __syncthreads();
   for (int kp = 0; kp < npair; ++kp) {
     issue(sA1, sB1);
-    compute(sA0, sB0);
+    compute(sA0, sB0, true, false);
     __builtin_amdgcn_s_waitcnt(kWaitVm0);
     __syncthreads();
     if (kp + 1 < npair) issue(sA0, sB0);
-    compute(sA1, sB1);
+    compute(sA1, sB1, false, true);
     __builtin_amdgcn_s_waitcnt(kWaitVm0);
     __syncthreads();
   }
@@ -1119,6 +1120,175 @@ __global__ __launch_bounds__(256) void site_gemm_bf16x3(KArgs p) {
       }
 }
 
+// Direct-to-LDS form of the BF16x3 kernel for interior launches (every tile
+// interior, every 32-real stage inside one k1 block, an even number of
+// stages).  A is copied global -> LDS in FP32 by the load unit and split into
+// hi / lo as its fragments are read; W's two pre-split planes are copied side
+// by side into one 128-byte LDS row per output column (hi k 0..31, then lo
+// k 0..31).  Both tiles are unpadded 128-byte rows with the chunk swizzle of
+// the 3M direct-to-LDS kernel.  512 threads: 8 waves as 4 (m) x 2 (n) blocks
+// of 64 x 128 outputs, 128 accumulator registers each, so two waves share a
+// SIMD.  The split, the products and their order for each output element are
+// those of site_gemm_bf16x3, so the two agree bit for bit.
+// x = hi + lo for 8 floats (x0 then x1) with hi = bf16(x) and lo =
+// bf16(x - hi), both rounded to nearest even, as the operand registers of a
+// 32x32x16 MFMA hold them.  Each pair is rounded in one packed conversion and
+// its hi values are widened back to FP32 by a shift and a mask of the packed
+// word (bf16 is the upper half of an FP32), so x - hi is exact as in the
+// scalar form.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void split_bf16x8(const f32x4 x0, const f32x4 x1, bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const f32x4& x = q < 2 ? x0 : x1;
+    const int e = 2 * (q & 1);
+    const bf16x2 h = __builtin_convertvector(f32x2{x[e], x[e + 1]}, bf16x2);
+    const unsigned u = __builtin_bit_cast(unsigned, h);
+    const float f0 = __builtin_bit_cast(float, u << 16), f1 = __builtin_bit_cast(float, u & 0xffff0000u);
+    const bf16x2 l = __builtin_convertvector(f32x2{x[e] - f0, x[e + 1] - f1}, bf16x2);
+    hi[2 * q] = h[0];
+    hi[2 * q + 1] = h[1];
+    lo[2 * q] = l[0];
+    lo[2 * q + 1] = l[1];
+  }
+}
+
+template <int BM, int BN>
+__global__ __launch_bounds__(512) void site_gemm_bf16x3_dtl(KArgs p) {
+  constexpr int BK = 32;                 // reals per stage: two MFMA k-steps
+  constexpr int NW = 8;                  // waves per workgroup
+  constexpr int WM = BM / 4, WN = BN / 2;
+  constexpr int MBLK = WM / 32, NBLK = WN / 32;
+  constexpr int A_INS = BM * 128 / 1024 / NW;  // wave-wide 1 KiB copies per wave and stage
+  constexpr int B_INS = BN * 128 / 1024 / NW;
+  static_assert(A_INS >= 1 && B_INS >= 1 && A_INS * NW * 1024 == BM * 128 && B_INS * NW * 1024 == BN * 128,
+                "tile");
+  __shared__ __attribute__((aligned(1024))) float sA0[BM * BK];
+  __shared__ __attribute__((aligned(1024))) float sA1[BM * BK];
+  __shared__ __attribute__((aligned(1024))) __bf16 sB0[BN * 2 * BK];
+  __shared__ __attribute__((aligned(1024))) __bf16 sB1[BN * 2 * BK];
+
+  const long long t = xcd_tile(p.T);
+  if (t >= p.T) return;
+  const long long nt = t % p.NT;
+  const long long rest = t / p.NT;
+  const long long mt = rest % p.MT;
+  const long long z = rest / p.MT;
+  const long long node = z / p.Bz, vb = z % p.Bz;
+  const long long ablk = p.a_index ? (long long)p.a_index[node] : node;
+  const float* __restrict__ A = (const float*)p.A + 2 * (ablk * p.sA_node + vb * p.sA_v);
+  const int tauv = p.tau ? (int)p.tau[node * p.tau_stride] : 0;
+  const __bf16* __restrict__ Wh = (const __bf16*)(tauv ? p.W1 : p.W0) + p.w_koff_r;
+  const __bf16* __restrict__ Wl = Wh + p.plane;
+  float* __restrict__ C = (float*)p.C + 2 * (node * p.sC_node + vb * p.sC_v);
+  const long long m0 = mt * BM, n0 = nt * BN;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  const long long sK1 = p.M * p.K2;
+
+  // Copy `it` of this wave fills tile rows (it * NW + wid) * 8 + lane / 8,
+  // physical chunk lane % 8, from logical chunk (lane % 8) ^ swz(row); for W
+  // logical chunks 0-3 are the hi plane's k 0..31 and 4-7 the lo plane's.
+  // Byte offsets from the uniform stage bases stay below 2^31.
+  const unsigned a_rs = (unsigned)(2 * p.K2 * 4);  // bytes between rows of A
+  const unsigned b_rs = (unsigned)(p.ldw * 2);     // bytes between rows of a W plane
+  long long fk1 = 0, fk2 = 0, kr = 0;              // next stage: (k1, k2) of A, real k of W
+  auto issue = [&](float* sa, __bf16* sb) {
+    const char* abase = (const char*)(A + 2 * (fk1 * sK1 + m0 * p.K2 + fk2));
+    const char* hbase = (const char*)(Wh + n0 * p.ldw + kr);
+    const char* lbase = (const char*)(Wl + n0 * p.ldw + kr);
+#pragma unroll
+    for (int it = 0; it < A_INS; ++it) {
+      const int row = (it * NW + wid) * 8 + (lane >> 3);
+      const int chk = (lane & 7) ^ dtl_swz(row);
+      __builtin_amdgcn_global_load_lds((const void*)(abase + (unsigned)row * a_rs + (unsigned)chk * 16u),
+                                       PSIM_LDS(sa + (it * NW + wid) * 256), 16, 0, 0);
+    }
+#pragma unroll
+    for (int it = 0; it < B_INS; ++it) {
+      const int row = (it * NW + wid) * 8 + (lane >> 3);
+      const int chk = (lane & 7) ^ dtl_swz(row);
+      const char* src = ((chk & 4) ? lbase : hbase) + (unsigned)row * b_rs + (unsigned)(chk & 3) * 16u;
+      __builtin_amdgcn_global_load_lds((const void*)src, PSIM_LDS(sb + (it * NW + wid) * 512), 16, 0, 0);
+    }
+    fk2 += BK / 2;
+    if (fk2 == p.K2) {
+      fk2 = 0;
+      ++fk1;
+    }
+    kr += BK;
+  };
+
+  f32x16 acc[MBLK][NBLK];
+#pragma unroll
+  for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < NBLK; ++bj)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[bi][bj][r] = 0;
+
+  const int frow = lane & 31, h = lane >> 5;  // lane half h supplies k 8h .. 8h+7 of a k-step
+  auto compute = [&](const float* a_s, const __bf16* b_s) {
+#pragma unroll
+    for (int j = 0; j < BK / 16; ++j) {
+      bf16x8 ah[MBLK], al[MBLK], bh[NBLK], bl[NBLK];
+#pragma unroll
+      for (int bi = 0; bi < MBLK; ++bi) {
+        const int r = wr * WM + bi * 32 + frow;
+        const int c0 = 4 * j + 2 * h, sw = dtl_swz(r);
+        const f32x4 x0 = *(const f32x4*)(a_s + r * BK + ((c0 ^ sw) << 2));
+        const f32x4 x1 = *(const f32x4*)(a_s + r * BK + (((c0 + 1) ^ sw) << 2));
+        split_bf16x8(x0, x1, ah[bi], al[bi]);
+      }
+#pragma unroll
+      for (int bj = 0; bj < NBLK; ++bj) {
+        const int r = wc * WN + bj * 32 + frow;
+        const int sw = dtl_swz(r);
+        bh[bj] = *(const bf16x8*)(b_s + r * 2 * BK + (((2 * j + h) ^ sw) << 3));
+        bl[bj] = *(const bf16x8*)(b_s + r * 2 * BK + (((4 + 2 * j + h) ^ sw) << 3));
+      }
+#pragma unroll
+      for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < NBLK; ++bj) {
+          acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[bi], bh[bj], acc[bi][bj], 0, 0, 0);
+          acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bl[bj], acc[bi][bj], 0, 0, 0);
+          acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bh[bj], acc[bi][bj], 0, 0, 0);
+        }
+    }
+  };
+  constexpr unsigned kWaitVm0 = 0x3f70;  // vmcnt(0): this wave's copies into LDS have landed
+
+  // the launcher guarantees an even number of stages
+  const int npair = (int)(p.Kr / (2 * BK));
+  issue(sA0, sB0);
+  __builtin_amdgcn_s_waitcnt(kWaitVm0);
+  __syncthreads();
+  for (int kp = 0; kp < npair; ++kp) {
+    issue(sA1, sB1);
+    compute(sA0, sB0);
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    __syncthreads();
+    if (kp + 1 < npair) issue(sA0, sB0);
+    compute(sA1, sB1);
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int bi = 0; bi < MBLK; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < NBLK; ++bj)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const long long row = m0 + wr * WM + bi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const long long col = n0 + wc * WN + bj * 32 + (lane & 31);
+        if (col < p.Nr) C[row * p.Nr + col] = acc[bi][bj][r];
+      }
+}
+
 // ---------------------------------------------------------------- rescale
 // Per node: largest binary exponent of any component (as exponent + 4096,
 // so that unsigned atomicMax orders it), 0 when the node is all zeros.
@@ -1369,8 +1539,9 @@ int fp32_3m_config_count() { return (int)(sizeof(kFp32_3mConfigs) / sizeof(kFp32
 // FP64 candidates: 0 = direct-to-LDS 128 x 64, 1 = direct-to-LDS 64 x 64,
 // 2 = row-major 128 x 64 x 16 (LDS through registers)
 int fp64_config_count() { return 3; }
-// BF16x3 candidates: 0 = 256 x 256 tiles, 1 = 128 x 256
-int bf16x3_config_count() { return 2; }
+// BF16x3 candidates: 0 = 256 x 256 tiles, 1 = 128 x 256, 2 = the direct-to-LDS
+// kernel with 256 x 256 tiles and two waves per SIMD
+int bf16x3_config_count() { return 3; }
 int config_count(int prec) {
   switch (prec) {
     case PSIM_FP32_4M: return fp32_config_count();
@@ -1635,7 +1806,14 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
       const long long bl = (b.T + 7) / 8 * 8;
       if (bl > 0x7fffffffLL) fail(PSIM_EUNSUPPORTED, "grid too large");
       const bool f = g.M % bm == 0 && (2 * g.K1 * g.K2) % 16 == 0 && (2 * g.K2) % 16 == 0;
-      if (big && f)
+      // candidate 2: the direct-to-LDS form (32-real stages inside one k1
+      // block, an even number of them, 32-bit copy offsets); other shapes
+      // take candidate 0's kernel, which gives the same results
+      const bool dtl = g.cfg == 2 && g.M % 256 == 0 && (2 * g.K2) % 32 == 0 && (2 * g.K1 * g.K2) % 64 == 0 &&
+                       g.K2 < (1 << 20) && g.ldwb < (1 << 22);
+      if (dtl)
+        hipLaunchKernelGGL((site_gemm_bf16x3_dtl<256, 256>), dim3((unsigned)bl), dim3(512), 0, st, b);
+      else if (big && f)
         hipLaunchKernelGGL((site_gemm_bf16x3<256, 256, true>), dim3((unsigned)bl), dim3(256), 0, st, b);
       else if (big)
         hipLaunchKernelGGL((site_gemm_bf16x3<256, 256, false>), dim3((unsigned)bl), dim3(256), 0, st, b);
@@ -1668,7 +1846,7 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
       // interior tiles, an even number of K stages, 32-bit copy offsets:
       // the direct-to-LDS kernel (same products in the same order as the
       // ROWFAST 3M kernel, so the same results bit for bit)
-      if (g.split && g.cfg == 3 && dtl3m_ok(g, mode, 64)) {
+      if (g.split && g.cfg == 3) {
         // split accumulation with 64 x 128 tiles: half the accumulators per
         // wave, three workgroups per CU instead of two
         KArgs f = b;

@@ -556,6 +556,9 @@ struct SqRun {
     GemmLaunch g;
     g.prec = prec;
     g.split = split;
+    // split 3M joins: the 64 x 128 split tile (no spills, three workgroups
+    // per CU; the 128 x 128 one is taken where M is not a multiple of 64)
+    g.cfg = (split && prec == PSIM_FP32_3M) ? 3 : 0;
     g.A = A;
     g.C = C;
     g.W0 = g.W1 = P;
@@ -613,6 +616,9 @@ struct SqRun {
     GemmLaunch g;
     g.prec = prec;
     g.split = split;
+    // split 3M joins: the 64 x 128 split tile (no spills, three workgroups
+    // per CU; the 128 x 128 one is taken where M is not a multiple of 64)
+    g.cfg = (split && prec == PSIM_FP32_3M) ? 3 : 0;
     g.A = A;
     g.C = C;
     g.W0 = g.W1 = P;

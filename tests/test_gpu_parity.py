@@ -112,6 +112,36 @@ def test_site_contraction_parity(ps, prec, M, K1, K2, N, batch, trans):
     assert np.max(np.abs(C - ref)) <= tol * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("prec,cfg", [("fp32", c) for c in range(1, 7)] + [("fp32_3m", c) for c in range(1, 4)] +
+                         [("fp64", c) for c in range(1, 3)] + [("bf16x3", c) for c in range(1, 3)])
+@pytest.mark.parametrize("M,K1,K2,N,batch", [
+    (512, 4, 16, 200, 2),    # interior tiles along m, an even number of 32-real stages, ragged N
+    (384, 2, 32, 100, 3),    # 3 batch entries, K = 64
+    (300, 3, 8, 50, 2),      # ragged M: shapes the direct-to-LDS kernels leave to the others
+])
+def test_site_contraction_tile_candidates(ps, prec, cfg, M, K1, K2, N, batch):
+    """Every tile candidate of a precision, one site contraction (eq. S4):
+    bit for bit the default candidate's output (same products in the same k
+    order), and within the precision's bound of the oracle."""
+    import torch
+    say(f"site {prec} tile {cfg} M={M} K1={K1} K2={K2} N={N} batch={batch}")
+    rng = np.random.default_rng(M + 13 * N + cfg)
+    A = (rng.standard_normal((batch, K1 * M * K2)) + 1j * rng.standard_normal((batch, K1 * M * K2)))
+    W = rng.standard_normal((K1 * K2, N)) + 1j * rng.standard_normal((K1 * K2, N))
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    if prec != "fp64":
+        A = A.astype(np.complex64).astype(np.complex128)
+        W = W.astype(np.complex64).astype(np.complex128)
+    Ad = torch.from_numpy(A.reshape(-1)).to(dt).cuda()
+    C0 = ps.contract_site(prec, Ad, W, M, K1, K2, N, batch=batch).cpu().numpy()
+    C = ps.contract_site(prec, Ad, W, M, K1, K2, N, batch=batch, tile_cfg=cfg).cpu().numpy()
+    assert np.array_equal(C, C0)
+    ref = _oracle_step(A, W, M, K1, K2, N)
+    tol = {"fp64": 1e-12, "fp32": 2e-6 * np.log2(2 * K1 * K2), "fp32_3m": 4e-6 * np.log2(2 * K1 * K2),
+           "bf16x3": 2e-4}[prec]
+    assert np.max(np.abs(C.reshape(ref.shape) - ref)) <= tol * np.max(np.abs(ref))
+
+
 def test_site_contraction_full_size_sampled(ps):
     """Hot step at the 6x6 (1+40+1) shape: M = 32^4, K = N = 32^2, sampled outputs."""
     import torch
@@ -312,7 +342,7 @@ def test_8x8_d25_vs_oracle_and_normalisation(ps):
 
 
 @pytest.mark.parametrize("prec,cfg", [("fp32", c) for c in range(1, 7)] + [("fp32_3m", c) for c in range(1, 4)] +
-                         [("fp64", c) for c in range(1, 3)] + [("bf16x3", 1)])
+                         [("fp64", c) for c in range(1, 3)] + [("bf16x3", c) for c in range(1, 3)])
 def test_tile_candidates(ps, prec, cfg):
     """Every tile candidate the autotuner may pick gives the oracle's amplitudes
     (5x5 (1+32+1), 256 bitstrings; the precision's bar) and, since every
