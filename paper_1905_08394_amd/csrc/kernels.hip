@@ -1766,7 +1766,17 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
       return mode == ROWMAJOR && g.M % bm == 0 && (2 * g.K1 * g.K2) % bk == 0 && (2 * g.K2) % bk == 0;
     };
     if (g.split && g.prec == PSIM_FP32_4M) {
-      if (fast(128, 32))
+      if (g.trans_out && g.N <= 32 && fast(128, 32)) {
+        // last sites of a row (N <= 32 complex): tiles 64 reals wide, so
+        // none of a 128-wide tile's columns are padding; the same products
+        // in the same k order as the 128 x 128 tiles
+        KArgs f = b;
+        f.NT = (f.Nr + 63) / 64;
+        f.T = f.MT * f.NT * Z;
+        const long long fb = (f.T + 7) / 8 * 8;
+        if (fb > 0x7fffffffLL) fail(PSIM_EUNSUPPORTED, "grid too large");
+        launch<float, 128, 64, 32, ROWFAST, true, 4, true>(f, fb, st);
+      } else if (fast(128, 32))
         g.trans_out ? launch<float, 128, 128, 32, ROWFAST, true, 4, true>(b, blocks, st)
                     : launch<float, 128, 128, 32, ROWFAST, false, 4, true>(b, blocks, st);
       else if (mode == ROWMAJOR)

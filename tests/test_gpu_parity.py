@@ -77,8 +77,7 @@ def _oracle_step(A, W, M, K1, K2, N):
     return np.stack(out)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_3m", "bf16x3"])
-@pytest.mark.parametrize("M,K1,K2,N,batch,trans", [
+SITE_SHAPES = [
     (300, 3, 8, 50, 2, False),     # row-major A, ragged M and N
     (260, 16, 1, 64, 1, False),    # K-major A (first site of a row)
     (77, 5, 3, 33, 2, False),      # odd K2: generic loader, odd M
@@ -90,10 +89,19 @@ def _oracle_step(A, W, M, K1, K2, N):
     (1000, 2, 32, 32, 1, True),    # last site of a 6x6 row: v chunk 2, N = 32
     (256, 4, 16, 48, 2, False),    # interior tiles only: the bounds-check-free loader
     (384, 2, 32, 100, 3, False),   # direct-to-LDS kernels: 3 row tiles, 3 batch entries, ragged N
-])
+    (1024, 8, 32, 32, 2, True),    # last site with the split kernels' 64-real-wide tiles (N = 32, 16 stages)
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_3m", "bf16x3", "fp32s", "fp32_3ms"])
+@pytest.mark.parametrize("M,K1,K2,N,batch,trans", SITE_SHAPES)
 def test_site_contraction_parity(ps, prec, M, K1, K2, N, batch, trans):
+    """One site contraction (eq. S4) against the oracle's, in every
+    precision; fp32s / fp32_3ms are the split-accumulation kernels."""
     import torch
     say(f"site {prec} M={M} K1={K1} K2={K2} N={N} batch={batch} trans={trans}")
+    split = prec in ("fp32s", "fp32_3ms")
+    prec = prec[:-1] if split else prec
     rng = np.random.default_rng(M * 7 + K1 + N)
     A = (rng.standard_normal((batch, K1 * M * K2)) + 1j * rng.standard_normal((batch, K1 * M * K2)))
     W = rng.standard_normal((K1 * K2, N)) + 1j * rng.standard_normal((K1 * K2, N))
@@ -102,7 +110,7 @@ def test_site_contraction_parity(ps, prec, M, K1, K2, N, batch, trans):
         A = A.astype(np.complex64).astype(np.complex128)
         W = W.astype(np.complex64).astype(np.complex128)
     Ad = torch.from_numpy(A.reshape(-1)).to(dt).cuda()
-    C = ps.contract_site(prec, Ad, W, M, K1, K2, N, batch=batch, transpose_out=trans).cpu().numpy()
+    C = ps.contract_site(prec, Ad, W, M, K1, K2, N, batch=batch, transpose_out=trans, split_acc=split).cpu().numpy()
     ref = _oracle_step(A, W, M, K1, K2, N)
     if trans:
         ref = ref.transpose(0, 2, 1)

@@ -135,6 +135,24 @@ def test_tile_cfg_validation(ps):
     assert ps.Plan(P, prec="fp32_3m", host_only=True, tile_cfg=3, split_acc=True).stats()["hot_cfg"] in (0, 3)
 
 
+def test_contract_site_refuses_missing_kernels(ps):
+    """psim_contract_site's tile and split bits name the kernels a plan would
+    run; choices a precision lacks are refused with EINVAL before any device
+    work (so this runs without a GPU, on placeholder pointers): tiles past
+    the precision's last candidate, split accumulation for FP64 and BF16x3,
+    split with a tile other than 0 or (FP32 3M) 3."""
+    L = ps.lib()
+    W = (ctypes.c_double * 32)()
+    split, shift = 0x100, 16
+    bad = [("fp32", 7 << shift), ("fp32_3m", 4 << shift), ("fp64", 3 << shift), ("bf16x3", 3 << shift),
+           ("fp64", split), ("bf16x3", split), ("fp32", split | (1 << shift)), ("fp32_3m", split | (2 << shift))]
+    for prec, bits in bad:
+        st = L.psim_contract_site(ps.PREC[prec] | bits, 1, 8, 2, 2, 4, ctypes.c_void_p(16), 32, W,
+                                  ctypes.c_void_p(16), 0, None)
+        assert st == ps.PSIM_EINVAL, (prec, hex(bits))
+        assert b"not available" in L.psim_last_error()
+
+
 def test_group_rejects_host_only_and_empty(ps):
     P = ps.Peps(rqcgen.generate(3, 3, 8, 0))
     pl = ps.Plan(P, prec="fp32", host_only=True)
