@@ -278,10 +278,11 @@ psim_status psim_amplitudes_static(psim_plan_t *plan, const uint8_t *bits, size_
  *    stores C[z][n][m] instead.  batch = number of z.
  * prec: a psim_precision, optionally OR'ed with PSIM_CONTRACT_SPLIT_ACC and
  * (k << PSIM_CONTRACT_TILE_SHIFT) to pick the kernels a plan with
- * PSIM_PLAN_SPLIT_ACC or tile_cfg = k would run (plain stores only).
+ * PSIM_PLAN_SPLIT_ACC or tile_cfg = k would run (the tile candidate applies
+ * to plain stores; transposed stores take the precision's one kernel).
  * Runs the same kernels the amplitude path uses; allocates its own scratch.
- * Errors: EINVAL for non-positive sizes, NULL, or a tile / split choice the
- * precision lacks; EUNSUPPORTED, EDEVICE. */
+ * Errors: EINVAL for non-positive sizes, NULL, a tile / split choice the
+ * precision lacks or any other bit set in prec; EUNSUPPORTED, EDEVICE. */
 psim_status psim_contract_site(int32_t prec, int64_t batch, int64_t M, int64_t K1, int64_t K2, int64_t N,
                                const void *d_A, int64_t a_batch_stride, const double *W,
                                void *d_C, int32_t transpose_out, void *hip_stream);

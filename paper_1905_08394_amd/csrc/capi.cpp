@@ -183,6 +183,8 @@ psim_status psim_contract_site(int32_t prec, int64_t batch, int64_t M, int64_t K
                                int32_t transpose_out, void* stream) {
   return guarded([&] {
     // optional bits above the precision: split accumulation and a tile candidate
+    if (prec & ~(0xff | PSIM_CONTRACT_SPLIT_ACC | (0xff << PSIM_CONTRACT_TILE_SHIFT)))
+      fail(PSIM_EINVAL, "unknown bits in the precision argument");
     const int split = (prec & PSIM_CONTRACT_SPLIT_ACC) ? 1 : 0;
     const int cfg = (prec >> PSIM_CONTRACT_TILE_SHIFT) & 0xff;
     prec &= 0xff;

@@ -151,6 +151,10 @@ def test_contract_site_refuses_missing_kernels(ps):
                                   ctypes.c_void_p(16), 0, None)
         assert st == ps.PSIM_EINVAL, (prec, hex(bits))
         assert b"not available" in L.psim_last_error()
+    for bits in (0x200, 1 << 24, 1 << 31):   # bits that name nothing
+        st = L.psim_contract_site(ctypes.c_int32(ps.PREC["fp32"] | bits).value, 1, 8, 2, 2, 4,
+                                  ctypes.c_void_p(16), 32, W, ctypes.c_void_p(16), 0, None)
+        assert st == ps.PSIM_EINVAL and b"unknown bits" in L.psim_last_error()
 
 
 def test_group_rejects_host_only_and_empty(ps):
