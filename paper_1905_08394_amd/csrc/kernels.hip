@@ -1796,9 +1796,17 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
       else if (mode == ROWMAJOR)
         g.trans_out ? launch<float, 128, 128, 32, ROWMAJOR, true, 3, true>(b, blocks, st)
                     : launch<float, 128, 128, 32, ROWMAJOR, false, 3, true>(b, blocks, st);
-      else if (mode == KMAJOR)
-        g.trans_out ? launch<float, 128, 128, 32, KMAJOR, true, 3, true>(b, blocks, st)
-                    : launch<float, 128, 128, 32, KMAJOR, false, 3, true>(b, blocks, st);
+      else if (mode == KMAJOR && !g.trans_out) {
+        // first sites of a row: 64-row tiles, half the accumulators of a
+        // wave, so more workgroups share a CU (same products, same order)
+        KArgs f = b;
+        f.MT = (f.M + 63) / 64;
+        f.T = f.MT * f.NT * Z;
+        const long long fb = (f.T + 7) / 8 * 8;
+        if (fb > 0x7fffffffLL) fail(PSIM_EUNSUPPORTED, "grid too large");
+        launch<float, 64, 128, 32, KMAJOR, false, 3, true>(f, fb, st);
+      } else if (mode == KMAJOR)
+        launch<float, 128, 128, 32, KMAJOR, true, 3, true>(b, blocks, st);
       else
         g.trans_out ? launch<float, 128, 128, 32, GENERIC, true, 3, true>(b, blocks, st)
                     : launch<float, 128, 128, 32, GENERIC, false, 3, true>(b, blocks, st);
