@@ -1121,15 +1121,18 @@ __global__ __launch_bounds__(256) void site_gemm_bf16x3(KArgs p) {
 }
 
 // Direct-to-LDS form of the BF16x3 kernel for interior launches (every tile
-// interior, every 32-real stage inside one k1 block, an even number of
+// interior, every 16-real stage inside one k1 block, a multiple of four
 // stages).  A is copied global -> LDS in FP32 by the load unit and split into
 // hi / lo as its fragments are read; W's two pre-split planes are copied side
-// by side into one 128-byte LDS row per output column (hi k 0..31, then lo
-// k 0..31).  Both tiles are unpadded 128-byte rows with the chunk swizzle of
-// the 3M direct-to-LDS kernel.  512 threads: 8 waves as 4 (m) x 2 (n) blocks
-// of 64 x 128 outputs, 128 accumulator registers each, so two waves share a
-// SIMD.  The split, the products and their order for each output element are
-// those of site_gemm_bf16x3, so the two agree bit for bit.
+// by side into one 64-byte LDS row per output column (hi k 0..15, then lo
+// k 0..15).  Rows are unpadded, their four 16-byte chunks permuted by
+// (row >> 2) & 3 so the fragment reads of 16 consecutive rows hit distinct
+// banks.  Four LDS buffers form a ring: the copies of a stage are issued
+// three stages before its products, so about 2 us of matrix work covers the
+// latency of a copy that misses L2.  512 threads: 8 waves as 4 (m) x 2 (n)
+// blocks of 64 x 128 outputs, 128 accumulator registers each, two waves per
+// SIMD.  The split, the products and their order for each output element
+// are those of site_gemm_bf16x3, so the two agree bit for bit.
 // x = hi + lo for 8 floats (x0 then x1) with hi = bf16(x) and lo =
 // bf16(x - hi), both rounded to nearest even, as the operand registers of a
 // 32x32x16 MFMA hold them.  Each pair is rounded in one packed conversion and
@@ -1153,20 +1156,25 @@ __device__ __forceinline__ void split_bf16x8(const f32x4 x0, const f32x4 x1, bf1
   }
 }
 
+__device__ __forceinline__ int ring_swz(int r) { return (r >> 2) & 3; }
+
 template <int BM, int BN>
 __global__ __launch_bounds__(512) void site_gemm_bf16x3_dtl(KArgs p) {
-  constexpr int BK = 32;                 // reals per stage: two MFMA k-steps
+  constexpr int BK = 16;                 // reals per stage: one MFMA k-step
   constexpr int NW = 8;                  // waves per workgroup
   constexpr int WM = BM / 4, WN = BN / 2;
   constexpr int MBLK = WM / 32, NBLK = WN / 32;
-  constexpr int A_INS = BM * 128 / 1024 / NW;  // wave-wide 1 KiB copies per wave and stage
-  constexpr int B_INS = BN * 128 / 1024 / NW;
-  static_assert(A_INS >= 1 && B_INS >= 1 && A_INS * NW * 1024 == BM * 128 && B_INS * NW * 1024 == BN * 128,
-                "tile");
+  constexpr int A_INS = BM * 64 / 1024 / NW;  // wave-wide 1 KiB copies per wave and stage
+  constexpr int B_INS = BN * 64 / 1024 / NW;
+  static_assert(A_INS >= 1 && B_INS >= 1 && A_INS * NW * 1024 == BM * 64 && B_INS * NW * 1024 == BN * 64, "tile");
   __shared__ __attribute__((aligned(1024))) float sA0[BM * BK];
   __shared__ __attribute__((aligned(1024))) float sA1[BM * BK];
+  __shared__ __attribute__((aligned(1024))) float sA2[BM * BK];
+  __shared__ __attribute__((aligned(1024))) float sA3[BM * BK];
   __shared__ __attribute__((aligned(1024))) __bf16 sB0[BN * 2 * BK];
   __shared__ __attribute__((aligned(1024))) __bf16 sB1[BN * 2 * BK];
+  __shared__ __attribute__((aligned(1024))) __bf16 sB2[BN * 2 * BK];
+  __shared__ __attribute__((aligned(1024))) __bf16 sB3[BN * 2 * BK];
 
   const long long t = xcd_tile(p.T);
   if (t >= p.T) return;
@@ -1188,9 +1196,9 @@ __global__ __launch_bounds__(512) void site_gemm_bf16x3_dtl(KArgs p) {
   const int wr = wid >> 1, wc = wid & 1;
   const long long sK1 = p.M * p.K2;
 
-  // Copy `it` of this wave fills tile rows (it * NW + wid) * 8 + lane / 8,
-  // physical chunk lane % 8, from logical chunk (lane % 8) ^ swz(row); for W
-  // logical chunks 0-3 are the hi plane's k 0..31 and 4-7 the lo plane's.
+  // Copy `it` of this wave fills tile rows (it * NW + wid) * 16 + lane / 4,
+  // physical chunk lane % 4, from logical chunk (lane % 4) ^ swz(row); for W
+  // logical chunks 0-1 are the hi plane's k 0..15 and 2-3 the lo plane's.
   // Byte offsets from the uniform stage bases stay below 2^31.
   const unsigned a_rs = (unsigned)(2 * p.K2 * 4);  // bytes between rows of A
   const unsigned b_rs = (unsigned)(p.ldw * 2);     // bytes between rows of a W plane
@@ -1201,16 +1209,16 @@ __global__ __launch_bounds__(512) void site_gemm_bf16x3_dtl(KArgs p) {
     const char* lbase = (const char*)(Wl + n0 * p.ldw + kr);
 #pragma unroll
     for (int it = 0; it < A_INS; ++it) {
-      const int row = (it * NW + wid) * 8 + (lane >> 3);
-      const int chk = (lane & 7) ^ dtl_swz(row);
+      const int row = (it * NW + wid) * 16 + (lane >> 2);
+      const int chk = (lane & 3) ^ ring_swz(row);
       __builtin_amdgcn_global_load_lds((const void*)(abase + (unsigned)row * a_rs + (unsigned)chk * 16u),
                                        PSIM_LDS(sa + (it * NW + wid) * 256), 16, 0, 0);
     }
 #pragma unroll
     for (int it = 0; it < B_INS; ++it) {
-      const int row = (it * NW + wid) * 8 + (lane >> 3);
-      const int chk = (lane & 7) ^ dtl_swz(row);
-      const char* src = ((chk & 4) ? lbase : hbase) + (unsigned)row * b_rs + (unsigned)(chk & 3) * 16u;
+      const int row = (it * NW + wid) * 16 + (lane >> 2);
+      const int chk = (lane & 3) ^ ring_swz(row);
+      const char* src = ((chk & 2) ? lbase : hbase) + (unsigned)row * b_rs + (unsigned)(chk & 1) * 16u;
       __builtin_amdgcn_global_load_lds((const void*)src, PSIM_LDS(sb + (it * NW + wid) * 512), 16, 0, 0);
     }
     fk2 += BK / 2;
@@ -1229,53 +1237,67 @@ __global__ __launch_bounds__(512) void site_gemm_bf16x3_dtl(KArgs p) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[bi][bj][r] = 0;
 
-  const int frow = lane & 31, h = lane >> 5;  // lane half h supplies k 8h .. 8h+7 of a k-step
+  const int frow = lane & 31, h = lane >> 5;  // lane half h supplies k 8h .. 8h+7 of the k-step
   auto compute = [&](const float* a_s, const __bf16* b_s) {
+    bf16x8 ah[MBLK], al[MBLK], bh[NBLK], bl[NBLK];
 #pragma unroll
-    for (int j = 0; j < BK / 16; ++j) {
-      bf16x8 ah[MBLK], al[MBLK], bh[NBLK], bl[NBLK];
+    for (int bi = 0; bi < MBLK; ++bi) {
+      const int r = wr * WM + bi * 32 + frow;
+      const int sw = ring_swz(r);
+      const f32x4 x0 = *(const f32x4*)(a_s + r * BK + (((2 * h) ^ sw) << 2));
+      const f32x4 x1 = *(const f32x4*)(a_s + r * BK + (((2 * h + 1) ^ sw) << 2));
+      split_bf16x8(x0, x1, ah[bi], al[bi]);
+    }
 #pragma unroll
-      for (int bi = 0; bi < MBLK; ++bi) {
-        const int r = wr * WM + bi * 32 + frow;
-        const int c0 = 4 * j + 2 * h, sw = dtl_swz(r);
-        const f32x4 x0 = *(const f32x4*)(a_s + r * BK + ((c0 ^ sw) << 2));
-        const f32x4 x1 = *(const f32x4*)(a_s + r * BK + (((c0 + 1) ^ sw) << 2));
-        split_bf16x8(x0, x1, ah[bi], al[bi]);
-      }
+    for (int bj = 0; bj < NBLK; ++bj) {
+      const int r = wc * WN + bj * 32 + frow;
+      const int sw = ring_swz(r);
+      bh[bj] = *(const bf16x8*)(b_s + r * 2 * BK + ((h ^ sw) << 3));
+      bl[bj] = *(const bf16x8*)(b_s + r * 2 * BK + (((2 + h) ^ sw) << 3));
+    }
+#pragma unroll
+    for (int bi = 0; bi < MBLK; ++bi)
 #pragma unroll
       for (int bj = 0; bj < NBLK; ++bj) {
-        const int r = wc * WN + bj * 32 + frow;
-        const int sw = dtl_swz(r);
-        bh[bj] = *(const bf16x8*)(b_s + r * 2 * BK + (((2 * j + h) ^ sw) << 3));
-        bl[bj] = *(const bf16x8*)(b_s + r * 2 * BK + (((4 + 2 * j + h) ^ sw) << 3));
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[bi], bh[bj], acc[bi][bj], 0, 0, 0);
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bl[bj], acc[bi][bj], 0, 0, 0);
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bh[bj], acc[bi][bj], 0, 0, 0);
       }
-#pragma unroll
-      for (int bi = 0; bi < MBLK; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < NBLK; ++bj) {
-          acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[bi], bh[bj], acc[bi][bj], 0, 0, 0);
-          acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bl[bj], acc[bi][bj], 0, 0, 0);
-          acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bh[bj], acc[bi][bj], 0, 0, 0);
-        }
-    }
   };
-  constexpr unsigned kWaitVm0 = 0x3f70;  // vmcnt(0): this wave's copies into LDS have landed
+  // vmcnt(n), other counters unconstrained: all but this wave's n most recent
+  // copies into LDS have landed (A_INS + B_INS copies per stage)
+  constexpr int PER = A_INS + B_INS;
+  static_assert(2 * PER <= 15, "vmcnt field");
+  constexpr unsigned kWaitVm0 = 0x3f70, kWaitVm1 = 0x3f70 | PER, kWaitVm2 = 0x3f70 | (2 * PER);
 
-  // the launcher guarantees an even number of stages
-  const int npair = (int)(p.Kr / (2 * BK));
-  issue(sA0, sB0);
-  __builtin_amdgcn_s_waitcnt(kWaitVm0);
-  __syncthreads();
-  for (int kp = 0; kp < npair; ++kp) {
-    issue(sA1, sB1);
-    compute(sA0, sB0);
-    __builtin_amdgcn_s_waitcnt(kWaitVm0);
-    __syncthreads();
-    if (kp + 1 < npair) issue(sA0, sB0);
-    compute(sA1, sB1);
-    __builtin_amdgcn_s_waitcnt(kWaitVm0);
-    __syncthreads();
+  // one stage: wait for its copies (the copies of up to two later stages
+  // may still be in flight), barrier (every wave's copies have landed and
+  // every wave is done with the buffer the next issue overwrites), issue the
+  // copies of stage s + 3 into that buffer, then the stage's products
+  const int nst = (int)(p.Kr / BK);  // the launcher guarantees a multiple of 4
+#define PSIM_BF16X3_RING(S, SA, SB, NA, NB)                     \
+  {                                                             \
+    const int s_ = (S);                                         \
+    if (s_ + 2 < nst)                                           \
+      __builtin_amdgcn_s_waitcnt(kWaitVm2);                     \
+    else if (s_ + 1 < nst)                                      \
+      __builtin_amdgcn_s_waitcnt(kWaitVm1);                     \
+    else                                                        \
+      __builtin_amdgcn_s_waitcnt(kWaitVm0);                     \
+    __syncthreads();                                            \
+    if (s_ + 3 < nst) issue(NA, NB);                            \
+    compute(SA, SB);                                            \
   }
+  issue(sA0, sB0);
+  issue(sA1, sB1);
+  issue(sA2, sB2);
+  for (int s0 = 0; s0 < nst; s0 += 4) {
+    PSIM_BF16X3_RING(s0, sA0, sB0, sA3, sB3)
+    PSIM_BF16X3_RING(s0 + 1, sA1, sB1, sA0, sB0)
+    PSIM_BF16X3_RING(s0 + 2, sA2, sB2, sA1, sB1)
+    PSIM_BF16X3_RING(s0 + 3, sA3, sB3, sA2, sB2)
+  }
+#undef PSIM_BF16X3_RING
 
 #pragma unroll
   for (int bi = 0; bi < MBLK; ++bi)
@@ -1824,10 +1846,10 @@ void launch_site_gemm(const GemmLaunch& g, void* stream) {
       const long long bl = (b.T + 7) / 8 * 8;
       if (bl > 0x7fffffffLL) fail(PSIM_EUNSUPPORTED, "grid too large");
       const bool f = g.M % bm == 0 && (2 * g.K1 * g.K2) % 16 == 0 && (2 * g.K2) % 16 == 0;
-      // candidate 2: the direct-to-LDS form (32-real stages inside one k1
-      // block, an even number of them, 32-bit copy offsets); other shapes
-      // take candidate 0's kernel, which gives the same results
-      const bool dtl = g.cfg == 2 && g.M % 256 == 0 && (2 * g.K2) % 32 == 0 && (2 * g.K1 * g.K2) % 64 == 0 &&
+      // candidate 2: the direct-to-LDS form (16-real stages inside one k1
+      // block, a multiple of four of them, 32-bit copy offsets); other
+      // shapes take candidate 0's kernel, which gives the same results
+      const bool dtl = g.cfg == 2 && g.M % 256 == 0 && (2 * g.K2) % 16 == 0 && (2 * g.K1 * g.K2) % 64 == 0 &&
                        g.K2 < (1 << 20) && g.ldwb < (1 << 22);
       if (dtl)
         hipLaunchKernelGGL((site_gemm_bf16x3_dtl<256, 256>), dim3((unsigned)bl), dim3(512), 0, st, b);
