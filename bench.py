@@ -792,7 +792,7 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1).",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1).",
               file=sys.stderr)
         sys.exit(2)
     if args.mem_gib == 0:

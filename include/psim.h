@@ -44,7 +44,7 @@ typedef enum {
   PSIM_EINVAL = -1,        /* bad argument: qubit out of range, non-neighbouring 2q gate, bit not 0/1, NULL */
   PSIM_ENOMEM = -2,        /* plan exceeds the memory budget (message states the bytes needed) or allocation failed */
   PSIM_EDEVICE = -3,       /* HIP runtime error (message carries the HIP error string) */
-  PSIM_EUNSUPPORTED = -4,  /* valid request this build does not implement */
+  PSIM_EUNSUPPORTED = -4,  /* valid request this library does not implement */
   PSIM_EINTERNAL = -5
 } psim_status;
 

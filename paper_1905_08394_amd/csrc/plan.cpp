@@ -181,7 +181,7 @@ psim_plan_t* make_plan(const psim_peps_t* P, const psim_plan_opts* o) {
   psim_plan_opts opts{};
   if (o) opts = *o;
   if (opts.prec != PSIM_FP64 && opts.prec != PSIM_FP32_4M && opts.prec != PSIM_FP32_3M && opts.prec != PSIM_BF16X3)
-    fail(PSIM_EUNSUPPORTED, "precision " + std::to_string(opts.prec) + " is not available in this build");
+    fail(PSIM_EUNSUPPORTED, "precision " + std::to_string(opts.prec) + " is not available in this library");
   if (opts.mem_budget_bytes == 0) opts.mem_budget_bytes = 200ull << 30;
   if (opts.max_batch <= 0) opts.max_batch = 1;
   if (opts.tile_cfg < 0 || opts.tile_cfg >= config_count(opts.prec))

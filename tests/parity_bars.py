@@ -1,4 +1,4 @@
-"""Parity bars of the GPU amplitude tests, stated before the runs they judge.
+"""Parity bars of the GPU amplitude tests, stated before the runs they apply to.
 
 For an amplitude a on N qubits against the FP64 oracle value r, with
 x = 2^N |r|^2 (the scaled probability; Porter-Thomas: x ~ Exp(1)):
