@@ -463,6 +463,7 @@ struct SqRun {
         GemmLaunch g;
         g.prec = prec;
         g.split = split;
+        g.cfg = (split && prec == PSIM_FP32_3M) ? 3 : 0;  // the 64 x 128 split tile, as for the joins
         g.A = (i == 0 && j == 0) ? pl->d_ones : (const void*)cur;
         g.C = nxt;
         g.W0 = g.W1 = w.ptr;
@@ -519,6 +520,7 @@ struct SqRun {
         GemmLaunch g;
         g.prec = prec;
         g.split = split;
+        g.cfg = (split && prec == PSIM_FP32_3M) ? 3 : 0;  // the 64 x 128 split tile, as for the joins
         g.A = first ? pl->d_ones : (const void*)cur;
         g.C = nxt;
         g.W0 = st_.w[0].ptr;
