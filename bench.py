@@ -306,8 +306,10 @@ def plain_fp64_gpu_baseline(stats, batch_cmac, nbits, reps=3):
 def counters_program(prec="fp32_3m", reps=3, split_acc=False, tile_cfg=0):
     """Short program for rocprofv3 --pmc passes: a plain 4 GiB device copy (to
     calibrate FETCH_SIZE / WRITE_SIZE) and the interior-site contraction at the
-    launch shape the 6x6 (1+40+1) bench runs (two v values of M = 32^4,
-    K = N = 32^2 complex64)."""
+    launch shape of the 6x6 (1+40+1) bench's interior sites before its rows
+    were cut over w as well (two v values of M = 32^4, K = N = 32^2;
+    complex64, complex128 for FP64), four times the work of one of its
+    interior launches now."""
     import numpy as np
     import torch
     import paper_1905_08394_amd as ps
@@ -318,7 +320,9 @@ def counters_program(prec="fp32_3m", reps=3, split_acc=False, tile_cfg=0):
         dst.copy_(src)
     torch.cuda.synchronize()
     M, K1, K2, N, batch = 32 ** 4, 32, 32, 1024, 2
-    A = torch.randn(batch * K1 * M * K2, dtype=torch.complex64, device="cuda")
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    eb = 16 if prec == "fp64" else 8
+    A = torch.randn(batch * K1 * M * K2, dtype=dt, device="cuda")
     rng = np.random.default_rng(0)
     W = rng.standard_normal((K1 * K2, N)) + 1j * rng.standard_normal((K1 * K2, N))
     for r in range(reps):
@@ -326,7 +330,7 @@ def counters_program(prec="fp32_3m", reps=3, split_acc=False, tile_cfg=0):
         log(f"hot step {r + 1}/{reps}")
     torch.cuda.synchronize()
     print(json.dumps({"prec": prec, "copy_bytes": 4 * n, "hot_step_algorithmic_bytes":
-                      2 * batch * K1 * M * K2 * 8 + K1 * K2 * N * 4 * 4, "reps": reps}), flush=True)
+                      2 * batch * K1 * M * K2 * eb + K1 * K2 * N * eb // 2 * 4, "reps": reps}), flush=True)
 
 
 def seven_program(args):
