@@ -47,12 +47,14 @@ def _golden(name):
     (4, 5, 24, "fp32_3m", 0, "rqc_4x5_d24_s0.json"),
     (3, 3, 8, "fp64", 0, "rqc_3x3_d8_s0.json"),
     (3, 3, 8, "fp32", 3, "rqc_3x3_d8_s0.json"),
+    (4, 5, 24, "fp32_3ms", 0, "rqc_4x5_d24_s0.json"),   # split accumulation
 ])
 def test_static_matches_workspace_entry(ps, lv, lh, d, prec, sweep, golden):
     bits, ref = _golden(golden)
     c = rqcgen.generate(lv, lh, d, 0)
     P = ps.Peps(c)
-    plan = ps.Plan(P, prec=prec, max_batch=len(bits), sweep=sweep)
+    split = prec == "fp32_3ms"
+    plan = ps.Plan(P, prec="fp32_3m" if split else prec, max_batch=len(bits), sweep=sweep, split_acc=split)
     assert plan.stats()["workspace_bytes"] <= 64 << 20
     n = lv * lh
     for sel in (slice(None), slice(3, 3 + max(1, len(bits) // 4))):   # second call smaller
