@@ -71,6 +71,16 @@ int main(void) {
   CHECK(st == PSIM_EINVAL && p2 == NULL && strstr(psim_last_error(), "neighbour"), "bad gate: %d %s", (int)st,
         psim_last_error());
 
+  /* psim_contract_site: a tile or split choice the precision lacks, or a
+     bit that names nothing, is refused before any device work */
+  double w[32] = {0};
+  int32_t bad_prec[3] = {PSIM_FP64 | PSIM_CONTRACT_SPLIT_ACC, PSIM_FP32_3M | (4 << PSIM_CONTRACT_TILE_SHIFT),
+                         PSIM_FP32_4M | 0x200};
+  for (int i = 0; i < 3; ++i) {
+    st = psim_contract_site(bad_prec[i], 1, 8, 2, 2, 4, (const void *)w, 32, w, (void *)w, 0, NULL);
+    CHECK(st == PSIM_EINVAL, "contract_site choice %d: %d", i, (int)st);
+  }
+
   psim_plan_free(plan);
   psim_peps_free(peps);
   psim_plan_free(NULL);
